@@ -1,0 +1,176 @@
+/*
+ * kcpc.h - C ABI of an MI355X (gfx950) solver for the kernel-compensated Yee-scheme
+ * Maxwell eigenproblem of 3D photonic crystals with anisotropic permittivity
+ * (Jin & Xie, "A Robust GPU-Accelerated Kernel Compensation Solver with Novel
+ * Discretization for Photonic Crystals in Anisotropic Media").
+ *
+ * Problem.  For a simple-cubic unit cell with grid division N (h = 1/N), a piecewise
+ * constant Hermitian inverse permittivity and a Bloch wave vector k, find the m smallest
+ * strictly positive eigenvalues lambda = omega^2 of
+ *
+ *     Op = A M A^H + gamma B^H B                                   (Section 2.3, eq (2.13))
+ *
+ * with A the Yee curl and B the divergence of eqs (2.5)-(2.7), M the discrete inverse
+ * permittivity (eq (3.3) diagonal, eq (3.4) "Trivial", eq (3.8) "CrossDoF") and gamma the
+ * penalty of eq (2.26).  The library works on k-space coefficients x = F3^H H (eq (2.30)),
+ * where F3 applies the unitary DFT of Lemma 2.1 (omega = exp(+2 pi i/N)) to each of the
+ * three face components; in those coordinates Op becomes
+ *
+ *     K_A F3^H M F3 K_A^H + gamma K_B                               (Prop 2.8, eq (2.30))
+ *
+ * with K_A, K_B diagonal per frequency.
+ *
+ * Vector layout.  A block of nvec vectors is complex128 (interleaved re, im), laid out
+ * [nvec][3][N][N][N] with the k-space index (qz, qy, qx), qx fastest; frequency index q
+ * corresponds to theta_q = 2 pi q / N.  Unless a function says otherwise vector pointers
+ * are DEVICE pointers owned by the caller; "_host" arguments are host pointers.
+ *
+ * Streams.  Every call that touches the GPU takes a hipStream_t passed as void* (NULL is
+ * the default stream) and enqueues its work there; calls return after enqueueing, except
+ * kc_solve which returns when the solve is complete.
+ *
+ * Errors.  Every function returns a kc_status; on error kc_last_error() gives a message
+ * (per calling thread).  No C++ exception crosses this boundary.  A handle is not
+ * thread-safe.
+ *
+ * Memory.  The library owns the handle and its device workspaces (allocated on first use
+ * with hipMalloc, grown as needed, released by kc_destroy).
+ */
+#ifndef KCPC_H
+#define KCPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum kc_status {
+  KC_OK = 0,
+  KC_ERR_INVALID_ARG = 1,   /* bad pointer, size or index                               */
+  KC_ERR_UNSUPPORTED = 2,   /* N is not a supported FFT length (see kc_supported_n)    */
+  KC_ERR_NOT_HPD = 3,       /* inverse-permittivity table violates Assumption 3.1      */
+  KC_ERR_HIP = 4,           /* a HIP runtime call or kernel launch failed              */
+  KC_ERR_ALLOC = 5,         /* device allocation failed                                */
+  KC_ERR_NO_CONVERGENCE = 6,/* kc_solve hit maxit; outputs hold the best iterate       */
+  KC_ERR_BREAKDOWN = 7      /* non-finite values or loss of positive definiteness      */
+} kc_status;
+
+/* Discretisation of the inverse permittivity (Section 3). */
+enum {
+  KC_EPS_DIAGONAL = 0, /* eq (3.3): diagonal entries at edge points, off-diagonals ignored   */
+  KC_EPS_TRIVIAL = 1,  /* eq (3.4): off-diagonal entries at volume points, no interpolation  */
+  KC_EPS_CROSSDOF = 2  /* eq (3.8): symmetrised cross-DoF transfer (four-point averages)     */
+};
+
+/* Arithmetic of the operator application (FFTs, curl, permittivity). */
+enum { KC_PREC_FP64 = 0, KC_PREC_FP32 = 1 };
+
+typedef struct kc_op kc_op;
+
+/* 1 if N is a supported grid division (FFT length), else 0.  Supported: 4, 6, 8, 12, 16,
+ * 24, 32, 48, 64, 96, 128. */
+int kc_supported_n(int N);
+
+/*
+ * Create an operator for grid division N and an inverse-permittivity field.
+ *   mat_ids_host : uint8 [4][N^3] material ids of the x-edge, y-edge, z-edge and volume
+ *                  points (eqs (2.1)-(2.3), eq (3.2)); index i + N j + N^2 k.  The points of
+ *                  cell (i, j, k) are ((i-1/2)h, jh, kh), (ih, (j-1/2)h, kh),
+ *                  (ih, jh, (k-1/2)h) and ((i-1/2)h, (j-1/2)h, (k-1/2)h).
+ *   eps_inv_host : float64 [n_mat][3][3][2]: the complex inverse permittivity of each
+ *                  material (row-major, (re, im)); must be Hermitian with eigenvalues in
+ *                  (0, 1] (Assumption 3.1), else KC_ERR_NOT_HPD.  Material 0 is usually air.
+ *   eps_scheme   : KC_EPS_DIAGONAL / KC_EPS_TRIVIAL / KC_EPS_CROSSDOF.
+ * The ids and the table are copied; the caller keeps ownership of its buffers.
+ */
+int kc_create(int N, int eps_scheme, const uint8_t* mat_ids_host, int n_mat,
+              const double* eps_inv_host, kc_op** out);
+
+/*
+ * Set the Bloch wave vectors (Cartesian, lattice constant 1): k_host float64 [nk][3].
+ * gamma_host: float64 [nk] penalty coefficients, or NULL for the rule of Remark 2.6,
+ * eq (2.26) (4 pi^2 if k = 0 or |k| >= 1, else 4 pi^2 / |k|^2).
+ */
+int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_host);
+
+/* Penalty coefficients in use: gamma_host float64 [nk]. */
+int kc_get_gamma(const kc_op* op, double* gamma_host);
+
+/*
+ * y = Op_k x for nvec vectors (k-space coefficients, eq (2.30)).  Vector v uses the k-point
+ * ik0 + v / vecs_per_k (vecs_per_k >= 1; use vecs_per_k = nvec for a single k-point).
+ *   x, y : device complex128 [nvec][3][N^3]; x and y must not overlap.
+ *   prec : KC_PREC_FP64, or KC_PREC_FP32 (FFTs, curl and permittivity in FP32; the penalty
+ *          term and the result are accumulated in FP64).
+ */
+int kc_apply(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* x, void* y, int prec,
+             void* stream);
+
+/*
+ * z = K_P^{-1} r, the diagonal-block preconditioner of eqs (2.31)-(2.32), per frequency:
+ * K_P = K_A K_A^H + gamma K_B.  Where K_P is singular (the DC frequency at k = 0, whose
+ * modes are the constant fields of Prop 2.5) z is zero.  r, z: device complex128
+ * [nvec][3][N^3]; r == z is allowed.
+ */
+int kc_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z,
+               void* stream);
+
+/*
+ * Unnormalised 3D DFT of nvec scalar grids along x, y and z:
+ *   out[q] = sum_j in[j] exp(sign 2 pi i (j . q) / N), sign = +1 or -1.
+ * prec KC_PREC_FP64: in/out complex128 [nvec][N^3]; KC_PREC_FP32: complex64.  in == out is
+ * allowed.  (The building block of kc_apply, exposed for testing.)
+ */
+int kc_fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, void* stream);
+
+/* Solver options for kc_solve (LOBPCG with soft locking, Section 4). */
+typedef struct kc_solve_opts {
+  int m;              /* bands wanted (smallest positive eigenvalues)                      */
+  int guard;          /* extra block columns carried but not required to converge (>= 0) */
+  double tol;         /* convergence: Res_j = ||Op x_j - lambda_j x_j|| / ||x_j|| <= tol  */
+                      /* (eq (4.3)), checked with an FP64 operator application             */
+  int maxit;          /* iteration limit                                                   */
+  int prec;           /* KC_PREC_FP64, or KC_PREC_FP32: FP32 operator applications until   */
+                      /* the residuals reach switch_tol, FP64 from there on                */
+  double switch_tol;  /* residual level where FP32 applications stop (prec = FP32)         */
+  int batch_k;        /* k-points solved together in one set of launches (>= 1)            */
+  uint64_t seed;      /* seed of the random initial block                                  */
+  int verbose;        /* 1: print per-iteration residuals to stderr                        */
+} kc_solve_opts;
+
+/* Fill opts with defaults (m = 10, guard = 0, tol = 1e-8, maxit = 500, FP64, batch_k = 1). */
+void kc_solve_opts_default(kc_solve_opts* opts);
+
+/*
+ * Smallest positive eigenvalues of Op_k for k-points ik0 .. ik0+nk-1.
+ *   eig_host   : float64 [nk][m] eigenvalues lambda = omega^2, ascending
+ *   res_host   : float64 [nk][m] final residuals Res_j (eq (4.3)), FP64 application
+ *   iters_host : int32 [nk] iterations used (may be NULL)
+ *   X_out      : NULL, or device complex128 [nk][m][3][N^3] for the eigenvectors
+ * At k = 0 the three constant fields (Prop 2.5 (1)) are deflated and not reported.
+ * Returns KC_ERR_NO_CONVERGENCE if some k-point did not reach tol within maxit (outputs
+ * then hold the last iterate).
+ */
+int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_host,
+             double* res_host, int* iters_host, void* X_out, void* stream);
+
+/* Statistics of the last kc_solve: float64 [8] = {matvecs FP64 (vector count), matvecs FP32,
+ * seconds total, iterations (sum over k-points), 0, 0, 0, 0}. */
+int kc_last_solve_stats(const kc_op* op, double* stats_host);
+
+/* Release the handle and every device buffer it owns.  NULL is allowed. */
+void kc_destroy(kc_op* op);
+
+/* Human-readable name of a status code. */
+const char* kc_status_string(int status);
+
+/* Message of the last error raised in this thread ("" if none). */
+const char* kc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KCPC_H */

@@ -1,0 +1,206 @@
+"""ctypes binding of libkcpc.so (include/kcpc.h): argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(HERE, "libkcpc.so")
+
+KC_EPS_DIAGONAL, KC_EPS_TRIVIAL, KC_EPS_CROSSDOF = 0, 1, 2
+KC_PREC_FP64, KC_PREC_FP32 = 0, 1
+KC_OK, KC_ERR_NO_CONVERGENCE = 0, 6
+
+_lib = None
+
+
+class KcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (msg, _status_name(status)))
+        self.status = status
+
+
+class KcSolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int),
+        ("guard", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("maxit", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("switch_tol", ctypes.c_double),
+        ("batch_k", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("verbose", ctypes.c_int),
+    ]
+
+
+def lib():
+    """The loaded library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(lib_path):
+            raise KcError(-1, "libkcpc.so is not built (run python -m paper_2511_17107_amd.build)")
+        L = ctypes.CDLL(lib_path)
+        vp, i32, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        L.kc_supported_n.argtypes = [i32]
+        L.kc_create.argtypes = [i32, i32, vp, i32, vp, ctypes.POINTER(vp)]
+        L.kc_set_kpoints.argtypes = [vp, i32, vp, vp]
+        L.kc_get_gamma.argtypes = [vp, vp]
+        L.kc_apply.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
+        L.kc_precond.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+        L.kc_fft3d.argtypes = [i32, i32, i32, i32, vp, vp, vp]
+        L.kc_solve_opts_default.argtypes = [ctypes.POINTER(KcSolveOpts)]
+        L.kc_solve_opts_default.restype = None
+        L.kc_solve.argtypes = [vp, i32, i32, ctypes.POINTER(KcSolveOpts), vp, vp, vp, vp, vp]
+        L.kc_last_solve_stats.argtypes = [vp, vp]
+        L.kc_destroy.argtypes = [vp]
+        L.kc_destroy.restype = None
+        L.kc_status_string.argtypes = [i32]
+        L.kc_status_string.restype = ctypes.c_char_p
+        L.kc_last_error.argtypes = []
+        L.kc_last_error.restype = ctypes.c_char_p
+        _ = dp
+        _lib = L
+    return _lib
+
+
+def _status_name(st: int) -> str:
+    if _lib is None or st < 0:
+        return "KC_ERR"
+    return _lib.kc_status_string(st).decode()
+
+
+def _check(st: int, what: str):
+    if st != KC_OK:
+        raise KcError(st, "%s failed: %s" % (what, lib().kc_last_error().decode()))
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name: str, what: str):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % what)
+    if str(t.dtype) != dtype_name:
+        raise TypeError("%s must have dtype %s, got %s" % (what, dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def kc_supported_n(N: int) -> bool:
+    return bool(lib().kc_supported_n(int(N)))
+
+
+def kc_fft3d(x, sign: int, prec: int = KC_PREC_FP64, out=None, stream=None):
+    """Unnormalised 3D DFT of x (complex128 for FP64, complex64 for FP32), shape (nvec, N^3)
+    or (nvec, N, N, N); out may be x."""
+    import torch
+
+    N = int(round(x.shape[-1] ** (1.0 / 3.0))) if x.dim() == 2 else int(x.shape[-1])
+    nvec = x.shape[0]
+    dt = "torch.complex128" if prec == KC_PREC_FP64 else "torch.complex64"
+    if out is None:
+        out = torch.empty_like(x)
+    _check(lib().kc_fft3d(N, nvec, int(sign), int(prec), _dev_ptr(x, dt, "x"), _dev_ptr(out, dt, "out"),
+                          _stream(stream)), "kc_fft3d")
+    return out
+
+
+class Op:
+    """Handle of one operator (grid, inverse-permittivity field, k-points)."""
+
+    def __init__(self, N: int, scheme: int, ids: np.ndarray, table: np.ndarray):
+        ids = np.ascontiguousarray(ids, dtype=np.uint8)
+        assert ids.shape == (4, N ** 3), ids.shape
+        tab = np.ascontiguousarray(np.asarray(table, dtype=np.complex128))
+        assert tab.ndim == 3 and tab.shape[1:] == (3, 3)
+        tab_r = np.ascontiguousarray(tab.view(np.float64).reshape(tab.shape[0], 3, 3, 2))
+        h = ctypes.c_void_p()
+        _check(lib().kc_create(int(N), int(scheme), ids.ctypes.data_as(ctypes.c_void_p), int(tab.shape[0]),
+                               tab_r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)), "kc_create")
+        self._h = h
+        self.N = int(N)
+        self.nk = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.kc_destroy(h)
+            self._h = None
+
+    def set_kpoints(self, k: np.ndarray, gamma: Optional[np.ndarray] = None):
+        k = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1, 3))
+        g = None if gamma is None else np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(-1))
+        _check(lib().kc_set_kpoints(self._h, int(k.shape[0]), k.ctypes.data_as(ctypes.c_void_p),
+                                    None if g is None else g.ctypes.data_as(ctypes.c_void_p)), "kc_set_kpoints")
+        self.nk = int(k.shape[0])
+
+    def gamma(self) -> np.ndarray:
+        g = np.zeros(self.nk)
+        _check(lib().kc_get_gamma(self._h, g.ctypes.data_as(ctypes.c_void_p)), "kc_get_gamma")
+        return g
+
+    def apply(self, x, ik0: int = 0, vecs_per_k: Optional[int] = None, prec: int = KC_PREC_FP64,
+              out=None, stream=None):
+        """y = Op x; x complex128 (nvec, 3, N^3) on the GPU."""
+        import torch
+
+        nvec = x.shape[0]
+        if out is None:
+            out = torch.empty_like(x)
+        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _check(lib().kc_apply(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(x, "torch.complex128", "x"),
+                              _dev_ptr(out, "torch.complex128", "y"), int(prec), _stream(stream)), "kc_apply")
+        return out
+
+    def precond(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, out=None, stream=None):
+        import torch
+
+        nvec = r.shape[0]
+        if out is None:
+            out = torch.empty_like(r)
+        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _check(lib().kc_precond(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(r, "torch.complex128", "r"),
+                                _dev_ptr(out, "torch.complex128", "z"), _stream(stream)), "kc_precond")
+        return out
+
+    def solve(self, m: int, ik0: int = 0, nk: Optional[int] = None, tol: float = 1e-8, maxit: int = 500,
+              prec: int = KC_PREC_FP64, switch_tol: float = 1e-3, batch_k: int = 1, guard: int = 0,
+              seed: int = 1234, X_out=None, verbose: int = 0, stream=None, check: bool = True):
+        """Smallest positive eigenvalues for k-points ik0 .. ik0+nk-1.  Returns
+        (eig (nk, m), res (nk, m), iters (nk,), status)."""
+        nk = self.nk - ik0 if nk is None else int(nk)
+        o = KcSolveOpts()
+        lib().kc_solve_opts_default(ctypes.byref(o))
+        o.m, o.guard, o.tol, o.maxit, o.prec = int(m), int(guard), float(tol), int(maxit), int(prec)
+        o.switch_tol, o.batch_k, o.seed, o.verbose = float(switch_tol), int(batch_k), int(seed), int(verbose)
+        eig = np.zeros((nk, m))
+        res = np.zeros((nk, m))
+        its = np.zeros(nk, dtype=np.int32)
+        xo = None if X_out is None else _dev_ptr(X_out, "torch.complex128", "X_out")
+        st = lib().kc_solve(self._h, int(ik0), nk, ctypes.byref(o), eig.ctypes.data_as(ctypes.c_void_p),
+                            res.ctypes.data_as(ctypes.c_void_p), its.ctypes.data_as(ctypes.c_void_p), xo,
+                            _stream(stream))
+        if check and st not in (KC_OK, KC_ERR_NO_CONVERGENCE):
+            _check(st, "kc_solve")
+        return eig, res, its, st
+
+    def last_solve_stats(self) -> np.ndarray:
+        s = np.zeros(8)
+        _check(lib().kc_last_solve_stats(self._h, s.ctypes.data_as(ctypes.c_void_p)), "kc_last_solve_stats")
+        return s
+
+
+def kc_create(N: int, scheme: int, ids: np.ndarray, table: np.ndarray) -> Op:
+    return Op(N, scheme, ids, table)

@@ -1,0 +1,337 @@
+// C ABI entry points (include/kcpc.h): argument checking, set-up of the per-k symbol tables,
+// the inverse-permittivity table and the twiddles, and dispatch to the kernels.
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "kc_state.h"
+
+namespace kc {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+int DevBuf::ensure(size_t n) {
+  if (n <= bytes && p != nullptr) return KC_OK;
+  release();
+  if (n == 0) return KC_OK;
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    p = nullptr;
+    set_error(std::string("hipMalloc(") + std::to_string(n) + "): " + hipGetErrorString(e));
+    return KC_ERR_ALLOC;
+  }
+  e = hipMemset(p, 0, n);
+  if (e != hipSuccess) {
+    set_error(std::string("hipMemset: ") + hipGetErrorString(e));
+    return KC_ERR_HIP;
+  }
+  bytes = n;
+  return KC_OK;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+int fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, const void* tw, hipStream_t s);
+void solver_release(kc_op* op);
+
+static bool supported_n(int N) {
+  switch (N) {
+    case 4: case 6: case 8: case 12: case 16: case 24: case 32: case 48: case 64: case 96: case 128:
+      return true;
+    default:
+      return false;
+  }
+}
+
+// twiddles exp(+2 pi i t/N), t < N, from long double
+static void make_twiddles(int N, std::vector<c64>& d, std::vector<c32>& f) {
+  d.resize(N);
+  f.resize(N);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int t = 0; t < N; ++t) {
+    const long double a = 2.0L * pi * (long double)t / (long double)N;
+    const long double c = std::cos(a), s = std::sin(a);
+    d[t] = mk((double)c, (double)s);
+    f[t] = mk((float)c, (float)s);
+  }
+}
+
+template <typename T>
+static int upload(DevBuf& b, const std::vector<T>& v) {
+  KC_TRY(b.ensure(v.size() * sizeof(T)));
+  KC_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return KC_OK;
+}
+
+// Hermitian 3x3 check of Assumption 3.1 (eigenvalues in (0, 1]): Cholesky of A (positive
+// definite) and of I - A + tol I (I - A positive semi-definite).
+static bool chol3_pd(std::complex<double> A[3][3]) {
+  std::complex<double> L[3][3] = {};
+  for (int j = 0; j < 3; ++j) {
+    double d = A[j][j].real();
+    for (int k = 0; k < j; ++k) d -= std::norm(L[j][k]);
+    if (!(d > 0.0)) return false;
+    L[j][j] = std::sqrt(d);
+    for (int i = j + 1; i < 3; ++i) {
+      std::complex<double> s = A[i][j];
+      for (int k = 0; k < j; ++k) s -= L[i][k] * std::conj(L[j][k]);
+      L[i][j] = s / L[j][j].real();
+    }
+  }
+  return true;
+}
+
+static int check_table(int n_mat, const double* t) {
+  for (int m = 0; m < n_mat; ++m) {
+    std::complex<double> A[3][3], B[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) A[r][c] = {t[((m * 3 + r) * 3 + c) * 2], t[((m * 3 + r) * 3 + c) * 2 + 1]};
+    double scale = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) scale = std::max(scale, std::abs(A[r][c]));
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c)
+        if (std::abs(A[r][c] - std::conj(A[c][r])) > 1e-12 * std::max(scale, 1.0)) {
+          set_error("inverse permittivity of material " + std::to_string(m) + " is not Hermitian");
+          return KC_ERR_NOT_HPD;
+        }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) B[r][c] = (r == c ? 1.0 + 1e-12 : 0.0) - A[r][c];
+    if (!chol3_pd(A) || !chol3_pd(B)) {
+      set_error("inverse permittivity of material " + std::to_string(m) +
+                " has an eigenvalue outside (0, 1] (Assumption 3.1)");
+      return KC_ERR_NOT_HPD;
+    }
+  }
+  return KC_OK;
+}
+
+// per-N twiddle tables for kc_fft3d (one set per process and device)
+struct TwCache {
+  std::mutex mu;
+  std::map<std::pair<int, int>, DevBuf*> tabs;  // (device, N) -> [c64 N | c32 N]
+};
+static TwCache& twcache() {
+  static TwCache* c = new TwCache();  // never destroyed: outlives static destructors
+  return *c;
+}
+
+}  // namespace kc
+
+using namespace kc;
+
+extern "C" {
+
+int kc_supported_n(int N) { return supported_n(N) ? 1 : 0; }
+
+int kc_create(int N, int eps_scheme, const uint8_t* mat_ids_host, int n_mat, const double* eps_inv_host,
+              kc_op** out) {
+  KC_ARG(out != nullptr, "out is NULL");
+  *out = nullptr;
+  if (!supported_n(N)) {
+    set_error("grid division N=" + std::to_string(N) + " is not a supported FFT length");
+    return KC_ERR_UNSUPPORTED;
+  }
+  KC_ARG(eps_scheme == KC_EPS_DIAGONAL || eps_scheme == KC_EPS_TRIVIAL || eps_scheme == KC_EPS_CROSSDOF,
+         "eps_scheme");
+  KC_ARG(mat_ids_host != nullptr && eps_inv_host != nullptr, "NULL ids or table");
+  KC_ARG(n_mat >= 1 && n_mat <= KC_MAX_MAT, "n_mat must be in [1, 64]");
+  KC_TRY(check_table(n_mat, eps_inv_host));
+  const size_t N3 = (size_t)N * N * N;
+  std::vector<uint32_t> packed(N3);
+  for (size_t p = 0; p < N3; ++p) {
+    uint32_t w = 0;
+    for (int s = 0; s < 4; ++s) {
+      const uint8_t id = mat_ids_host[s * N3 + p];
+      if (id >= n_mat) {
+        set_error("material id " + std::to_string(id) + " >= n_mat");
+        return KC_ERR_INVALID_ARG;
+      }
+      w |= (uint32_t)id << (8 * s);
+    }
+    packed[p] = w;
+  }
+  kc_op* op = new kc_op();
+  op->N = N;
+  op->scheme = eps_scheme;
+  op->n_mat = n_mat;
+  op->eps_host.assign(eps_inv_host, eps_inv_host + (size_t)n_mat * 18);
+  // permittivity entries scaled by 1/N^3 (normalisation of the two unnormalised DFTs)
+  const double sc = 1.0 / (double)N3;
+  std::vector<EpsEntry<double>> e64(n_mat);
+  std::vector<EpsEntry<float>> e32(n_mat);
+  const int offd[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (int m = 0; m < n_mat; ++m) {
+    const double* t = eps_inv_host + (size_t)m * 18;
+    for (int c = 0; c < 3; ++c) {
+      e64[m].d[c] = t[(c * 3 + c) * 2] * sc;
+      e32[m].d[c] = (float)e64[m].d[c];
+    }
+    for (int q = 0; q < 3; ++q) {
+      const int r = offd[q][0], c = offd[q][1];
+      double re = t[(r * 3 + c) * 2] * sc, im = t[(r * 3 + c) * 2 + 1] * sc;
+      if (eps_scheme == KC_EPS_DIAGONAL) re = im = 0.0;
+      e64[m].o[q] = mk(re, im);
+      e32[m].o[q] = mk((float)re, (float)im);
+    }
+  }
+  int st = upload(op->ids, packed);
+  if (st == KC_OK) st = upload(op->eps64, e64);
+  if (st == KC_OK) st = upload(op->eps32, e32);
+  std::vector<c64> twd;
+  std::vector<c32> twf;
+  make_twiddles(N, twd, twf);
+  if (st == KC_OK) st = upload(op->tw64, twd);
+  if (st == KC_OK) st = upload(op->tw32, twf);
+  if (st != KC_OK) {
+    delete op;
+    return st;
+  }
+  *out = op;
+  return KC_OK;
+}
+
+int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_host) {
+  KC_ARG(op != nullptr, "op is NULL");
+  KC_ARG(nk >= 1 && k_host != nullptr, "nk >= 1 and k_host required");
+  const int N = op->N;
+  const double h = 1.0 / N;
+  const double fourpi2 = 4.0 * M_PI * M_PI;
+  op->nk = nk;
+  op->kvec.assign(k_host, k_host + 3 * (size_t)nk);
+  op->gamma.resize(nk);
+  std::vector<c64> kt((size_t)nk * 3 * N);
+  std::vector<c32> kf(kt.size());
+  for (int ik = 0; ik < nk; ++ik) {
+    const double* k = k_host + 3 * ik;
+    for (int a = 0; a < 3; ++a)
+      KC_ARG(std::isfinite(k[a]), "non-finite wave vector");
+    const double kn2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    double g;
+    if (gamma_host) {
+      g = gamma_host[ik];
+      KC_ARG(std::isfinite(g) && g > 0.0, "gamma must be positive");
+    } else {
+      // Remark 2.6, eq (2.26)
+      g = (kn2 == 0.0 || kn2 >= 1.0) ? fourpi2 : fourpi2 / kn2;
+    }
+    op->gamma[ik] = g;
+    for (int a = 0; a < 3; ++a) {
+      for (int q = 0; q < N; ++q) {
+        // eigenvalues of D1 and D0 (first rows (1,0,...,0,-1)/h and (1,0,...,0,1)/2) by
+        // Lemma 2.1: (1 - e^{-i theta})/h and (1 + e^{-i theta})/2, theta = 2 pi q/N
+        const double th = 2.0 * M_PI * (double)q / (double)N;
+        const std::complex<double> em(std::cos(th), -std::sin(th));
+        const std::complex<double> l1 = (1.0 - em) / h;
+        const std::complex<double> l0 = 0.5 * (1.0 + em);
+        const std::complex<double> K = l1 + std::complex<double>(0.0, k[a]) * l0;
+        kt[((size_t)ik * 3 + a) * N + q] = mk(K.real(), K.imag());
+        kf[((size_t)ik * 3 + a) * N + q] = mk((float)K.real(), (float)K.imag());
+      }
+    }
+  }
+  KC_TRY(upload(op->ktab64, kt));
+  KC_TRY(upload(op->ktab32, kf));
+  KC_TRY(upload(op->gamma_d, op->gamma));
+  return KC_OK;
+}
+
+int kc_get_gamma(const kc_op* op, double* gamma_host) {
+  KC_ARG(op != nullptr && gamma_host != nullptr, "NULL argument");
+  for (int i = 0; i < op->nk; ++i) gamma_host[i] = op->gamma[i];
+  return KC_OK;
+}
+
+int kc_apply(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* x, void* y, int prec, void* stream) {
+  KC_ARG(op != nullptr, "op is NULL");
+  KC_ARG(op->nk > 0, "no k-points set");
+  KC_ARG(nvec >= 0 && vecs_per_k >= 1, "nvec >= 0, vecs_per_k >= 1");
+  KC_ARG(prec == KC_PREC_FP64 || prec == KC_PREC_FP32, "prec");
+  if (nvec == 0) return KC_OK;
+  KC_ARG(x != nullptr && y != nullptr && x != y, "x, y must be distinct device buffers");
+  KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
+  return apply_op(op, ik0, nvec, vecs_per_k, (const c64*)x, (c64*)y, prec, (hipStream_t)stream);
+}
+
+int kc_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z, void* stream) {
+  KC_ARG(op != nullptr, "op is NULL");
+  KC_ARG(op->nk > 0, "no k-points set");
+  KC_ARG(nvec >= 0 && vecs_per_k >= 1, "nvec >= 0, vecs_per_k >= 1");
+  if (nvec == 0) return KC_OK;
+  KC_ARG(r != nullptr && z != nullptr, "NULL vector");
+  KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
+  return apply_precond(op, ik0, nvec, vecs_per_k, (const c64*)r, (c64*)z, (hipStream_t)stream);
+}
+
+int kc_fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, void* stream) {
+  if (!supported_n(N)) {
+    set_error("unsupported N");
+    return KC_ERR_UNSUPPORTED;
+  }
+  KC_ARG(nvec >= 0, "nvec");
+  KC_ARG(sign == 1 || sign == -1, "sign must be +1 or -1");
+  KC_ARG(prec == KC_PREC_FP64 || prec == KC_PREC_FP32, "prec");
+  if (nvec == 0) return KC_OK;
+  KC_ARG(in != nullptr && out != nullptr, "NULL buffer");
+  int dev = 0;
+  KC_HIP(hipGetDevice(&dev));
+  DevBuf* tb = nullptr;
+  {
+    TwCache& c = twcache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.tabs.find({dev, N});
+    if (it == c.tabs.end()) {
+      std::vector<c64> d;
+      std::vector<c32> f;
+      make_twiddles(N, d, f);
+      tb = new DevBuf();
+      KC_TRY(tb->ensure(N * (sizeof(c64) + sizeof(c32))));
+      KC_HIP(hipMemcpy(tb->p, d.data(), N * sizeof(c64), hipMemcpyHostToDevice));
+      KC_HIP(hipMemcpy((char*)tb->p + N * sizeof(c64), f.data(), N * sizeof(c32), hipMemcpyHostToDevice));
+      c.tabs[{dev, N}] = tb;
+    } else {
+      tb = it->second;
+    }
+  }
+  const void* tw = (prec == KC_PREC_FP64) ? tb->p : (const void*)((const char*)tb->p + N * sizeof(c64));
+  return fft3d(N, nvec, sign, prec, in, out, tw, (hipStream_t)stream);
+}
+
+int kc_last_solve_stats(const kc_op* op, double* stats_host) {
+  KC_ARG(op != nullptr && stats_host != nullptr, "NULL argument");
+  for (int i = 0; i < 8; ++i) stats_host[i] = op->stats[i];
+  return KC_OK;
+}
+
+void kc_destroy(kc_op* op) {
+  if (!op) return;
+  solver_release(op);
+  delete op;
+}
+
+const char* kc_status_string(int status) {
+  switch (status) {
+    case KC_OK: return "KC_OK";
+    case KC_ERR_INVALID_ARG: return "KC_ERR_INVALID_ARG";
+    case KC_ERR_UNSUPPORTED: return "KC_ERR_UNSUPPORTED";
+    case KC_ERR_NOT_HPD: return "KC_ERR_NOT_HPD";
+    case KC_ERR_HIP: return "KC_ERR_HIP";
+    case KC_ERR_ALLOC: return "KC_ERR_ALLOC";
+    case KC_ERR_NO_CONVERGENCE: return "KC_ERR_NO_CONVERGENCE";
+    case KC_ERR_BREAKDOWN: return "KC_ERR_BREAKDOWN";
+    default: return "KC_ERR_UNKNOWN";
+  }
+}
+
+const char* kc_last_error(void) { return get_error(); }
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// Common definitions of the kcpc HIP library (gfx950): complex type, error plumbing,
+// launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/kcpc.h"
+
+namespace kc {
+
+// ----------------------------------------------------------------------------------------
+// complex numbers: interleaved (re, im), 8- or 16-byte aligned so a load is one vector op
+// ----------------------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> mk(T r, T i) {
+  cpx<T> z;
+  z.re = r;
+  z.im = i;
+  return z;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) {
+  return mk(a.re + b.re, a.im + b.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) {
+  return mk(a.re - b.re, a.im - b.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) {
+  return mk(s * a.re, s * a.im);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> conj(cpx<T> a) {
+  return mk(a.re, -a.im);
+}
+// conj(a) * b
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+// i * a
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) {
+  return mk(-a.im, a.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ T abs2(cpx<T> a) {
+  return a.re * a.re + a.im * a.im;
+}
+template <typename TO, typename TI>
+__host__ __device__ __forceinline__ cpx<TO> cvt(cpx<TI> a) {
+  return mk(static_cast<TO>(a.re), static_cast<TO>(a.im));
+}
+
+using c64 = cpx<double>;  // complex128
+using c32 = cpx<float>;   // complex64
+
+// ----------------------------------------------------------------------------------------
+// error plumbing: every C entry point returns a status; the message is kept per thread
+// ----------------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+const char* get_error();
+
+#define KC_HIP(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      ::kc::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));             \
+      return KC_ERR_HIP;                                                              \
+    }                                                                                 \
+  } while (0)
+
+#define KC_TRY(expr)            \
+  do {                          \
+    int s_ = (expr);            \
+    if (s_ != KC_OK) return s_; \
+  } while (0)
+
+#define KC_ARG(cond, msg)                             \
+  do {                                                \
+    if (!(cond)) {                                    \
+      ::kc::set_error(std::string("invalid argument: ") + (msg)); \
+      return KC_ERR_INVALID_ARG;                      \
+    }                                                 \
+  } while (0)
+
+// after a kernel launch
+#define KC_LAUNCHED()                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess) {                                                            \
+      ::kc::set_error(std::string("kernel launch: ") + hipGetErrorString(e_));         \
+      return KC_ERR_HIP;                                                               \
+    }                                                                                  \
+  } while (0)
+
+// Workgroup ids are dealt to the 8 XCDs of an MI355X round-robin (id % 8).  Remapping makes
+// consecutive logical tiles land on the same XCD (and hence share its L2) while the grid is
+// still spread evenly over the chip.  Requires nblocks to be a multiple of 8 to be a
+// bijection; otherwise the identity is used.
+__device__ __forceinline__ unsigned xcd_swizzle(unsigned b, unsigned nblocks) {
+  if ((nblocks & 7u) != 0u) return b;
+  const unsigned per = nblocks >> 3;
+  return (b & 7u) * per + (b >> 3);
+}
+
+}  // namespace kc

@@ -1,0 +1,65 @@
+// Internal state of a kc_op handle and the launchers shared between translation units.
+#pragma once
+
+#include <vector>
+
+#include "kc_common.h"
+
+namespace kc {
+
+// Largest number of materials (entries of the inverse-permittivity table).
+constexpr int KC_MAX_MAT = 64;
+
+// Inverse-permittivity entry of one material in compute precision T: the real diagonal
+// (eps^-1)_cc and the upper off-diagonals (eps^-1)_12, _13, _23, all pre-multiplied by 1/N^3
+// (the normalisation of the two unnormalised 3D DFTs around the permittivity step).
+template <typename T>
+struct EpsEntry {
+  T d[3];
+  cpx<T> o[3];
+};
+
+// Device buffer that grows on demand (contents are not preserved when it grows).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t n);  // zero-fills newly allocated memory
+  void release();
+  ~DevBuf() { release(); }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct SolverWork;  // LOBPCG buffers (kc_solver.hip)
+
+}  // namespace kc
+
+struct kc_op {
+  int N = 0;
+  int scheme = 0;
+  int n_mat = 0;
+  std::vector<double> eps_host;  // [n_mat][3][3][2]
+  kc::DevBuf ids;                // uint32 [N^3]: x-edge | y-edge << 8 | z-edge << 16 | vol << 24
+  kc::DevBuf eps64, eps32;       // EpsEntry<double/float> [n_mat]
+  kc::DevBuf tw64, tw32;         // twiddles exp(+2 pi i t/N), t < N
+  int nk = 0;
+  std::vector<double> kvec, gamma;  // [nk][3], [nk]
+  kc::DevBuf ktab64, ktab32;        // 1D symbols [nk][3][N]
+  kc::DevBuf gamma_d;               // double [nk]
+  kc::DevBuf work_a, work_b;        // operator intermediates
+  kc::SolverWork* solver = nullptr;
+  double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace kc {
+
+// y = Op x (kc_apply without argument checks); vectors v use k-point ik0 + v / vecs_per_k.
+int apply_op(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* x, c64* y, int prec,
+             hipStream_t s);
+// z = K_P^{-1} r
+int apply_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* r, c64* z,
+                  hipStream_t s);
+
+}  // namespace kc

@@ -1,0 +1,88 @@
+"""The C-ABI library loads and exports every symbol declared in include/kcpc.h; host-side
+argument checks return the documented status codes without touching a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2511_17107_amd as kc
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kcpc.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char)\s*\*?\s*(kc_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["kc_create", "kc_set_kpoints", "kc_apply", "kc_precond", "kc_solve", "kc_destroy",
+              "kc_fft3d", "kc_last_error", "kc_status_string"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = kc.lib()
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_supported_sizes():
+    for N in (4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128):
+        assert kc.kc_supported_n(N)
+    for N in (0, 1, 2, 3, 5, 7, 10, 100, 120, 256):
+        assert not kc.kc_supported_n(N)
+
+
+def test_status_strings():
+    L = kc.lib()
+    assert L.kc_status_string(0) == b"KC_OK"
+    assert L.kc_status_string(3) == b"KC_ERR_NOT_HPD"
+    assert L.kc_status_string(99) == b"KC_ERR_UNKNOWN"
+
+
+def test_create_rejects_unsupported_n():
+    ids = np.zeros((4, 5 ** 3), dtype=np.uint8)
+    with pytest.raises(kc.KcError) as e:
+        kc.Op(5, kc.KC_EPS_CROSSDOF, ids, W.eps_table([]))
+    assert e.value.status == 2
+
+
+def test_create_rejects_table_outside_assumption_31():
+    """Assumption 3.1: eigenvalues of the inverse permittivity in (0, 1]."""
+    N = 4
+    ids = np.zeros((4, N ** 3), dtype=np.uint8)
+    bad = [np.diag([2.0, 1.0, 1.0]).astype(complex),           # eigenvalue 2 > 1
+           np.diag([0.5, -0.1, 0.5]).astype(complex),           # not positive
+           np.array([[0.5, 0.1j, 0], [0.1j, 0.5, 0], [0, 0, 0.5]])]  # not Hermitian
+    for t in bad:
+        tab = np.stack([np.eye(3, dtype=complex), t])
+        with pytest.raises(kc.KcError) as e:
+            kc.Op(N, kc.KC_EPS_CROSSDOF, ids, tab)
+        assert e.value.status == 3
+
+
+def test_create_rejects_bad_ids():
+    N = 4
+    ids = np.zeros((4, N ** 3), dtype=np.uint8)
+    ids[2, 5] = 7
+    with pytest.raises(kc.KcError) as e:
+        kc.Op(N, kc.KC_EPS_TRIVIAL, ids, W.eps_table([13 * np.eye(3)]))
+    assert e.value.status == 1
+
+
+def test_null_handle_arguments():
+    L = kc.lib()
+    vp = ctypes.c_void_p
+    assert L.kc_set_kpoints(None, 1, None, None) == 1
+    assert L.kc_apply(None, 0, 1, 1, vp(1), vp(2), 0, None) == 1
+    assert L.kc_solve(None, 0, 1, None, None, None, None, None, None) == 1
+    assert b"NULL" in L.kc_last_error() or b"invalid" in L.kc_last_error()
+    L.kc_destroy(None)

@@ -1,0 +1,160 @@
+"""Parity of the HIP path (through the C ABI) against the CPU FP64 oracle: 3D DFT, operator
+application and preconditioner, on seeded inputs at grids that span several tiles and
+ragged shapes."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2511_17107_amd as kc
+import workloads as W
+from oracle import kspace, yee
+
+from gpu_util import note, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SMALL_N = [4, 6, 8, 12, 16]
+KPTS = [(0.3, 0.5, 0.7), (0.0, 0.0, 0.0), (math.pi, math.pi, math.pi), (math.pi, 0.9, 0.0), (-1.2, 0.4, 2.1)]
+
+
+# ---------------------------------------------------------------- 3D DFT
+@pytest.mark.parametrize("N", [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128])
+@pytest.mark.parametrize("sign", [1, -1])
+def test_fft3d_fp64(N, sign):
+    import torch
+
+    nvec = 3 if N <= 32 else 1
+    note("fft3d fp64", N, sign)
+    a = W.random_block(100 + N, nvec, N)[:, 0, :]
+    x = to_dev(a)
+    y = to_host(kc.kc_fft3d(x, sign, kc.KC_PREC_FP64))
+    cube = a.reshape(nvec, N, N, N)
+    if N <= 8:
+        # direct DFT definition along each axis
+        ref = cube
+        for ax in (3, 2, 1):
+            ref = np.moveaxis(kspace.direct_dft(np.moveaxis(ref, ax, -1), sign), -1, ax)
+    else:
+        ref = np.fft.fftn(cube, axes=(1, 2, 3)) if sign < 0 else np.fft.ifftn(cube, axes=(1, 2, 3)) * N ** 3
+    ref = ref.reshape(nvec, -1)
+    assert rel_err(y, ref) < 1e-14 * math.log2(N) * 4
+    # in place
+    x2 = to_dev(a)
+    kc.kc_fft3d(x2, sign, kc.KC_PREC_FP64, out=x2)
+    assert rel_err(to_host(x2), ref) < 1e-14 * math.log2(N) * 4
+    del torch
+
+
+@pytest.mark.parametrize("N", [6, 16, 96, 128])
+def test_fft3d_fp32(N):
+    import torch
+
+    note("fft3d fp32", N)
+    a = W.random_block(200 + N, 1, N)[:, 0, :]
+    x = to_dev(a.astype(np.complex64))
+    y = to_host(kc.kc_fft3d(x, -1, kc.KC_PREC_FP32))
+    ref = np.fft.fftn(a.reshape(1, N, N, N), axes=(1, 2, 3)).reshape(1, -1)
+    assert rel_err(y, ref) < 3e-7 * math.log2(N)
+    del torch
+
+
+# ---------------------------------------------------------------- operator
+def _case(N, scheme_name, seed=0):
+    if scheme_name == "iso":
+        wl = W.sphere_isotropic(N=N)
+        return wl.ids, wl.table, "crossdof"
+    wl = W.sphere_anisotropic(N=N, nk=2, m=4, seed=seed)
+    # add a second inclusion with a gyrotropic tensor so all off-diagonals and complex
+    # entries are exercised, and material ids differ between the point sets
+    ids = W.sample_ids(N, [W.Sphere((0.5, 0.5, 0.5), 0.3, 1), W.Rod(2, (0.1, 0.2, 0.0), 0.17, 2)])
+    tab = np.concatenate([wl.table, W.eps_table([W.gyrotropic_eps(12.0, 0.5, 10.0)])[1:]])
+    return ids, tab, scheme_name
+
+
+@pytest.mark.parametrize("N", SMALL_N)
+@pytest.mark.parametrize("scheme", ["diagonal", "trivial", "crossdof", "iso"])
+def test_apply_fp64_matches_oracle(N, scheme):
+    ids, tab, sch = _case(N, scheme)
+    op = kc.Op(N, kc.SCHEMES[sch], ids, tab)
+    op.set_kpoints(np.array(KPTS))
+    nvec_per_k = 2
+    x = W.random_block(7 + N, nvec_per_k * len(KPTS), N)
+    note("apply fp64", N, scheme)
+    y = to_host(op.apply(to_dev(x), ik0=0, vecs_per_k=nvec_per_k))
+    for ik, k in enumerate(KPTS):
+        Op = yee.compensated_operator(N, k, ids, tab, sch)
+        ref = kspace.kspace_apply(Op, x[ik * nvec_per_k:(ik + 1) * nvec_per_k], N)
+        err = rel_err(y[ik * nvec_per_k:(ik + 1) * nvec_per_k], ref)
+        assert err < 1e-12, (k, err)
+
+
+@pytest.mark.parametrize("N", [8, 16])
+@pytest.mark.parametrize("scheme", ["trivial", "crossdof"])
+def test_apply_fp32_close_to_oracle(N, scheme):
+    ids, tab, sch = _case(N, scheme)
+    op = kc.Op(N, kc.SCHEMES[sch], ids, tab)
+    op.set_kpoints(np.array(KPTS[:2]))
+    x = W.random_block(3, 4, N)
+    note("apply fp32", N, scheme)
+    y = to_host(op.apply(to_dev(x), vecs_per_k=2, prec=kc.KC_PREC_FP32))
+    for ik, k in enumerate(KPTS[:2]):
+        Op = yee.compensated_operator(N, k, ids, tab, sch)
+        ref = kspace.kspace_apply(Op, x[2 * ik:2 * ik + 2], N)
+        assert rel_err(y[2 * ik:2 * ik + 2], ref) < 2e-6
+
+
+@pytest.mark.parametrize("N", [4, 8, 16])
+def test_precond_matches_oracle(N):
+    ids, tab, sch = _case(N, "crossdof")
+    op = kc.Op(N, kc.SCHEMES[sch], ids, tab)
+    op.set_kpoints(np.array(KPTS))
+    r = W.random_block(11, len(KPTS), N)
+    note("precond", N)
+    z = to_host(op.precond(to_dev(r), vecs_per_k=1))
+    g = op.gamma()
+    for ik, k in enumerate(KPTS):
+        assert g[ik] == pytest.approx(yee.gamma_rule(k), rel=1e-15)
+        ref = kspace.precond_apply(N, k, g[ik], r[ik:ik + 1])
+        assert rel_err(z[ik:ik + 1], ref) < 1e-13
+    # in place
+    rr = to_dev(r)
+    op.precond(rr, vecs_per_k=1, out=rr)
+    assert rel_err(to_host(rr)[0:1], kspace.precond_apply(N, KPTS[0], g[0], r[0:1])) < 1e-13
+
+
+@pytest.mark.parametrize("N", [32, 64, 128])
+def test_apply_homogeneous_closed_form_large(N):
+    """At full grid sizes: for a homogeneous anisotropic medium and the Trivial scheme,
+    F3^H M F3 = eps1 per frequency, so Op_p = K_A eps1 K_A^H + gamma conj(K) K^T is a 3x3
+    per-frequency map that the oracle symbols give independently of any FFT."""
+    eps = W.gyrotropic_eps(12.0, 0.5, 10.0)
+    ids = np.ones((4, N ** 3), dtype=np.uint8)
+    tab = W.eps_table([eps])
+    k = (0.4, -1.3, 2.2)
+    op = kc.Op(N, kc.KC_EPS_TRIVIAL, ids, tab)
+    op.set_kpoints(np.array([k]))
+    x = W.random_block(5, 1, N)
+    note("apply homogeneous", N)
+    y = to_host(op.apply(to_dev(x)))[0]
+    K = kspace.symbols_3d(N, k)
+    v = K.conj()
+    e1 = tab[1]
+    e = -np.cross(v.T, x[0].T).T
+    yy = np.cross(K.T, (e1 @ e).T).T + yee.gamma_rule(k) * v * (K * x[0]).sum(axis=0)[None, :]
+    assert rel_err(y, yy) < 1e-12
+
+
+@pytest.mark.parametrize("N", [32, 64])
+def test_apply_hermitian_positive(N):
+    """Properties at any size: <u, Op w> = <Op u, w> and <u, Op u> > 0 for k != 0 (Prop 2.5)."""
+    wl = W.sphere_anisotropic(N=N, nk=3, m=4)
+    op = kc.Op(N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(wl.kpoints[1:2])
+    uw = W.random_block(9, 2, N)
+    note("apply hermitian", N)
+    out = to_host(op.apply(to_dev(uw)))
+    a = np.vdot(uw[0], out[1])
+    b = np.vdot(out[0], uw[1])
+    assert abs(a - b) < 1e-12 * abs(a)
+    assert np.vdot(uw[0], out[0]).real > 0
