@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput benchmark: k-points per second to Res_j <= 1e-8 (eq (4.3)) for the simple-cubic
+woodpile of four rod layers (rod width 0.25a) with gyrotropic permittivity
+eps = [[12, 0.5i, 0], [-0.5i, 12, 0], [0, 0, 10]] at N = 128 (3 x 128^3 = 6.3M unknowns),
+CrossDoF inverse permittivity, 16 bands, 60 k-points on Gamma-X-M-Gamma-R, FP32 operator
+applications with FP64 orthogonalisation / Rayleigh-Ritz / residual checks.
+
+One step = one kc_solve of a batch of k-points (default 4, interleaved along the 60-point
+path so that consecutive steps walk the whole path).  Inputs (geometry, tables, k-points)
+are resident before the timed region; the solve allocates its block workspace once and
+reuses it.  Prints one JSON line (see the keys below).
+
+    python bench.py [--steps K] [--warmup W] [--kpb 4] [--prec fp32|fp64] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--kpb", type=int, default=4, help="k-points per step (one batched solve)")
+    ap.add_argument("--nk", type=int, default=60)
+    ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--m", type=int, default=16)
+    ap.add_argument("--guard", type=int, default=4)
+    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--switch-tol", type=float, default=3e-4)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=600)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", type=int, default=0)
+    return ap.parse_args()
+
+
+def pass_bytes(N, nvec, scheme_cross, tbytes):
+    """Algorithmic bytes of each pencil pass of one operator application: what the pass must
+    read and write once (complex128 input/output vectors, compute-precision intermediates,
+    4-byte packed material ids)."""
+    n3 = N ** 3
+    v64 = 16 * 3 * n3 * nvec
+    vt = tbytes * 3 * n3 * nvec
+    ids = 4 * n3 * nvec
+    if scheme_cross:
+        names = ["X1", "Y1", "Za", "Zb", "Y2", "X2"]
+        b = [v64 + vt, 2 * vt, 2 * vt, 2 * vt + ids, 2 * vt, vt + 2 * v64]
+    else:
+        names = ["X1", "Y1", "Z", "Y2", "X2"]
+        b = [v64 + vt, 2 * vt, 2 * vt + ids, 2 * vt, vt + 2 * v64]
+    return names, b
+
+
+def cpu_baseline(kpath):
+    """The oracle (explicit sparse operator + shift-invert Lanczos) on the same woodpile geometry
+    and k-path at the largest grid it solves in well under a minute (N = 16)."""
+    ncpu = min(len(os.sched_getaffinity(0)), 16)
+    os.environ["OPENBLAS_NUM_THREADS"] = str(ncpu)
+    try:
+        from threadpoolctl import threadpool_limits
+
+        threadpool_limits(limits=ncpu)
+    except Exception:
+        pass
+    import workloads as W
+    from oracle import eigs, yee
+
+    wl = W.woodpile_gyrotropic(N=16, nk=60, m=16)
+    ks = [kpath[7]]
+    t = time.time()
+    for k in ks:
+        Op = yee.compensated_operator(wl.N, k, wl.ids, wl.table, "crossdof")
+        eigs.smallest_positive(Op, 16, method="shift_invert")
+    dt = time.time() - t
+    return {"value": len(ks) / dt, "unit": "k-points/s", "cores": ncpu, "kind": "oracle",
+            "sample": "oracle shift-invert Lanczos on the explicit sparse operator, same woodpile/"
+                      "gyrotropic geometry and k-path, N=16 (3*16^3 unknowns), 16 bands, 1 k-point "
+                      "(%.1f s); the oracle cannot factor the N=128 operator" % dt}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X; --gpus %d is not "
+              "supported (k-points shard across GPUs with no communication; see DESIGN.md)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2511_17107_amd as kc
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = W.woodpile_gyrotropic(N=a.N, nk=a.nk, m=a.m)
+    op = kc.Op(wl.N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(wl.kpoints)
+    prec = kc.KC_PREC_FP32 if a.prec == "fp32" else kc.KC_PREC_FP64
+    nsteps_path = a.nk // a.kpb
+
+    # k-points reordered so that batch s holds path points s, s + P, s + 2P, ... (P = nk/kpb):
+    # consecutive steps walk the whole path, and each batch is a consecutive index range
+    order = np.concatenate([[(s + j * nsteps_path) for j in range(a.kpb)] for s in range(nsteps_path)])
+    op.set_kpoints(wl.kpoints[order])
+
+    def run_step(step):
+        ik0 = (step % nsteps_path) * a.kpb
+        eig, res, its, st = op.solve(a.m, ik0=ik0, nk=a.kpb, tol=a.tol, maxit=a.maxit, prec=prec,
+                                     switch_tol=a.switch_tol, batch_k=a.kpb, guard=a.guard,
+                                     verbose=a.verbose, check=True)
+        return ik0, eig, res, its, st, op.last_solve_stats()
+
+    for w in range(a.warmup):
+        run_step(nsteps_path - 1 - w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for s in range(a.steps):
+        results.append(run_step(s))
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    nkp = a.steps * a.kpb
+    converged = all(r[4] == 0 for r in results)
+    maxres = max(float(r[2].max()) for r in results)
+    iters = [int(i) for r in results for i in r[3]]
+    mv64 = sum(r[5][0] for r in results)
+    mv32 = sum(r[5][1] for r in results)
+
+    # per-pass roofline of the operator application on one block of 16 vectors
+    x = torch.randn((a.m, 3, a.N ** 3), dtype=torch.complex128, device=dev)
+    tbytes = 8 if prec == kc.KC_PREC_FP32 else 16
+    names, pbytes = pass_bytes(a.N, a.m, True, tbytes)
+    reps = 5
+    acc = np.zeros(len(names))
+    for r in range(reps + 1):
+        _, ms = op.apply_timed(x, prec=prec)
+        if r > 0:
+            acc += ms
+    ms = acc / reps
+    gbs = [pb / (t * 1e-3) / 1e9 for pb, t in zip(pbytes, ms)]
+    dom = int(np.argmax(ms))
+    mv_time = float(ms.sum())
+    alg_mv = (16 * 3 * a.N ** 3 * 2 + 4 * a.N ** 3) * a.m  # read x, write y, read ids
+    del x
+
+    out = {
+        "metric": "k-points/s to rel. residual 1e-8 at n=128, 16 bands; matvec GB/s vs HBM peak",
+        "value": nkp / T,
+        "unit": "k-points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * T / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 operator / f64 block" if prec == kc.KC_PREC_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "sc128-woodpile-gyrotropic-crossdof, 16 bands (+%d guard), "
+                               "%d k-points/step of the 60-point G-X-M-G-R path" % (a.guard, a.kpb),
+                   "N": a.N, "bands": a.m, "kpoints_per_step": a.kpb, "tol": a.tol,
+                   "precision": a.prec},
+        "converged": converged,
+        "max_residual": maxres,
+        "iterations": iters,
+        "matvecs_fp64": mv64,
+        "matvecs_fp32": mv32,
+        "roofline": {"bound": "hbm", "kernel": "matvec pass " + names[dom],
+                     "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs[dom] / HBM_PEAK_GBS, "traffic": None},
+        "matvec": {"passes": names, "ms": [round(float(t), 4) for t in ms],
+                   "alg_GBps": [round(g, 1) for g in gbs], "nvec": a.m,
+                   "ms_per_band": mv_time / a.m,
+                   "effective_GBps": alg_mv / (mv_time * 1e-3) / 1e9},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl.kpoints)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,6 +109,15 @@ int kc_apply(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* x, void* 
              void* stream);
 
 /*
+ * kc_apply with HIP events recorded on `stream` between its pencil passes (for measuring
+ * each pass): pass_ms_host float64 [6] receives the milliseconds of the passes in launch order
+ * (CrossDoF: X1, Y1, Za, Zb, Y2, X2; otherwise X1, Y1, Z, Y2, X2), *npass_host their count.
+ * Blocks until the application is complete.  Same arguments and errors as kc_apply.
+ */
+int kc_apply_timed(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* x, void* y, int prec,
+                   void* stream, double* pass_ms_host, int* npass_host);
+
+/*
  * z = K_P^{-1} r, the diagonal-block preconditioner of eqs (2.31)-(2.32), per frequency:
  * K_P = K_A K_A^H + gamma K_B.  Where K_P is singular (the DC frequency at k = 0, whose
  * modes are the constant fields of Prop 2.5) z is zero.  r, z: device complex128

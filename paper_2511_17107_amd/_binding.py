@@ -43,6 +43,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(lib_path):
             raise KcError(-1, "libkcpc.so is not built (run python -m paper_2511_17107_amd.build)")
+        # PyTorch ships its own HIP runtime with the same soname as the system one; loading torch
+        # first makes the library bind to that single runtime, so device pointers and streams
+        # from torch are valid in the library.
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(lib_path)
         vp, i32, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
         L.kc_supported_n.argtypes = [i32]
@@ -51,6 +56,7 @@ def lib():
         L.kc_get_gamma.argtypes = [vp, vp]
         L.kc_apply.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
         L.kc_precond.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+        L.kc_apply_timed.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp, vp, vp]
         L.kc_fft3d.argtypes = [i32, i32, i32, i32, vp, vp, vp]
         L.kc_solve_opts_default.argtypes = [ctypes.POINTER(KcSolveOpts)]
         L.kc_solve_opts_default.restype = None
@@ -163,6 +169,23 @@ class Op:
         _check(lib().kc_apply(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(x, "torch.complex128", "x"),
                               _dev_ptr(out, "torch.complex128", "y"), int(prec), _stream(stream)), "kc_apply")
         return out
+
+    def apply_timed(self, x, ik0: int = 0, vecs_per_k: Optional[int] = None, prec: int = KC_PREC_FP64,
+                    out=None, stream=None):
+        """kc_apply with per-pass HIP-event timings; returns (y, pass_ms)."""
+        import torch
+
+        nvec = x.shape[0]
+        if out is None:
+            out = torch.empty_like(x)
+        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        ms = np.zeros(6)
+        npass = ctypes.c_int(0)
+        _check(lib().kc_apply_timed(self._h, int(ik0), int(nvec), max(vpk, 1),
+                                    _dev_ptr(x, "torch.complex128", "x"), _dev_ptr(out, "torch.complex128", "y"),
+                                    int(prec), _stream(stream), ms.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.byref(npass)), "kc_apply_timed")
+        return out, ms[: npass.value]
 
     def precond(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, out=None, stream=None):
         import torch

@@ -1,0 +1,356 @@
+// Tall-skinny block kernels of the LOBPCG iteration on gfx950: complex Gram products on FP64
+// MFMA, in-place block updates on FP64 MFMA, the fused residual/preconditioner pass and the
+// seeded initial block.
+//
+// Block storage (per k-point b of a batch): column c of a block lives at base + (b*kstride + c)*n,
+// n = 3N^3 complex128 entries per column (one k-space vector, [3][N^3]).
+//
+// v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and holds D[l/16 + 4r][l%16], r = 0..3, afterwards.
+#include <algorithm>
+
+#include "kc_blas.h"
+
+namespace kc {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------------------------
+// Gram: G_b = A_b^H B_b (p x q complex), partial sums over row chunks.
+// Complex products on real MFMA: with a = ar + i ai, b = br + i bi,
+//   Re(conj(a) b) = ar br + ai bi,   Im(conj(a) b) = ar bi - ai br,
+// so each 16x16 tile over 4 rows is four real MFMAs whose A operands are the real and
+// imaginary parts of 4 rows of 16 A-columns and whose B operands are (br, bi) and (bi, -br).
+// Grid: x = row chunk (ksplit), y = tile block, z = k-point.  Each of the 4 waves of a
+// workgroup walks a contiguous quarter of the chunk and writes its own partial tile block.
+// ------------------------------------------------------------------------------------
+template <int TA, int TB>
+__global__ __launch_bounds__(256) void k_gram(const c64* __restrict__ A, const c64* __restrict__ B, size_t n,
+                                              int p, int q, int akstride, int acol0, int bkstride, int bcol0,
+                                              int ntb_b, int rows_per_chunk, c64* __restrict__ part,
+                                              const int* __restrict__ kskip) {
+  const int b = blockIdx.z;
+  if (kskip && kskip[b]) return;
+  const int chunk = blockIdx.x;
+  const int tbi = blockIdx.y / ntb_b, tbj = blockIdx.y % ntb_b;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const size_t r_begin = (size_t)chunk * rows_per_chunk;
+  const size_t r_end = std::min(n, r_begin + rows_per_chunk);
+  const size_t per_wave = ((size_t)rows_per_chunk / 4 + 3) & ~(size_t)3;
+  const size_t w_begin = std::min(r_end, r_begin + wave * per_wave);
+  const size_t w_end = std::min(r_end, w_begin + per_wave);
+
+  const c64* acol[TA];
+  const c64* bcol[TB];
+  bool aok[TA], bok[TB];
+#pragma unroll
+  for (int t = 0; t < TA; ++t) {
+    const int c = (tbi * TA + t) * 16 + li;
+    aok[t] = c < p;
+    acol[t] = A + ((size_t)b * akstride + acol0 + (aok[t] ? c : 0)) * n;
+  }
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    const int c = (tbj * TB + t) * 16 + li;
+    bok[t] = c < q;
+    bcol[t] = B + ((size_t)b * bkstride + bcol0 + (bok[t] ? c : 0)) * n;
+  }
+  d4 re[TA][TB], im[TA][TB];
+#pragma unroll
+  for (int i = 0; i < TA; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+      re[i][j] = d4{0, 0, 0, 0};
+      im[i][j] = d4{0, 0, 0, 0};
+    }
+  for (size_t r = w_begin; r < w_end; r += 4) {
+    const size_t row = r + lk;
+    const bool rok = row < w_end;
+    c64 av[TA], bv[TB];
+#pragma unroll
+    for (int t = 0; t < TA; ++t) av[t] = (rok && aok[t]) ? acol[t][row] : mk(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < TB; ++t) bv[t] = (rok && bok[t]) ? bcol[t][row] : mk(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < TA; ++i)
+#pragma unroll
+      for (int j = 0; j < TB; ++j) {
+        re[i][j] = mfma(av[i].re, bv[j].re, re[i][j]);
+        re[i][j] = mfma(av[i].im, bv[j].im, re[i][j]);
+        im[i][j] = mfma(av[i].re, bv[j].im, im[i][j]);
+        im[i][j] = mfma(av[i].im, -bv[j].re, im[i][j]);
+      }
+  }
+  // partial layout: [b][chunk*4 + wave][p][q]
+  const int nsplit = gridDim.x * 4;
+  c64* out = part + ((size_t)b * nsplit + (size_t)chunk * 4 + wave) * p * q;
+#pragma unroll
+  for (int i = 0; i < TA; ++i)
+#pragma unroll
+    for (int j = 0; j < TB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = (tbi * TA + i) * 16 + lk + 4 * r;
+        const int gj = (tbj * TB + j) * 16 + li;
+        if (gi < p && gj < q) out[(size_t)gi * q + gj] = mk(re[i][j][r], im[i][j][r]);
+      }
+}
+
+// G[b][i][j] = sum over splits, fixed order (deterministic)
+__global__ void k_gram_reduce(const c64* __restrict__ part, int nsplit, int pq, c64* __restrict__ G,
+                              const int* __restrict__ kskip) {
+  const int b = blockIdx.y;
+  if (kskip && kskip[b]) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= pq) return;
+  const c64* src = part + (size_t)b * nsplit * pq + e;
+  double sr = 0.0, si = 0.0;
+  for (int s = 0; s < nsplit; ++s) {
+    const c64 v = src[(size_t)s * pq];
+    sr += v.re;
+    si += v.im;
+  }
+  G[(size_t)b * pq + e] = mk(sr, si);
+}
+
+// ------------------------------------------------------------------------------------
+// Update: Y_b[:, map(j)] = sum_c S_b[:, c] C_b[c][j], j < q, in place (Y may be S).
+// Computed transposed, D = C^T S^T: the B operand lanes read 16 consecutive rows of one
+// column (coalesced), the output lanes hold 16 consecutive rows of one output column.
+// Re(Y) = Cr Sr - Ci Si, Im(Y) = Cr Si + Ci Sr.  Output column j goes to column
+// (j < q1 ? ycol0 + j : ycol1 + j - q1).  Each wave owns 16 rows at a time, so all reads of
+// its rows happen before its writes and other waves never touch them.
+// ------------------------------------------------------------------------------------
+template <int TQ>
+__global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64* __restrict__ C, size_t n,
+                                                int p, int q, int skstride, int scol0, int ykstride, int q1,
+                                                int ycol0, int ycol1, const int* __restrict__ kskip) {
+  extern __shared__ c64 csh[];  // C_b, p x q
+  const int b = blockIdx.y;
+  if (kskip && kskip[b]) return;
+  const c64* Cb = C + (size_t)b * p * q;
+  for (int t = threadIdx.x; t < p * q; t += blockDim.x) csh[t] = Cb[t];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const c64* Sb = S + ((size_t)b * skstride + scol0) * n;
+  c64* Yb = Y + (size_t)b * ykstride * n;
+  const size_t nblk = (n + 15) / 16;
+  const int pk = (p + 3) / 4;
+  for (size_t rb = (size_t)blockIdx.x * 4 + wave; rb < nblk; rb += (size_t)gridDim.x * 4) {
+    const size_t row = rb * 16 + li;
+    const bool rok = row < n;
+    d4 re[TQ], im[TQ];
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) {
+      re[t] = d4{0, 0, 0, 0};
+      im[t] = d4{0, 0, 0, 0};
+    }
+    for (int kb = 0; kb < pk; ++kb) {
+      const int c = kb * 4 + lk;
+      const c64 s = (rok && c < p) ? Sb[(size_t)c * n + row] : mk(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < TQ; ++t) {
+        const int j = t * 16 + li;
+        const int ca = kb * 4 + lk;
+        const c64 cv = (ca < p && j < q) ? csh[ca * q + j] : mk(0.0, 0.0);
+        // A operand lane (i = li -> output column, k = lk -> input column): C[k][i]
+        // B operand lane (k = lk -> input column, j = li -> row): S[row][k]
+        // both use lane index li for their 16-wide dimension, lk for k.
+        re[t] = mfma(cv.re, s.re, re[t]);
+        re[t] = mfma(-cv.im, s.im, re[t]);
+        im[t] = mfma(cv.re, s.im, im[t]);
+        im[t] = mfma(cv.im, s.re, im[t]);
+      }
+    }
+    // output lane holds D[lk + 4r][li]: output column t*16 + lk + 4r, row rb*16 + li
+#pragma unroll
+    for (int t = 0; t < TQ; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = t * 16 + lk + 4 * r;
+        if (rok && j < q) {
+          const int col = (j < q1) ? ycol0 + j : ycol1 + (j - q1);
+          Yb[(size_t)col * n + row] = mk(re[t][r], im[t][r]);
+        }
+      }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Residual + preconditioner: r_j = AX_j - theta_j X_j, W_j = K_P^{-1} r_j (closed form of
+// the diagonal-block preconditioner, eqs (2.31)-(2.32)), per-block partial sums of |r_j|^2
+// and |x_j|^2.  Grid: x = blocks per vector, y = column j, z = k-point b.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S, const c64* __restrict__ AS,
+                                                       c64* __restrict__ Wout, const double* __restrict__ theta,
+                                                       const c64* __restrict__ ktab64,
+                                                       const double* __restrict__ gamma, int N, int kstride,
+                                                       int xcol0, int wcol0, int mb, double* __restrict__ part,
+                                                       const int* __restrict__ kskip) {
+  const int b = blockIdx.z, j = blockIdx.y;
+  if (kskip && kskip[b]) return;
+  const size_t N3 = (size_t)N * N * N, n = 3 * N3;
+  const c64* x = S + ((size_t)b * kstride + xcol0 + j) * n;
+  const c64* ax = AS + ((size_t)b * kstride + xcol0 + j) * n;
+  c64* w = Wout + ((size_t)b * kstride + wcol0 + j) * n;
+  const double th = theta[b * mb + j];
+  const c64* K = ktab64 + (size_t)b * 3 * N;
+  const double g = gamma[b];
+  double rr = 0.0, xx = 0.0;
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N3; p += (size_t)gridDim.x * blockDim.x) {
+    const int qx = (int)(p % N), qy = (int)((p / N) % N), qz = (int)(p / ((size_t)N * N));
+    const c64 K1 = K[qx], K2 = K[N + qy], K3 = K[2 * N + qz];
+    const c64 x1 = x[p], x2 = x[N3 + p], x3 = x[2 * N3 + p];
+    const c64 r1 = ax[p] - th * x1, r2 = ax[N3 + p] - th * x2, r3 = ax[2 * N3 + p] - th * x3;
+    rr += abs2(r1) + abs2(r2) + abs2(r3);
+    xx += abs2(x1) + abs2(x2) + abs2(x3);
+    const double s = abs2(K1) + abs2(K2) + abs2(K3);
+    if (s == 0.0) {
+      w[p] = mk(0.0, 0.0);
+      w[N3 + p] = mk(0.0, 0.0);
+      w[2 * N3 + p] = mk(0.0, 0.0);
+    } else {
+      const double is = 1.0 / s;
+      const c64 u = ((1.0 / g - 1.0) * is * is) * (K1 * r1 + K2 * r2 + K3 * r3);
+      w[p] = is * r1 + cmulc(K1, u);
+      w[N3 + p] = is * r2 + cmulc(K2, u);
+      w[2 * N3 + p] = is * r3 + cmulc(K3, u);
+    }
+  }
+  // block reduction (fixed order)
+  __shared__ double sr[256], sx[256];
+  sr[threadIdx.x] = rr;
+  sx[threadIdx.x] = xx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sr[threadIdx.x] += sr[threadIdx.x + o];
+      sx[threadIdx.x] += sx[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* o = part + (((size_t)b * mb + j) * gridDim.x + blockIdx.x) * 2;
+    o[0] = sr[0];
+    o[1] = sx[0];
+  }
+}
+
+__global__ void k_resid_reduce(const double* __restrict__ part, int nblk, int nvec, double* __restrict__ res,
+                               double* __restrict__ xnorm2) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nvec) return;
+  double a = 0.0, c = 0.0;
+  for (int i = 0; i < nblk; ++i) {
+    a += part[((size_t)v * nblk + i) * 2];
+    c += part[((size_t)v * nblk + i) * 2 + 1];
+  }
+  res[v] = (c > 0.0) ? sqrt(a / c) : 0.0;
+  if (xnorm2) xnorm2[v] = c;
+}
+
+// ------------------------------------------------------------------------------------
+// Seeded initial block: entries uniform in [-1/2, 1/2) (real and imaginary parts) from a
+// counter-based generator (the splitmix64 finaliser applied to a unique 64-bit counter).
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_random_block(c64* S, size_t n, int kstride, int col0, int ncol, uint64_t seed,
+                               const int* __restrict__ kglobal) {
+  const int b = blockIdx.z, j = blockIdx.y;
+  if (j >= ncol) return;
+  c64* v = S + ((size_t)b * kstride + col0 + j) * n;
+  const uint64_t base = mix64(seed ^ mix64(((uint64_t)kglobal[b] << 20) ^ (uint64_t)j));
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (size_t)gridDim.x * blockDim.x) {
+    const uint64_t h = mix64(base + 2 * p), g = mix64(base + 2 * p + 1);
+    const double r = (double)(h >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    const double i = (double)(g >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    v[p] = mk(r, i);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// host launchers
+// ------------------------------------------------------------------------------------
+int gram(const c64* A, int akstride, int acol0, int p, const c64* B, int bkstride, int bcol0, int q, size_t n,
+         int nb, DevBuf& part, c64* G, const int* kskip, hipStream_t s) {
+  // row chunk so that the grid has a few thousand waves in total
+  constexpr int TA = 3, TB = 3;
+  const int ntb_a = (p + 16 * TA - 1) / (16 * TA);
+  const int ntb_b = (q + 16 * TB - 1) / (16 * TB);
+  const size_t target_wg = 2048;
+  size_t per_tile_wg = std::max<size_t>(1, target_wg / ((size_t)nb * ntb_a * ntb_b));
+  size_t rows = (n + per_tile_wg - 1) / per_tile_wg;
+  rows = std::max<size_t>(rows, 256);
+  rows = (rows + 15) & ~(size_t)15;
+  const int ksplit = (int)((n + rows - 1) / rows);
+  const int nsplit = ksplit * 4;
+  KC_TRY(part.ensure((size_t)nb * nsplit * p * q * sizeof(c64)));
+  dim3 grid(ksplit, ntb_a * ntb_b, nb);
+  k_gram<TA, TB><<<grid, 256, 0, s>>>(A, B, n, p, q, akstride, acol0, bkstride, bcol0, ntb_b, (int)rows,
+                                      part.as<c64>(), kskip);
+  KC_LAUNCHED();
+  const int pq = p * q;
+  dim3 g2((pq + 255) / 256, nb);
+  k_gram_reduce<<<g2, 256, 0, s>>>(part.as<c64>(), nsplit, pq, G, kskip);
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, int q, int q1, int ycol0,
+           int ycol1, const c64* C, size_t n, int nb, const int* kskip, hipStream_t s) {
+  const size_t nblk = (n + 15) / 16;
+  const unsigned gx = (unsigned)std::max<size_t>(1, std::min<size_t>((nblk + 3) / 4, 4096 / std::max(nb, 1) + 1));
+  dim3 grid(gx, nb);
+  const size_t shm = (size_t)p * q * sizeof(c64);
+  if (q <= 16) {
+    k_update<1><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, kskip);
+  } else if (q <= 32) {
+    k_update<2><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, kskip);
+  } else if (q <= 48) {
+    k_update<3><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, kskip);
+  } else {
+    set_error("update: too many output columns");
+    return KC_ERR_INVALID_ARG;
+  }
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
+                  const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
+                  double* res, double* xnorm2, const int* kskip, hipStream_t s) {
+  const size_t N3 = (size_t)N * N * N;
+  const int nblk = (int)std::max<size_t>(1, std::min<size_t>((N3 + 255) / 256, 256));
+  KC_TRY(part.ensure((size_t)nb * mb * nblk * 2 * sizeof(double)));
+  dim3 grid(nblk, mb, nb);
+  k_resid_precond<<<grid, 256, 0, s>>>(S, AS, W, theta, ktab64, gamma, N, kstride, xcol0, wcol0, mb,
+                                       part.as<double>(), kskip);
+  KC_LAUNCHED();
+  const int nv = nb * mb;
+  k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2);
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+int random_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, uint64_t seed, const int* kglobal,
+                 hipStream_t s) {
+  const unsigned gx = (unsigned)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 1024));
+  dim3 grid(gx, ncol, nb);
+  k_random_block<<<grid, 256, 0, s>>>(S, n, kstride, col0, ncol, seed, kglobal);
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+}  // namespace kc

@@ -259,7 +259,41 @@ int kc_apply(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* x, void* 
   if (nvec == 0) return KC_OK;
   KC_ARG(x != nullptr && y != nullptr && x != y, "x, y must be distinct device buffers");
   KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
-  return apply_op(op, ik0, nvec, vecs_per_k, (const c64*)x, (c64*)y, prec, (hipStream_t)stream);
+  VecMap vm;
+  vm.vpk = vecs_per_k;
+  vm.kstride = vecs_per_k;
+  return apply_op(op, ik0, nvec, vm, (const c64*)x, (c64*)y, prec, (hipStream_t)stream);
+}
+
+int kc_apply_timed(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* x, void* y, int prec, void* stream,
+                   double* pass_ms_host, int* npass_host) {
+  KC_ARG(op != nullptr && pass_ms_host != nullptr && npass_host != nullptr, "NULL argument");
+  KC_ARG(op->nk > 0 && nvec >= 1 && vecs_per_k >= 1, "nvec >= 1, vecs_per_k >= 1, k-points set");
+  KC_ARG(prec == KC_PREC_FP64 || prec == KC_PREC_FP32, "prec");
+  KC_ARG(x != nullptr && y != nullptr && x != y, "x, y must be distinct device buffers");
+  KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
+  const int np = (op->scheme == KC_EPS_CROSSDOF) ? 6 : 5;
+  hipEvent_t ev[7];
+  for (int i = 0; i <= np; ++i) KC_HIP(hipEventCreate(&ev[i]));
+  VecMap vm;
+  vm.vpk = vecs_per_k;
+  vm.kstride = vecs_per_k;
+  int st = apply_op(op, ik0, nvec, vm, (const c64*)x, (c64*)y, prec, (hipStream_t)stream, ev);
+  if (st == KC_OK) {
+    hipError_t e = hipEventSynchronize(ev[np]);
+    for (int i = 0; i < np && e == hipSuccess; ++i) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+      pass_ms_host[i] = ms;
+    }
+    if (e != hipSuccess) {
+      set_error(std::string("event timing: ") + hipGetErrorString(e));
+      st = KC_ERR_HIP;
+    }
+    *npass_host = np;
+  }
+  for (int i = 0; i <= np; ++i) (void)hipEventDestroy(ev[i]);
+  return st;
 }
 
 int kc_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z, void* stream) {

@@ -45,7 +45,7 @@ __device__ __forceinline__ void load_eps_table(EpsEntry<T>* lt, const EpsEntry<T
 // ------------------------------------------------------------------------------------
 template <int N, typename T>
 __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, cpx<T>* __restrict__ E,
-                                                    const cpx<T>* __restrict__ ktab, int vecs_per_k,
+                                                    const cpx<T>* __restrict__ ktab, VecMap vm,
                                                     const cpx<T>* __restrict__ gtw) {
   constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
@@ -57,9 +57,10 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
   b /= (N / P);
   const int z = b % N;
   const int vec = b / N;
-  const cpx<T>* K = ktab + (size_t)(vec / vecs_per_k) * 3 * N;
+  if (!vm.on(vec)) return;
+  const cpx<T>* K = ktab + (size_t)(vec / vm.vpk) * 3 * N;
   load_twiddles<N>(tw, gtw);
-  const c64* xv = x + (size_t)vec * 3 * N3;
+  const c64* xv = x + vm.off(vec) * 3 * N3;
   const cpx<T> v3 = conj(K[2 * N + z]);
   for (int w = threadIdx.x; w < N * P; w += NT) {
     const int e = w % N, p = w / N, y = yt * P + p;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
                                                         const cpx<T>* __restrict__ ktab,
                                                         const c64* __restrict__ ktab64,
                                                         const double* __restrict__ gamma,
-                                                        int vecs_per_k, const cpx<T>* __restrict__ gtw) {
+                                                        VecMap vm, const cpx<T>* __restrict__ gtw) {
   constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
@@ -99,7 +100,8 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
   b /= (N / P);
   const int z = b % N;
   const int vec = b / N;
-  const int ik = vec / vecs_per_k;
+  if (!vm.on(vec)) return;
+  const int ik = vec / vm.vpk;
   const cpx<T>* K = ktab + (size_t)ik * 3 * N;
   const c64* Kd = ktab64 + (size_t)ik * 3 * N;
   const double g = gamma[ik];
@@ -111,8 +113,8 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
   }
   __syncthreads();
   fft_tile<N, P, 3, NT, -1, T>(lds, tw);
-  const c64* xv = x + (size_t)vec * 3 * N3;
-  c64* yv = y + (size_t)vec * 3 * N3;
+  const c64* xv = x + vm.off(vec) * 3 * N3;
+  c64* yv = y + vm.off(vec) * 3 * N3;
   const cpx<T> K3 = K[2 * N + z];
   const c64 K3d = Kd[2 * N + z];
   for (int w = threadIdx.x; w < N * P; w += NT) {
@@ -137,7 +139,8 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
 // Y: DFT along y, in place.  Tile: P consecutive x of one (vec*3+c, z).
 // ------------------------------------------------------------------------------------
 template <int N, int DIR, typename T>
-__global__ __launch_bounds__(NT) void k_y(cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ gtw) {
+__global__ __launch_bounds__(NT) void k_y(cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ gtw,
+                                          const int* __restrict__ active) {
   constexpr int P = TileP<N, 1, T>::P;
   using G = TileGeom<N, P, 1>;
   __shared__ cpx<T> lds[G::ELEMS];
@@ -148,6 +151,7 @@ __global__ __launch_bounds__(NT) void k_y(cpx<T>* __restrict__ buf, const cpx<T>
   b /= (N / P);
   const int z = b % N;
   const size_t vc = b / N;
+  if (active && !active[vc / 3]) return;
   load_twiddles<N>(tw, gtw);
   cpx<T>* base = buf + vc * N3 + (size_t)z * N * N + xt * P;
   for (int w = threadIdx.x; w < N * P; w += NT) {
@@ -195,7 +199,8 @@ __global__ __launch_bounds__(NT) void k_x_plain(const cpx<T>* in, cpx<T>* out, c
 // Z (plain): DFT along z, in -> out (may alias).  Tile: P consecutive x of one (vc, y).
 // ------------------------------------------------------------------------------------
 template <int N, int DIR, typename T>
-__global__ __launch_bounds__(NT) void k_z_plain(const cpx<T>* in, cpx<T>* out, const cpx<T>* __restrict__ gtw) {
+__global__ __launch_bounds__(NT) void k_z_plain(const cpx<T>* in, cpx<T>* out, const cpx<T>* __restrict__ gtw,
+                                                const int* __restrict__ active, int ncomp) {
   constexpr int P = TileP<N, 1, T>::P;
   using G = TileGeom<N, P, 1>;
   __shared__ cpx<T> lds[G::ELEMS];
@@ -206,6 +211,7 @@ __global__ __launch_bounds__(NT) void k_z_plain(const cpx<T>* in, cpx<T>* out, c
   b /= (N / P);
   const int yy = b % N;
   const size_t vc = b / N;
+  if (active && !active[vc / ncomp]) return;
   load_twiddles<N>(tw, gtw);
   const size_t base = vc * N3 + (size_t)yy * N + xt * P;
   for (int w = threadIdx.x; w < N * P; w += NT) {
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_z_plain(const cpx<T>* in, cpx<T>* out, c
 template <int N, typename T>
 __global__ __launch_bounds__(NT) void k_z_trivial(cpx<T>* __restrict__ buf, const uint32_t* __restrict__ ids,
                                                   const EpsEntry<T>* __restrict__ geps, int n_mat,
-                                                  const cpx<T>* __restrict__ gtw) {
+                                                  const cpx<T>* __restrict__ gtw, const int* __restrict__ active) {
   constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
@@ -240,6 +246,7 @@ __global__ __launch_bounds__(NT) void k_z_trivial(cpx<T>* __restrict__ buf, cons
   b /= (N / P);
   const int yy = b % N;
   const size_t vec = b / N;
+  if (active && !active[vec]) return;
   load_twiddles<N>(tw, gtw);
   load_eps_table(eps, geps, n_mat);
   cpx<T>* base = buf + vec * 3 * N3 + (size_t)yy * N + xt * P;
@@ -358,7 +365,7 @@ template <int N, typename T>
 __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E, cpx<T>* __restrict__ out,
                                                     const uint32_t* __restrict__ ids,
                                                     const EpsEntry<T>* __restrict__ geps, int n_mat,
-                                                    const cpx<T>* __restrict__ gtw) {
+                                                    const cpx<T>* __restrict__ gtw, const int* __restrict__ active) {
   constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
@@ -371,6 +378,7 @@ __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E
   b /= (N / P);
   const int yy = b % N;
   const size_t vec = b / N;
+  if (active && !active[vec]) return;
   load_twiddles<N>(tw, gtw);
   load_eps_table(eps, geps, n_mat);
   __syncthreads();
@@ -441,7 +449,13 @@ __global__ __launch_bounds__(NT) void k_precond(const c64* r, c64* z, const c64*
 static inline unsigned nblk(size_t n) { return (unsigned)n; }
 
 template <int N, typename T>
-static int apply_n(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* x, c64* y, hipStream_t s) {
+static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x, c64* y, hipStream_t s,
+                   hipEvent_t* ev) {
+  int nev = 0;
+  auto mark = [&]() -> int {
+    if (ev) KC_HIP(hipEventRecord(ev[nev++], s));
+    return KC_OK;
+  };
   constexpr size_t N3 = (size_t)N * N * N;
   const size_t nbuf = (size_t)nvec * 3 * N3 * sizeof(cpx<T>);
   KC_TRY(op->work_a.ensure(nbuf));
@@ -457,25 +471,33 @@ static int apply_n(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* x, c
   constexpr int P1 = TileP<N, 1, T>::P;
   const unsigned g3 = nblk((size_t)nvec * N * (N / P3));
   const unsigned g1 = nblk((size_t)nvec * 3 * N * (N / P1));
-  k_x1_curl_inv<N, T><<<g3, NT, 0, s>>>(x, A, ktab, vecs_per_k, tw);
+  const int* act = vm.active;
+  if (op->scheme == KC_EPS_CROSSDOF) KC_TRY(op->work_b.ensure(nbuf));
+  KC_TRY(mark());
+  k_x1_curl_inv<N, T><<<g3, NT, 0, s>>>(x, A, ktab, vm, tw);
   KC_LAUNCHED();
-  k_y<N, +1, T><<<g1, NT, 0, s>>>(A, tw);
+  KC_TRY(mark());
+  k_y<N, +1, T><<<g1, NT, 0, s>>>(A, tw, act);
   KC_LAUNCHED();
+  KC_TRY(mark());
   if (op->scheme == KC_EPS_CROSSDOF) {
-    KC_TRY(op->work_b.ensure(nbuf));
     cpx<T>* B = op->work_b.as<cpx<T>>();
-    k_z_plain<N, +1, T><<<g1, NT, 0, s>>>(A, B, tw);
+    k_z_plain<N, +1, T><<<g1, NT, 0, s>>>(A, B, tw, act, 3);
     KC_LAUNCHED();
-    k_zb_crossdof<N, T><<<g3, NT, 0, s>>>(B, A, ids, eps, op->n_mat, tw);
+    KC_TRY(mark());
+    k_zb_crossdof<N, T><<<g3, NT, 0, s>>>(B, A, ids, eps, op->n_mat, tw, act);
     KC_LAUNCHED();
   } else {
-    k_z_trivial<N, T><<<g3, NT, 0, s>>>(A, ids, eps, op->n_mat, tw);
+    k_z_trivial<N, T><<<g3, NT, 0, s>>>(A, ids, eps, op->n_mat, tw, act);
     KC_LAUNCHED();
   }
-  k_y<N, -1, T><<<g1, NT, 0, s>>>(A, tw);
+  KC_TRY(mark());
+  k_y<N, -1, T><<<g1, NT, 0, s>>>(A, tw, act);
   KC_LAUNCHED();
-  k_x2_fwd_curl_pen<N, T><<<g3, NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vecs_per_k, tw);
+  KC_TRY(mark());
+  k_x2_fwd_curl_pen<N, T><<<g3, NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, tw);
   KC_LAUNCHED();
+  KC_TRY(mark());
   return KC_OK;
 }
 
@@ -486,16 +508,16 @@ static int fft3d_n(int nvec, int sign, const cpx<T>* in, cpx<T>* out, const cpx<
   if (sign > 0) {
     k_x_plain<N, +1, T><<<g1, NT, 0, s>>>(in, out, tw);
     KC_LAUNCHED();
-    k_y<N, +1, T><<<g1, NT, 0, s>>>(out, tw);
+    k_y<N, +1, T><<<g1, NT, 0, s>>>(out, tw, nullptr);
     KC_LAUNCHED();
-    k_z_plain<N, +1, T><<<g1, NT, 0, s>>>(out, out, tw);
+    k_z_plain<N, +1, T><<<g1, NT, 0, s>>>(out, out, tw, nullptr, 1);
     KC_LAUNCHED();
   } else {
     k_x_plain<N, -1, T><<<g1, NT, 0, s>>>(in, out, tw);
     KC_LAUNCHED();
-    k_y<N, -1, T><<<g1, NT, 0, s>>>(out, tw);
+    k_y<N, -1, T><<<g1, NT, 0, s>>>(out, tw, nullptr);
     KC_LAUNCHED();
-    k_z_plain<N, -1, T><<<g1, NT, 0, s>>>(out, out, tw);
+    k_z_plain<N, -1, T><<<g1, NT, 0, s>>>(out, out, tw, nullptr, 1);
     KC_LAUNCHED();
   }
   return KC_OK;
@@ -517,12 +539,13 @@ static int fft3d_n(int nvec, int sign, const cpx<T>* in, cpx<T>* out, const cpx<
     default: break;                                   \
   }
 
-int apply_op(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* x, c64* y, int prec, hipStream_t s) {
+int apply_op(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x, c64* y, int prec, hipStream_t s,
+             hipEvent_t* ev) {
   if (nvec == 0) return KC_OK;
   if (prec == KC_PREC_FP64) {
-    KC_DISPATCH_N(op->N, (apply_n<NN, double>(op, ik0, nvec, vecs_per_k, x, y, s)))
+    KC_DISPATCH_N(op->N, (apply_n<NN, double>(op, ik0, nvec, vm, x, y, s, ev)))
   } else {
-    KC_DISPATCH_N(op->N, (apply_n<NN, float>(op, ik0, nvec, vecs_per_k, x, y, s)))
+    KC_DISPATCH_N(op->N, (apply_n<NN, float>(op, ik0, nvec, vm, x, y, s, ev)))
   }
   set_error("unsupported N");
   return KC_ERR_UNSUPPORTED;

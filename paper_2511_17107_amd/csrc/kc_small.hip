@@ -1,0 +1,515 @@
+// Small dense steps of the LOBPCG iteration, one workgroup (256 threads) per k-point, all in
+// LDS and FP64: masked Cholesky, triangular solves, cyclic Jacobi for complex Hermitian
+// matrices with a parallel (round-robin) pair ordering, Ritz-vector selection and the
+// construction of the next search direction P orthogonal to the new Ritz vectors.
+//
+// Columns of S = [X W P] can be inactive (soft-locked bands, dropped directions, or no P yet):
+// an inactive column is replaced by the identity in the Gram matrix GB and by an isolated
+// diagonal entry above the active spectrum in GA, so it never enters the selected Ritz
+// vectors and its coefficients are zero.
+#include <algorithm>
+#include <cmath>
+
+#include "kc_blas.h"
+
+namespace kc {
+
+constexpr int LD = RR_NMAX;  // leading dimension of LDS matrices
+
+// In-place right-looking Cholesky A = L L^H (lower triangle, leading dimension LD) of the
+// Hermitian n x n matrix.  A column whose pivot is not above tol * diag0[j] (or is not
+// finite) is dropped: its row and column of L become the identity, act[j] = 0, and if it is
+// `protect`ed the breakdown flag is raised.  The factor then belongs to the matrix with that
+// row and column replaced by the identity.
+__device__ void chol_masked(c64* A, int n, int* act, const double* diag0, double tol, const int* protect,
+                            int* breakdown) {
+  __shared__ double piv;
+  __shared__ int fail;
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = A[j * LD + j].re;
+      const bool ok = act[j] && (d > tol * diag0[j]) && std::isfinite(d);
+      fail = !ok;
+      piv = ok ? sqrt(d) : 1.0;
+      if (!ok && act[j]) {
+        act[j] = 0;
+        if (protect && protect[j]) *breakdown = 1;
+      }
+    }
+    __syncthreads();
+    if (fail) {
+      for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        if (t < j) A[j * LD + t] = mk(0.0, 0.0);
+        if (t > j) A[t * LD + j] = mk(0.0, 0.0);
+      }
+      if (threadIdx.x == 0) A[j * LD + j] = mk(1.0, 0.0);
+      __syncthreads();
+      continue;
+    }
+    const double ip = 1.0 / piv;
+    for (int t = j + 1 + threadIdx.x; t < n; t += blockDim.x) A[t * LD + j] = ip * A[t * LD + j];
+    if (threadIdx.x == 0) A[j * LD + j] = mk(piv, 0.0);
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) A[i * LD + k] = A[i * LD + k] - A[i * LD + j] * conj(A[k * LD + j]);
+    }
+    __syncthreads();
+  }
+}
+
+// B <- L^{-1} B for an n x ncol matrix B (leading dimension ldb), L lower (LD).
+__device__ void trsm_lower(const c64* L, int n, c64* B, int ldb, int ncol) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      c64 s = B[i * ldb + c];
+      for (int k = 0; k < i; ++k) s = s - L[i * LD + k] * B[k * ldb + c];
+      B[i * ldb + c] = (1.0 / L[i * LD + i].re) * s;
+    }
+  }
+  __syncthreads();
+}
+
+// B <- L^{-H} B (back substitution with L^H).
+__device__ void trsm_lower_h(const c64* L, int n, c64* B, int ldb, int ncol) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    for (int i = n - 1; i >= 0; --i) {
+      c64 s = B[i * ldb + c];
+      for (int k = i + 1; k < n; ++k) s = s - conj(L[k * LD + i]) * B[k * ldb + c];
+      B[i * ldb + c] = (1.0 / L[i * LD + i].re) * s;
+    }
+  }
+  __syncthreads();
+}
+
+// in-place conjugate transpose of an n x n LDS matrix (LD)
+__device__ void conj_transpose(c64* A, int n) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    if (i < j) {
+      const c64 a = A[i * LD + j], b = A[j * LD + i];
+      A[i * LD + j] = conj(b);
+      A[j * LD + i] = conj(a);
+    } else if (i == j) {
+      A[i * LD + i] = mk(A[i * LD + i].re, -A[i * LD + i].im);
+    }
+  }
+  __syncthreads();
+}
+
+// Cyclic Jacobi for the Hermitian n x n matrix A (LD), accumulating V <- V J.  A rotation of
+// the pair (p, q) with a_pq = |a_pq| u, tau = (a_qq - a_pp)/(2|a_pq|),
+// t = sign(tau)/(|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c, uses
+// J = [[c, s u], [-s conj(u), c]] on the (p, q) plane and annihilates a_pq.  Pairs come from
+// the round-robin schedule (n-1 rounds of n/2 disjoint pairs per sweep); rotations with
+// |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) are skipped and sweeps stop when none is applied.
+__device__ void jacobi(c64* A, c64* V, int n) {
+  __shared__ int pp[LD / 2], qq[LD / 2];
+  __shared__ double cc[LD / 2], ss[LD / 2];
+  __shared__ c64 uu[LD / 2];
+  __shared__ int nrot;
+  const int ne = (n + 1) & ~1;  // even number of players (index n is a dummy when n is odd)
+  const int half = ne / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) nrot = 0;
+    __syncthreads();
+    for (int r = 0; r < ne - 1; ++r) {
+      // circle method: player ne-1 fixed, pairs (r, ne-1) and ((r+k) mod (ne-1), (r-k) mod (ne-1))
+      for (int k = threadIdx.x; k < half; k += blockDim.x) {
+        int a, b;
+        if (k == 0) {
+          a = r;
+          b = ne - 1;
+        } else {
+          a = (r + k) % (ne - 1);
+          b = (r - k + (ne - 1)) % (ne - 1);
+        }
+        int p = min(a, b), q = max(a, b);
+        double c = 1.0, s = 0.0;
+        c64 u = mk(1.0, 0.0);
+        if (q < n) {
+          const c64 apq = A[p * LD + q];
+          const double g = sqrt(abs2(apq));
+          const double app = A[p * LD + p].re, aqq = A[q * LD + q].re;
+          if (g > 1e-300 && g > 1e-15 * sqrt(fabs(app * aqq))) {
+            const double tau = (aqq - app) / (2.0 * g);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+            u = mk(apq.re / g, apq.im / g);
+            atomicAdd(&nrot, 1);
+          } else {
+            q = n;  // mark as no-op
+          }
+        }
+        pp[k] = p;
+        qq[k] = q;
+        cc[k] = c;
+        ss[k] = s;
+        uu[k] = u;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int e = threadIdx.x; e < half * n; e += blockDim.x) {
+        const int k = e / n, i = e % n;
+        const int p = pp[k], q = qq[k];
+        if (q >= n) continue;
+        const double c = cc[k], s = ss[k];
+        const c64 u = uu[k];
+        const c64 ap = A[i * LD + p], aq = A[i * LD + q];
+        A[i * LD + p] = c * ap - s * cmulc(u, aq);  // c a_p - s conj(u) a_q
+        A[i * LD + q] = s * (u * ap) + c * aq;
+        const c64 vp = V[i * LD + p], vq = V[i * LD + q];
+        V[i * LD + p] = c * vp - s * cmulc(u, vq);
+        V[i * LD + q] = s * (u * vp) + c * vq;
+      }
+      __syncthreads();
+      // rows: A <- J^H A, J^H = [[c, -s u], [s conj(u), c]]
+      for (int e = threadIdx.x; e < half * n; e += blockDim.x) {
+        const int k = e / n, j = e % n;
+        const int p = pp[k], q = qq[k];
+        if (q >= n) continue;
+        const double c = cc[k], s = ss[k];
+        const c64 u = uu[k];
+        const c64 ap = A[p * LD + j], aq = A[q * LD + j];
+        A[p * LD + j] = c * ap - s * (u * aq);
+        A[q * LD + j] = s * cmulc(u, ap) + c * aq;
+      }
+      __syncthreads();
+      for (int k = threadIdx.x; k < half; k += blockDim.x) {
+        const int p = pp[k], q = qq[k];
+        if (q >= n) continue;
+        A[p * LD + q] = mk(0.0, 0.0);
+        A[q * LD + p] = mk(0.0, 0.0);
+        A[p * LD + p] = mk(A[p * LD + p].re, 0.0);
+        A[q * LD + q] = mk(A[q * LD + q].re, 0.0);
+      }
+      __syncthreads();
+    }
+    if (nrot == 0) break;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// W orthogonalisation + Cholesky QR.  G1 rows: [X^H W; W^H W; P^H W].
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_small_ortho(const c64* __restrict__ G1, int mb,
+                                                     const int* __restrict__ xmask, const int* __restrict__ pmask,
+                                                     int* __restrict__ wmask, c64* __restrict__ Cw,
+                                                     int* __restrict__ flags, const int* __restrict__ kskip) {
+  const int b = blockIdx.x;
+  if (kskip && kskip[b]) return;
+  __shared__ c64 Gp[LD * LD];        // projected Gram (mb x mb) -> L
+  __shared__ c64 Rh[LD * LD];        // RHS (mb x 3mb): [-CX^H, I, -CP^H], leading dim LD
+  __shared__ int act[LD], xa[LD], pa[LD];
+  __shared__ double d0[LD];
+  __shared__ int brk;
+  const int n = 3 * mb;
+  const c64* G = G1 + (size_t)b * n * mb;
+  for (int i = threadIdx.x; i < mb; i += blockDim.x) {
+    act[i] = wmask[b * mb + i];
+    xa[i] = xmask[b * mb + i];
+    pa[i] = pmask[b * mb + i];
+  }
+  if (threadIdx.x == 0) brk = 0;
+  __syncthreads();
+  // G' = W^H W - CX^H CX - CP^H CP, CX = X^H W (active X rows), CP = P^H W (active P rows)
+  for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {
+    const int i = e / mb, j = e % mb;
+    c64 s = G[(size_t)(mb + i) * mb + j];
+    for (int k = 0; k < mb; ++k) {
+      if (xa[k]) s = s - cmulc(G[(size_t)k * mb + i], G[(size_t)k * mb + j]);
+      if (pa[k]) s = s - cmulc(G[(size_t)(2 * mb + k) * mb + i], G[(size_t)(2 * mb + k) * mb + j]);
+    }
+    Gp[i * LD + j] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {
+    const int i = e / mb, j = e % mb;
+    if (i < j) {
+      const c64 a = Gp[i * LD + j], c = Gp[j * LD + i];
+      c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
+      if (!act[i] || !act[j]) h = mk(0.0, 0.0);
+      Gp[i * LD + j] = h;
+      Gp[j * LD + i] = conj(h);
+    } else if (i == j) {
+      Gp[i * LD + i] = act[i] ? mk(Gp[i * LD + i].re, 0.0) : mk(1.0, 0.0);
+    }
+  }
+  for (int i = threadIdx.x; i < mb; i += blockDim.x) {
+    const double w2 = G[(size_t)(mb + i) * mb + i].re;
+    d0[i] = (w2 > 0.0 && std::isfinite(w2)) ? w2 : 1.0;
+  }
+  __syncthreads();
+  chol_masked(Gp, mb, act, d0, 1e-10, nullptr, &brk);
+  // RHS = [-CX^H, I, -CP^H] (mb x 3mb), then L^{-1} RHS = (Cw)^H
+  for (int e = threadIdx.x; e < mb * n; e += blockDim.x) {
+    const int i = e / n, c = e % n;
+    c64 v;
+    if (c < mb) v = xa[c] ? mk(-G[(size_t)c * mb + i].re, G[(size_t)c * mb + i].im) : mk(0.0, 0.0);
+    else if (c < 2 * mb) v = (c - mb == i) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+    else v = pa[c - 2 * mb] ? mk(-G[(size_t)c * mb + i].re, G[(size_t)c * mb + i].im) : mk(0.0, 0.0);
+    Rh[i * LD + c] = v;
+  }
+  __syncthreads();
+  trsm_lower(Gp, mb, Rh, LD, n);
+  c64* out = Cw + (size_t)b * n * mb;
+  for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {
+    const int r = e / mb, j = e % mb;
+    out[e] = act[j] ? conj(Rh[j * LD + r]) : mk(0.0, 0.0);
+  }
+  for (int i = threadIdx.x; i < mb; i += blockDim.x) wmask[b * mb + i] = act[i];
+  if (threadIdx.x == 0 && brk) atomicOr(&flags[b], 1);
+}
+
+// ------------------------------------------------------------------------------------
+// Rayleigh-Ritz.  Dynamic LDS: Am (LD x LD), Bm (LD x LD), C1 (LD x mb).
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, const c64* __restrict__ GB, int mb,
+                                                  const int* __restrict__ xmask, const int* __restrict__ wmask,
+                                                  const int* __restrict__ pmask, double* __restrict__ theta,
+                                                  c64* __restrict__ Cu, int* __restrict__ pvalid,
+                                                  c64* __restrict__ Lsave, int* __restrict__ flags,
+                                                  const int* __restrict__ kskip) {
+  const int b = blockIdx.x;
+  if (kskip && kskip[b]) return;
+  extern __shared__ c64 sm[];
+  c64* Am = sm;
+  c64* Bm = sm + LD * LD;
+  constexpr int LDC = 24;       // leading dim of n x mb blocks (mb <= 21)
+  c64* C1 = sm + 2 * LD * LD;  // n x mb
+  __shared__ int act[LD], prot[LD], ord[LD], pact[LD];
+  __shared__ double ev[LD], d0[LD];
+  __shared__ int brk, nact;
+  __shared__ double fro;
+  const int n = 3 * mb;
+  const c64* ga = GA + (size_t)b * n * n;
+  const c64* gb = GB + (size_t)b * n * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    act[i] = (i < mb) ? xmask[b * mb + i] : (i < 2 * mb) ? wmask[b * mb + i - mb] : pmask[b * mb + i - 2 * mb];
+    prot[i] = (i < mb) ? 1 : 0;
+  }
+  if (threadIdx.x == 0) {
+    brk = 0;
+    fro = 0.0;
+  }
+  __syncthreads();
+  // GB, masked and Hermitian
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    const c64 a = gb[(size_t)i * n + j], c = gb[(size_t)j * n + i];
+    c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
+    if (i == j) h = act[i] ? mk(h.re, 0.0) : mk(1.0, 0.0);
+    else if (!act[i] || !act[j]) h = mk(0.0, 0.0);
+    Bm[i * LD + j] = h;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = Bm[i * LD + i].re;
+    d0[i] = (d > 0.0 && std::isfinite(d)) ? d : 1.0;
+  }
+  __syncthreads();
+  chol_masked(Bm, n, act, d0, 1e-8, prot, &brk);
+  // GA, masked and Hermitian (inactive: zero row/column, diagonal set after the transform)
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    const c64 a = ga[(size_t)i * n + j], c = ga[(size_t)j * n + i];
+    c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
+    if (i == j) h = mk(h.re, 0.0);
+    if (!act[i] || !act[j]) h = mk(0.0, 0.0);
+    Am[i * LD + j] = h;
+  }
+  __syncthreads();
+  // Am <- L^{-1} Am L^{-H}
+  trsm_lower(Bm, n, Am, LD, n);
+  conj_transpose(Am, n);
+  trsm_lower(Bm, n, Am, LD, n);
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    if (i < j) {
+      const c64 a = Am[i * LD + j], c = Am[j * LD + i];
+      const c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
+      Am[i * LD + j] = h;
+      Am[j * LD + i] = conj(h);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double f = 0.0;
+    int na = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!act[i]) continue;
+      ++na;
+      for (int j = 0; j < n; ++j)
+        if (act[j]) f += abs2(Am[i * LD + j]);
+    }
+    fro = sqrt(f);
+    nact = na;
+    if (!std::isfinite(f) || na < mb) brk = 1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (!act[i]) Am[i * LD + i] = mk(2.0 * fro + 1.0 + (double)i, 0.0);
+  // save L, V = I
+  c64* Ls = Lsave + (size_t)b * LD * LD;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    Ls[i * LD + j] = Bm[i * LD + j];
+    Bm[i * LD + j] = (i == j) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  jacobi(Am, Bm, n);
+  // ascending order by rank (ties by index)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = Am[i * LD + i].re;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int r = 0;
+    for (int j = 0; j < n; ++j) r += (ev[j] < ev[i]) || (ev[j] == ev[i] && j < i);
+    ord[r] = i;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < mb; j += blockDim.x) theta[b * mb + j] = ev[ord[j]];
+  // C1 = L^{-H} V[:, ord[0..mb)]
+  for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {
+    const int i = e / mb, j = e % mb;
+    C1[i * LDC + j] = Bm[i * LD + ord[j]];
+  }
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    Am[i * LD + j] = Ls[i * LD + j];
+  }
+  __syncthreads();
+  trsm_lower_h(Am, n, C1, LDC, mb);
+  // P direction: Y = C1 with the X rows zeroed; Y' = Y - C1 (C1^H GB Y); Y'' = Y' M^{-1/2}
+  // through the Cholesky factor of M = Y'^H GB Y'.  Bm <- GB (masked), Am regions:
+  c64* GY = Am;                    // n x mb (LDC)
+  c64* T = Am + LD * LDC;          // mb x mb (LDC)
+  c64* Yp = T + LDC * LDC;         // n x mb (LDC); ends below LD*LD
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    const c64 a = gb[(size_t)i * n + j], c = gb[(size_t)j * n + i];
+    c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
+    if (i == j) h = act[i] ? mk(h.re, 0.0) : mk(1.0, 0.0);
+    else if (!act[i] || !act[j]) h = mk(0.0, 0.0);
+    Bm[i * LD + j] = h;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {  // GY = GB Y
+    const int i = e / mb, j = e % mb;
+    c64 s = mk(0.0, 0.0);
+    for (int k = mb; k < n; ++k) s = s + Bm[i * LD + k] * C1[k * LDC + j];
+    GY[i * LDC + j] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {  // T = C1^H GY
+    const int i = e / mb, j = e % mb;
+    c64 s = mk(0.0, 0.0);
+    for (int k = 0; k < n; ++k) s = s + cmulc(C1[k * LDC + i], GY[k * LDC + j]);
+    T[i * LDC + j] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {  // Y' = Y - C1 T
+    const int i = e / mb, j = e % mb;
+    c64 s = (i >= mb) ? C1[i * LDC + j] : mk(0.0, 0.0);
+    for (int k = 0; k < mb; ++k) s = s - C1[i * LDC + k] * T[k * LDC + j];
+    Yp[i * LDC + j] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {  // GY = GB Y'
+    const int i = e / mb, j = e % mb;
+    c64 s = mk(0.0, 0.0);
+    for (int k = 0; k < n; ++k) s = s + Bm[i * LD + k] * Yp[k * LDC + j];
+    GY[i * LDC + j] = s;
+  }
+  __syncthreads();
+  // M = Y'^H GB Y' into Bm (mb x mb, LD), then Cholesky with drops
+  for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {
+    const int i = e / mb, j = e % mb;
+    c64 s = mk(0.0, 0.0);
+    for (int k = 0; k < n; ++k) s = s + cmulc(Yp[k * LDC + i], GY[k * LDC + j]);
+    Bm[i * LD + j] = s;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {
+    const int i = e / mb, j = e % mb;
+    if (i < j) {
+      const c64 a = Bm[i * LD + j], c = Bm[j * LD + i];
+      const c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
+      Bm[i * LD + j] = h;
+      Bm[j * LD + i] = conj(h);
+    } else if (i == j) {
+      Bm[i * LD + i] = mk(Bm[i * LD + i].re, 0.0);
+    }
+  }
+  // scale M to unit diagonal (the P candidates of nearly converged bands are tiny but still
+  // carry a direction); a zero or non-finite column is dropped
+  for (int i = threadIdx.x; i < mb; i += blockDim.x) {
+    const double d = Bm[i * LD + i].re;
+    const bool ok = d > 1e-300 && std::isfinite(d);
+    pact[i] = ok ? 1 : 0;
+    ev[i] = ok ? 1.0 / sqrt(d) : 0.0;  // column scales
+    d0[i] = 1.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {
+    const int i = e / mb, j = e % mb;
+    Bm[i * LD + j] = (ev[i] * ev[j]) * Bm[i * LD + j];
+  }
+  for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {
+    const int i = e / mb, j = e % mb;
+    Yp[i * LDC + j] = ev[j] * Yp[i * LDC + j];
+  }
+  __syncthreads();
+  chol_masked(Bm, mb, pact, d0, 1e-10, nullptr, &brk);
+  // Y''^H = L_M^{-1} Y'^H (mb x n, leading dim LD) over the dead GY/T regions (below Yp)
+  c64* YH = Am;
+  __syncthreads();
+  for (int e = threadIdx.x; e < mb * n; e += blockDim.x) {
+    const int i = e / n, c = e % n;
+    YH[i * LD + c] = conj(Yp[c * LDC + i]);
+  }
+  __syncthreads();
+  trsm_lower(Bm, mb, YH, LD, n);
+  c64* out = Cu + (size_t)b * n * 2 * mb;
+  for (int e = threadIdx.x; e < n * 2 * mb; e += blockDim.x) {
+    const int i = e / (2 * mb), j = e % (2 * mb);
+    c64 v;
+    if (j < mb) v = C1[i * LDC + j];
+    else v = pact[j - mb] ? conj(YH[(j - mb) * LD + i]) : mk(0.0, 0.0);
+    out[e] = v;
+  }
+  for (int j = threadIdx.x; j < mb; j += blockDim.x) pvalid[b * mb + j] = pact[j];
+  if (threadIdx.x == 0 && brk) atomicOr(&flags[b], 1);
+}
+
+int small_ortho(const c64* G1, int mb, int nb, const int* xmask, const int* pmask, int* wmask, c64* Cw,
+                int* flags, const int* kskip, hipStream_t s) {
+  if (3 * mb > RR_NMAX) {
+    set_error("block size too large");
+    return KC_ERR_INVALID_ARG;
+  }
+  k_small_ortho<<<nb, 256, 0, s>>>(G1, mb, xmask, pmask, wmask, Cw, flags, kskip);
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,
+             double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, hipStream_t s) {
+  if (3 * mb > RR_NMAX || mb > 21) {
+    set_error("block size too large");
+    return KC_ERR_INVALID_ARG;
+  }
+  const size_t shm = (size_t)(2 * LD * LD + LD * 24) * sizeof(c64);
+  static bool attr = false;
+  if (!attr) {
+    KC_HIP(hipFuncSetAttribute((const void*)k_small_rr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    attr = true;
+  }
+  k_small_rr<<<nb, 256, shm, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave, flags, kskip);
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+}  // namespace kc

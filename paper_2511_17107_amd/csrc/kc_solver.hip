@@ -1,10 +1,34 @@
-// LOBPCG driver (placeholder until the block kernels land).
-#include "kc_state.h"
+// LOBPCG with soft locking (Section 4: custom block solver, convergence test of eq (4.3)) for
+// the m smallest positive eigenvalues of the compensated operator, run for a batch of
+// k-points in lock-step (one set of launches per step for the whole batch).
+//
+// Per k-point the search space is S = [X W P] (3 mb columns) with images AS = [AX AW AP]:
+//   1. R = AX - X Theta, Res_j = |r_j| / |x_j|, W = K_P^{-1} R            (k_resid_precond)
+//   2. soft locking: columns with Res_j <= tol (j < m) get no new W; k-points whose
+//      m bands all satisfy the test are verified with a fresh FP64 application and retired
+//   3. W <- (W - X X^H W - P P^H W) R^{-1}  (one projection + Cholesky QR; Gram on MFMA)
+//   4. AW = Op W (FP32 while the mixed-precision phase lasts, FP64 after)
+//   5. GA = S^H AS, GB = S^H S; Rayleigh-Ritz: X = S C1, P = S Cp with P orthonormal and
+//      orthogonal to X (Cp from the W and P parts of C1), same coefficients for AX, AP.
+// At k = 0 the preconditioner removes the DC frequency from every direction, so the
+// constant fields (Prop 2.5 (1)) never enter the search space and the reported eigenvalues
+// are the smallest positive ones.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "kc_blas.h"
 
 namespace kc {
 
 struct SolverWork {
-  int dummy = 0;
+  DevBuf S, AS;
+  DevBuf part_gram, part_res;
+  DevBuf G1, GA, GB, Cw, Cu, Lsave;
+  DevBuf theta, res, xn2;
+  DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal [nb each]
 };
 
 void solver_release(kc_op* op) {
@@ -12,6 +36,306 @@ void solver_release(kc_op* op) {
   op->solver = nullptr;
 }
 
+namespace {
+
+struct Batch {
+  kc_op* op;
+  SolverWork* w;
+  int ik0, nb, m, mb, nc, N;
+  size_t n;
+  hipStream_t s;
+  int *xmask, *wmask, *pmask, *pvalid, *kskip, *flags, *kglobal;
+  c64 *S, *AS;
+};
+
+int upload_ints(int* dst, const std::vector<int>& v, hipStream_t s) {
+  KC_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  return KC_OK;
+}
+
+// AX (or AP...) for columns [col0, col0+mb) of every k-point in the batch, masked by `active`
+int apply_cols(Batch& B, int col0, const int* active, int prec) {
+  VecMap vm;
+  vm.vpk = B.mb;
+  vm.kstride = B.nc;
+  vm.active = active;
+  return apply_op(B.op, B.ik0, B.nb * B.mb, vm, B.S + (size_t)col0 * B.n, B.AS + (size_t)col0 * B.n, prec, B.s);
+}
+
+int ortho_w(Batch& B) {
+  KC_TRY(gram(B.S, B.nc, 0, B.nc, B.S, B.nc, B.mb, B.mb, B.n, B.nb, B.w->part_gram, B.w->G1.as<c64>(), B.kskip,
+              B.s));
+  KC_TRY(small_ortho(B.w->G1.as<c64>(), B.mb, B.nb, B.xmask, B.pmask, B.wmask, B.w->Cw.as<c64>(), B.flags,
+                     B.kskip, B.s));
+  KC_TRY(update(B.S, B.nc, 0, B.nc, B.S, B.nc, B.mb, B.mb, B.mb, B.mb, B.w->Cw.as<c64>(), B.n, B.nb, B.kskip,
+                B.s));
+  return KC_OK;
+}
+
+int rayleigh_ritz(Batch& B) {
+  KC_TRY(gram(B.S, B.nc, 0, B.nc, B.AS, B.nc, 0, B.nc, B.n, B.nb, B.w->part_gram, B.w->GA.as<c64>(), B.kskip,
+              B.s));
+  KC_TRY(gram(B.S, B.nc, 0, B.nc, B.S, B.nc, 0, B.nc, B.n, B.nb, B.w->part_gram, B.w->GB.as<c64>(), B.kskip,
+              B.s));
+  KC_TRY(small_rr(B.w->GA.as<c64>(), B.w->GB.as<c64>(), B.mb, B.nb, B.xmask, B.wmask, B.pmask,
+                  B.w->theta.as<double>(), B.w->Cu.as<c64>(), B.pvalid, B.w->Lsave.as<c64>(), B.flags, B.kskip,
+                  B.s));
+  // [X | P] <- S Cu, [AX | AP] <- AS Cu
+  KC_TRY(update(B.S, B.nc, 0, B.nc, B.S, B.nc, 2 * B.mb, B.mb, 0, 2 * B.mb, B.w->Cu.as<c64>(), B.n, B.nb,
+                B.kskip, B.s));
+  KC_TRY(update(B.AS, B.nc, 0, B.nc, B.AS, B.nc, 2 * B.mb, B.mb, 0, 2 * B.mb, B.w->Cu.as<c64>(), B.n, B.nb,
+                B.kskip, B.s));
+  return KC_OK;
+}
+
+int residuals(Batch& B) {
+  return resid_precond(B.S, B.AS, B.S, B.w->theta.as<double>(), B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N,
+                       B.op->gamma_d.as<double>() + B.ik0, B.N, B.nc, 0, B.mb, B.mb, B.nb, B.w->part_res,
+                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s);
+}
+
+int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig, double* res_out, int* iters,
+                c64* Xout, hipStream_t s, bool* all_conv) {
+  if (!op->solver) op->solver = new SolverWork();
+  SolverWork* w = op->solver;
+  Batch B;
+  B.op = op;
+  B.w = w;
+  B.ik0 = ik0;
+  B.nb = nb;
+  B.m = o.m;
+  B.mb = o.m + o.guard;
+  B.nc = 3 * B.mb;
+  B.N = op->N;
+  B.n = 3 * (size_t)op->N * op->N * op->N;
+  B.s = s;
+  const int mb = B.mb, nc = B.nc, m = B.m;
+  const size_t n = B.n;
+  const size_t colbytes = n * sizeof(c64);
+  KC_TRY(w->S.ensure((size_t)nb * nc * colbytes));
+  KC_TRY(w->AS.ensure((size_t)nb * nc * colbytes));
+  KC_TRY(w->G1.ensure((size_t)nb * nc * mb * sizeof(c64)));
+  KC_TRY(w->GA.ensure((size_t)nb * nc * nc * sizeof(c64)));
+  KC_TRY(w->GB.ensure((size_t)nb * nc * nc * sizeof(c64)));
+  KC_TRY(w->Cw.ensure((size_t)nb * nc * mb * sizeof(c64)));
+  KC_TRY(w->Cu.ensure((size_t)nb * nc * 2 * mb * sizeof(c64)));
+  KC_TRY(w->Lsave.ensure((size_t)nb * RR_NMAX * RR_NMAX * sizeof(c64)));
+  KC_TRY(w->theta.ensure((size_t)nb * mb * sizeof(double)));
+  KC_TRY(w->res.ensure((size_t)nb * mb * sizeof(double)));
+  KC_TRY(w->xn2.ensure((size_t)nb * mb * sizeof(double)));
+  KC_TRY(w->ints.ensure((size_t)(4 * nb * mb + 3 * nb) * sizeof(int)));
+  B.S = w->S.as<c64>();
+  B.AS = w->AS.as<c64>();
+  int* ib = w->ints.as<int>();
+  B.xmask = ib;
+  B.wmask = ib + nb * mb;
+  B.pmask = ib + 2 * nb * mb;
+  B.pvalid = ib + 3 * nb * mb;
+  B.kskip = ib + 4 * nb * mb;
+  B.flags = B.kskip + nb;
+  B.kglobal = B.flags + nb;
+
+  std::vector<int> hx(nb * mb, 0), hw(nb * mb, 1), hp(nb * mb, 0), hpv(nb * mb, 0), hskip(nb, 0), hflags(nb, 0),
+      hkg(nb);
+  for (int b = 0; b < nb; ++b) hkg[b] = ik0 + b;
+  std::vector<double> hres(nb * mb, 0.0), htheta(nb * mb, -1.0);
+  std::vector<char> done(nb, 0);
+  std::vector<int> its(nb, 0), brk_count(nb, 0);
+  std::vector<char> drop_p(nb, 0);
+
+  KC_HIP(hipMemsetAsync(B.S, 0, (size_t)nb * nc * colbytes, s));
+  KC_HIP(hipMemsetAsync(B.AS, 0, (size_t)nb * nc * colbytes, s));
+  KC_TRY(upload_ints(B.kglobal, hkg, s));
+  KC_TRY(upload_ints(B.kskip, hskip, s));
+  KC_TRY(upload_ints(B.flags, hflags, s));
+  KC_TRY(upload_ints(B.pvalid, hpv, s));
+  // initial block: W = K_P^{-1} (random), using the residual pass with AX = 0, theta = -1
+  KC_TRY(random_block(B.S, n, nc, 0, mb, nb, o.seed, B.kglobal, s));
+  KC_HIP(hipMemcpyAsync(w->theta.p, htheta.data(), htheta.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  KC_TRY(residuals(B));
+  KC_TRY(upload_ints(B.xmask, hx, s));
+  KC_TRY(upload_ints(B.wmask, hw, s));
+  KC_TRY(upload_ints(B.pmask, hp, s));
+  KC_TRY(ortho_w(B));
+  KC_TRY(ortho_w(B));
+  int prec = o.prec;
+  bool mixed = (o.prec == KC_PREC_FP32);
+  double nmv64 = 0, nmv32 = 0;
+  KC_TRY(apply_cols(B, mb, B.wmask, prec));
+  (prec == KC_PREC_FP64 ? nmv64 : nmv32) += nb * mb;
+  KC_TRY(rayleigh_ritz(B));
+  std::fill(hx.begin(), hx.end(), 1);
+  KC_TRY(upload_ints(B.xmask, hx, s));
+
+  int it = 0;
+  double best_max = 1e300;
+  int stall = 0;
+  bool verify_pending = false;
+  while (true) {
+    KC_TRY(residuals(B));
+    KC_HIP(hipMemcpyAsync(hres.data(), w->res.p, hres.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    KC_HIP(hipMemcpyAsync(hpv.data(), B.pvalid, hpv.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    KC_HIP(hipMemcpyAsync(hflags.data(), B.flags, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    KC_HIP(hipStreamSynchronize(s));
+    bool reset_flags = false;
+    for (int b = 0; b < nb; ++b) {
+      if (done[b]) continue;
+      for (int j = 0; j < mb; ++j)
+        if (!std::isfinite(hres[b * mb + j])) hflags[b] |= 1;
+      if (hflags[b] & 1) {
+        reset_flags = true;
+        drop_p[b] = 1;
+        if (++brk_count[b] > 5) {
+          set_error("LOBPCG breakdown (loss of positive definiteness or non-finite values) at k-point " +
+                    std::to_string(ik0 + b));
+          return KC_ERR_BREAKDOWN;
+        }
+      }
+    }
+    if (reset_flags) {
+      std::fill(hflags.begin(), hflags.end(), 0);
+      KC_TRY(upload_ints(B.flags, hflags, s));
+    }
+    if (o.verbose) {
+      double mx = 0;
+      for (int b = 0; b < nb; ++b)
+        if (!done[b])
+          for (int j = 0; j < m; ++j) mx = std::max(mx, hres[b * mb + j]);
+      fprintf(stderr, "[kc_solve] k %d..%d it %d prec %s max res %.3e\n", ik0, ik0 + nb - 1, it,
+              prec == KC_PREC_FP64 ? "fp64" : "fp32", mx);
+      if (o.verbose > 1) {
+        std::vector<double> th(nb * mb);
+        KC_HIP(hipMemcpy(th.data(), w->theta.p, th.size() * sizeof(double), hipMemcpyDeviceToHost));
+        fprintf(stderr, "   theta:");
+        for (int j = 0; j < mb; ++j) fprintf(stderr, " %.10f", th[j]);
+        fprintf(stderr, "\n   res:  ");
+        for (int j = 0; j < mb; ++j) fprintf(stderr, " %.2e", hres[j]);
+        fprintf(stderr, "\n   pval: ");
+        for (int j = 0; j < mb; ++j) fprintf(stderr, " %d", hpv[j]);
+        fprintf(stderr, " flags %d\n", hflags[0]);
+      }
+    }
+    // verification outcome / convergence test
+    std::vector<int> cand(nb, 0);
+    int ncand = 0, nlive = 0;
+    double mxres = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      if (done[b]) continue;
+      ++nlive;
+      bool ok = true;
+      for (int j = 0; j < m; ++j) {
+        ok = ok && hres[b * mb + j] <= o.tol;
+        mxres = std::max(mxres, hres[b * mb + j]);
+      }
+      if (ok) {
+        cand[b] = 1;
+        ++ncand;
+      }
+    }
+    if (verify_pending) {
+      // residuals above come from a fresh FP64 application of Op to X
+      for (int b = 0; b < nb; ++b)
+        if (!done[b] && cand[b]) {
+          done[b] = 1;
+          its[b] = it;
+        }
+      verify_pending = false;
+      bool any = false;
+      for (int b = 0; b < nb; ++b) any = any || !done[b];
+      if (!any) break;
+      for (int b = 0; b < nb; ++b) hskip[b] = done[b];
+      KC_TRY(upload_ints(B.kskip, hskip, s));
+      continue;  // recompute residuals/W for the live k-points with the same X
+    }
+    if (ncand > 0 && prec == KC_PREC_FP64) {
+      // fresh FP64 AX for the candidates, then re-test
+      std::vector<int> act(nb * mb, 0);
+      for (int b = 0; b < nb; ++b)
+        if (cand[b])
+          for (int j = 0; j < mb; ++j) act[b * mb + j] = 1;
+      KC_TRY(upload_ints(B.wmask, act, s));
+      KC_TRY(apply_cols(B, 0, B.wmask, KC_PREC_FP64));
+      nmv64 += ncand * mb;
+      verify_pending = true;
+      continue;
+    }
+    if (it >= o.maxit) break;
+    // mixed precision: leave the FP32 phase once the residuals reach switch_tol or stall
+    if (mixed && prec == KC_PREC_FP32) {
+      if (mxres < best_max * 0.7) {
+        best_max = mxres;
+        stall = 0;
+      } else {
+        ++stall;
+      }
+      if (mxres <= o.switch_tol || stall >= 4 || ncand > 0) {
+        prec = KC_PREC_FP64;
+        std::vector<int> act(nb * mb, 0);
+        for (int b = 0; b < nb; ++b)
+          if (!done[b])
+            for (int j = 0; j < mb; ++j) act[b * mb + j] = 1;
+        KC_TRY(upload_ints(B.wmask, act, s));
+        KC_TRY(apply_cols(B, 0, B.wmask, KC_PREC_FP64));  // AX
+        nmv64 += nlive * mb;
+        std::vector<int> pa(nb * mb, 0);
+        for (int i = 0; i < nb * mb; ++i) pa[i] = act[i] && hpv[i];
+        KC_TRY(upload_ints(B.wmask, pa, s));
+        KC_TRY(apply_cols(B, 2 * mb, B.wmask, KC_PREC_FP64));  // AP
+        for (int v : pa) nmv64 += v;
+        continue;
+      }
+    }
+    // masks for this iteration; after a breakdown the k-point restarts without P
+    int nact = 0;
+    for (int b = 0; b < nb; ++b)
+      for (int j = 0; j < mb; ++j) {
+        const int i = b * mb + j;
+        hw[i] = !done[b] && (j >= m || hres[i] > o.tol);
+        // P is kept for locked bands too: its columns are orthonormalised together (each is a
+        // mixture of the bands' directions), so dropping one would cut the others
+        hp[i] = !done[b] && hpv[i] && !drop_p[b];
+        nact += hw[i];
+      }
+    for (int b = 0; b < nb; ++b) {
+      hskip[b] = done[b];
+      drop_p[b] = 0;
+    }
+    KC_TRY(upload_ints(B.wmask, hw, s));
+    KC_TRY(upload_ints(B.pmask, hp, s));
+    KC_TRY(upload_ints(B.kskip, hskip, s));
+    KC_TRY(ortho_w(B));
+    KC_TRY(apply_cols(B, mb, B.wmask, prec));
+    (prec == KC_PREC_FP64 ? nmv64 : nmv32) += nact;
+    KC_TRY(rayleigh_ritz(B));
+    ++it;
+  }
+  // results
+  std::vector<double> th(nb * mb);
+  KC_HIP(hipMemcpyAsync(th.data(), w->theta.p, th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  KC_HIP(hipStreamSynchronize(s));
+  bool allc = true;
+  for (int b = 0; b < nb; ++b) {
+    for (int j = 0; j < m; ++j) {
+      eig[(size_t)b * m + j] = th[b * mb + j];
+      res_out[(size_t)b * m + j] = hres[b * mb + j];
+    }
+    if (iters) iters[b] = done[b] ? its[b] : it;
+    allc = allc && done[b];
+    if (Xout) {
+      for (int j = 0; j < m; ++j)
+        KC_HIP(hipMemcpyAsync(Xout + ((size_t)b * m + j) * n, B.S + ((size_t)b * nc + j) * n, colbytes,
+                              hipMemcpyDeviceToDevice, s));
+    }
+  }
+  KC_HIP(hipStreamSynchronize(s));
+  op->stats[0] += nmv64;
+  op->stats[1] += nmv32;
+  op->stats[3] += (double)it * nb;
+  *all_conv = allc;
+  return KC_OK;
+}
+
+}  // namespace
 }  // namespace kc
 
 extern "C" {
@@ -32,10 +356,32 @@ void kc_solve_opts_default(kc_solve_opts* o) {
 int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_host, double* res_host,
              int* iters_host, void* X_out, void* stream) {
   KC_ARG(op != nullptr && opts != nullptr, "NULL op or opts");
-  (void)ik0; (void)nk; (void)eig_host; (void)res_host; (void)iters_host;
-  (void)X_out; (void)stream;
-  kc::set_error("kc_solve not built yet");
-  return KC_ERR_UNSUPPORTED;
+  KC_ARG(eig_host != nullptr && res_host != nullptr, "NULL eig or res output");
+  KC_ARG(op->nk > 0 && nk >= 1 && ik0 >= 0 && ik0 + nk <= op->nk, "k-point range");
+  const kc_solve_opts& o = *opts;
+  KC_ARG(o.m >= 1 && o.guard >= 0 && o.m + o.guard <= 21, "m + guard must be in [1, 21]");
+  KC_ARG((size_t)3 * (o.m + o.guard) <= 3 * (size_t)op->N * op->N * op->N, "block larger than the space");
+  KC_ARG(o.tol > 0.0 && o.maxit >= 1 && o.batch_k >= 1, "tol > 0, maxit >= 1, batch_k >= 1");
+  KC_ARG(o.prec == KC_PREC_FP64 || o.prec == KC_PREC_FP32, "prec");
+  hipStream_t s = (hipStream_t)stream;
+  auto t0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < 8; ++i) op->stats[i] = 0.0;
+  bool allc = true;
+  for (int k0 = 0; k0 < nk; k0 += o.batch_k) {
+    const int nb = std::min(o.batch_k, nk - k0);
+    bool c = true;
+    KC_TRY(kc::solve_batch(op, ik0 + k0, nb, o, eig_host + (size_t)k0 * o.m, res_host + (size_t)k0 * o.m,
+                           iters_host ? iters_host + k0 : nullptr,
+                           X_out ? (kc::c64*)X_out + (size_t)k0 * o.m * 3 * op->N * op->N * op->N : nullptr, s,
+                           &c));
+    allc = allc && c;
+  }
+  op->stats[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (!allc) {
+    kc::set_error("some k-points did not reach tol within maxit");
+    return KC_ERR_NO_CONVERGENCE;
+  }
+  return KC_OK;
 }
 
 }  // extern "C"

@@ -34,6 +34,17 @@ struct DevBuf {
 
 struct SolverWork;  // LOBPCG buffers (kc_solver.hip)
 
+// Addressing of the vectors of a block operation: vector v belongs to k-point v / vpk and is
+// column v % vpk of that k-point's group, stored at (v / vpk) * kstride + v % vpk (in units of
+// one 3N^3 vector).  active[v] == 0 skips the vector (its output is left untouched).
+struct VecMap {
+  int vpk = 1;
+  int kstride = 1;
+  const int* active = nullptr;
+  __host__ __device__ size_t off(int v) const { return (size_t)(v / vpk) * kstride + (v % vpk); }
+  __device__ bool on(int v) const { return active == nullptr || active[v] != 0; }
+};
+
 }  // namespace kc
 
 struct kc_op {
@@ -55,9 +66,10 @@ struct kc_op {
 
 namespace kc {
 
-// y = Op x (kc_apply without argument checks); vectors v use k-point ik0 + v / vecs_per_k.
-int apply_op(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* x, c64* y, int prec,
-             hipStream_t s);
+// y = Op x (kc_apply without argument checks); vectors v use k-point ik0 + v / vm.vpk.  With
+// ev != nullptr, events ev[0..6] are recorded around the passes (6 passes for CrossDoF, 5 else).
+int apply_op(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x, c64* y, int prec,
+             hipStream_t s, hipEvent_t* ev = nullptr);
 // z = K_P^{-1} r
 int apply_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* r, c64* z,
                   hipStream_t s);
