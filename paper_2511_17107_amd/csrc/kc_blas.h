@@ -5,10 +5,10 @@
 
 namespace kc {
 
-// G_b = A_b^H B_b, A_b columns acol0.. (p of them), B_b columns bcol0.. (q), for nb k-points;
-// G: [nb][p][q] complex (row-major).  `part` is scratch.
-int gram(const c64* A, int akstride, int acol0, int p, const c64* B, int bkstride, int bcol0, int q, size_t n,
-         int nb, DevBuf& part, c64* G, const int* kskip, hipStream_t s);
+// GA_b = S_b^H AS_b, GB_b = S_b^H S_b (nc x nc, complex, row-major [nb][nc][nc]); columns of
+// k-point b start at (b * kstride) * n.  `part` is scratch.
+int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
+          const int* kskip, hipStream_t s);
 
 // Y_b[:, map(j)] = S_b[:, scol0 .. scol0+p) C_b, C: [nb][p][q]; output column j < q goes to
 // ycol0 + j (j < q1) or ycol1 + j - q1; Y may alias S.
@@ -26,14 +26,10 @@ int random_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, uint
 // Small dense steps (one workgroup per k-point), see kc_small.hip.
 constexpr int RR_NMAX = 64;  // 3 * block size
 
-// Orthogonalise W against X and P and orthonormalise it (Cholesky QR): from
-// G1 = [X W P]^H W (3mb x mb) build Cw (3mb x mb) with W_new = [X W P] Cw.
-int small_ortho(const c64* G1, int mb, int nb, const int* xmask, const int* pmask, int* wmask, c64* Cw,
-                int* flags, const int* kskip, hipStream_t s);
-
 // Rayleigh-Ritz on S = [X W P]: from GA = S^H AS, GB = S^H S (3mb x 3mb) compute the mb
 // smallest Ritz values theta and Cu = [C1 | Cp] (3mb x 2mb) with X_new = S C1, P_new = S Cp
-// (P_new orthonormal and orthogonal to X_new in the GB inner product).
+// (P_new orthonormal and orthogonal to X_new in the GB inner product).  The columns of S need
+// not be normalised or orthogonal: the pencil is scaled to unit diagonal first.
 int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,
              double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, hipStream_t s);
 

@@ -20,102 +20,131 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 }
 
 // ------------------------------------------------------------------------------------
-// Gram: G_b = A_b^H B_b (p x q complex), partial sums over row chunks.
-// Complex products on real MFMA: with a = ar + i ai, b = br + i bi,
+// Gram matrices of the Rayleigh-Ritz step: GA_b = S_b^H AS_b and GB_b = S_b^H S_b (nc x nc,
+// Hermitian: only the 16x16 tiles on and above the diagonal are formed).  Complex products on
+// real MFMA: with a = ar + i ai, b = br + i bi,
 //   Re(conj(a) b) = ar br + ai bi,   Im(conj(a) b) = ar bi - ai br,
-// so each 16x16 tile over 4 rows is four real MFMAs whose A operands are the real and
-// imaginary parts of 4 rows of 16 A-columns and whose B operands are (br, bi) and (bi, -br).
-// Grid: x = row chunk (ksplit), y = tile block, z = k-point.  Each of the 4 waves of a
-// workgroup walks a contiguous quarter of the chunk and writes its own partial tile block.
+// so a 16x16 tile over 4 rows is four real MFMAs whose A operands are the real and imaginary
+// parts of 4 rows of 16 S-columns and whose B operands are (br, bi) and (bi, -br).
+// A workgroup owns a chunk of rows of one k-point; it stages 16 rows of all 2 nc columns
+// (S and AS) in LDS with coalesced loads, so each column is read from HBM once, and its 4
+// waves share the tiles.  Partial tiles per chunk are summed in a fixed order afterwards.
 // ------------------------------------------------------------------------------------
-template <int TA, int TB>
-__global__ __launch_bounds__(256) void k_gram(const c64* __restrict__ A, const c64* __restrict__ B, size_t n,
-                                              int p, int q, int akstride, int acol0, int bkstride, int bcol0,
-                                              int ntb_b, int rows_per_chunk, c64* __restrict__ part,
-                                              const int* __restrict__ kskip) {
-  const int b = blockIdx.z;
-  if (kskip && kskip[b]) return;
-  const int chunk = blockIdx.x;
-  const int tbi = blockIdx.y / ntb_b, tbj = blockIdx.y % ntb_b;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const size_t r_begin = (size_t)chunk * rows_per_chunk;
-  const size_t r_end = std::min(n, r_begin + rows_per_chunk);
-  const size_t per_wave = ((size_t)rows_per_chunk / 4 + 3) & ~(size_t)3;
-  const size_t w_begin = std::min(r_end, r_begin + wave * per_wave);
-  const size_t w_end = std::min(r_end, w_begin + per_wave);
+constexpr int G2_ROWS = 16;
+constexpr int G2_PITCH = 2 * 64 + 1;  // LDS row pitch (complex), odd to spread banks
 
-  const c64* acol[TA];
-  const c64* bcol[TB];
-  bool aok[TA], bok[TB];
-#pragma unroll
-  for (int t = 0; t < TA; ++t) {
-    const int c = (tbi * TA + t) * 16 + li;
-    aok[t] = c < p;
-    acol[t] = A + ((size_t)b * akstride + acol0 + (aok[t] ? c : 0)) * n;
-  }
-#pragma unroll
-  for (int t = 0; t < TB; ++t) {
-    const int c = (tbj * TB + t) * 16 + li;
-    bok[t] = c < q;
-    bcol[t] = B + ((size_t)b * bkstride + bcol0 + (bok[t] ? c : 0)) * n;
-  }
-  d4 re[TA][TB], im[TA][TB];
-#pragma unroll
-  for (int i = 0; i < TA; ++i)
-#pragma unroll
-    for (int j = 0; j < TB; ++j) {
-      re[i][j] = d4{0, 0, 0, 0};
-      im[i][j] = d4{0, 0, 0, 0};
-    }
-  for (size_t r = w_begin; r < w_end; r += 4) {
-    const size_t row = r + lk;
-    const bool rok = row < w_end;
-    c64 av[TA], bv[TB];
-#pragma unroll
-    for (int t = 0; t < TA; ++t) av[t] = (rok && aok[t]) ? acol[t][row] : mk(0.0, 0.0);
-#pragma unroll
-    for (int t = 0; t < TB; ++t) bv[t] = (rok && bok[t]) ? bcol[t][row] : mk(0.0, 0.0);
-#pragma unroll
-    for (int i = 0; i < TA; ++i)
-#pragma unroll
-      for (int j = 0; j < TB; ++j) {
-        re[i][j] = mfma(av[i].re, bv[j].re, re[i][j]);
-        re[i][j] = mfma(av[i].im, bv[j].im, re[i][j]);
-        im[i][j] = mfma(av[i].re, bv[j].im, im[i][j]);
-        im[i][j] = mfma(av[i].im, -bv[j].re, im[i][j]);
-      }
-  }
-  // partial layout: [b][chunk*4 + wave][p][q]
-  const int nsplit = gridDim.x * 4;
-  c64* out = part + ((size_t)b * nsplit + (size_t)chunk * 4 + wave) * p * q;
-#pragma unroll
-  for (int i = 0; i < TA; ++i)
-#pragma unroll
-    for (int j = 0; j < TB; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gi = (tbi * TA + i) * 16 + lk + 4 * r;
-        const int gj = (tbj * TB + j) * 16 + li;
-        if (gi < p && gj < q) out[(size_t)gi * q + gj] = mk(re[i][j][r], im[i][j][r]);
-      }
-}
-
-// G[b][i][j] = sum over splits, fixed order (deterministic)
-__global__ void k_gram_reduce(const c64* __restrict__ part, int nsplit, int pq, c64* __restrict__ G,
-                              const int* __restrict__ kskip) {
+__global__ __launch_bounds__(256) void k_gram2(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
+                                               int nc, int kstride, int rows_per_chunk, int ntile,
+                                               c64* __restrict__ part, const int* __restrict__ kskip) {
+  __shared__ c64 st[G2_ROWS * G2_PITCH];
   const int b = blockIdx.y;
   if (kskip && kskip[b]) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= pq) return;
-  const c64* src = part + (size_t)b * nsplit * pq + e;
+  const int chunk = blockIdx.x;
+  const int T = (nc + 15) / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  // this wave's tiles: t = wave, wave + 4, ...; t -> (mat, ti, tj), ti <= tj
+  constexpr int MAXT = 5;
+  int tmat[MAXT], tti[MAXT], ttj[MAXT];
+  int nt = 0;
+  {
+    int t = 0;
+    for (int mat = 0; mat < 2; ++mat)
+      for (int i = 0; i < T; ++i)
+        for (int j = i; j < T; ++j, ++t)
+          if ((t & 3) == wave && nt < MAXT) {
+            tmat[nt] = mat;
+            tti[nt] = i;
+            ttj[nt] = j;
+            ++nt;
+          }
+  }
+  d4 re[MAXT], im[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    re[t] = d4{0, 0, 0, 0};
+    im[t] = d4{0, 0, 0, 0};
+  }
+  const c64* Sb = S + (size_t)b * kstride * n;
+  const c64* ASb = AS + (size_t)b * kstride * n;
+  const size_t r_begin = (size_t)chunk * rows_per_chunk;
+  const size_t r_end = std::min(n, r_begin + rows_per_chunk);
+  const int ncol2 = 2 * nc;
+  for (size_t r0 = r_begin; r0 < r_end; r0 += G2_ROWS) {
+    for (int e = threadIdx.x; e < G2_ROWS * ncol2; e += 256) {
+      const int c = e / G2_ROWS, r = e % G2_ROWS;
+      const size_t row = r0 + r;
+      c64 v = mk(0.0, 0.0);
+      if (row < r_end) v = (c < nc) ? Sb[(size_t)c * n + row] : ASb[(size_t)(c - nc) * n + row];
+      st[r * G2_PITCH + c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < G2_ROWS; kb += 4) {
+      const c64* srow = st + (kb + lk) * G2_PITCH;
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) {
+        if (t < nt) {
+          const int ca = tti[t] * 16 + li;
+          const int cb = ttj[t] * 16 + li;
+          const c64 av = (ca < nc) ? srow[ca] : mk(0.0, 0.0);
+          const c64 bv = (cb < nc) ? srow[(tmat[t] == 0 ? nc : 0) + cb] : mk(0.0, 0.0);
+          re[t] = mfma(av.re, bv.re, re[t]);
+          re[t] = mfma(av.im, bv.im, re[t]);
+          im[t] = mfma(av.re, bv.im, im[t]);
+          im[t] = mfma(av.im, -bv.re, im[t]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // partial tiles: [b][chunk][tile][256], tile id = wave + 4 t
+  const int nchunk = gridDim.x;
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    if (t < nt) {
+      c64* out = part + (((size_t)b * nchunk + chunk) * ntile + (wave + 4 * t)) * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[(lk + 4 * r) * 16 + li] = mk(re[t][r], im[t][r]);
+    }
+  }
+}
+
+// Sum the partial tiles over chunks (fixed order) and scatter: G[mat][b] full nc x nc, lower
+// triangle from the conjugate of the upper tiles.
+__global__ void k_gram2_reduce(const c64* __restrict__ part, int nchunk, int ntile, int nc, c64* __restrict__ GA,
+                               c64* __restrict__ GB, const int* __restrict__ kskip) {
+  const int b = blockIdx.z;
+  if (kskip && kskip[b]) return;
+  const int t = blockIdx.y;
+  const int e = threadIdx.x;  // 256 entries of the tile
+  const int T = (nc + 15) / 16;
+  int mat = 0, ti = 0, tj = 0;
+  {
+    int c = 0;
+    bool found = false;
+    for (int m = 0; m < 2 && !found; ++m)
+      for (int i = 0; i < T && !found; ++i)
+        for (int j = i; j < T && !found; ++j, ++c)
+          if (c == t) {
+            mat = m;
+            ti = i;
+            tj = j;
+            found = true;
+          }
+  }
+  const c64* src = part + ((size_t)b * nchunk * ntile + t) * 256 + e;
   double sr = 0.0, si = 0.0;
-  for (int s = 0; s < nsplit; ++s) {
-    const c64 v = src[(size_t)s * pq];
+  for (int k = 0; k < nchunk; ++k) {
+    const c64 v = src[(size_t)k * ntile * 256];
     sr += v.re;
     si += v.im;
   }
-  G[(size_t)b * pq + e] = mk(sr, si);
+  const int i = ti * 16 + e / 16, j = tj * 16 + e % 16;
+  if (i >= nc || j >= nc) return;
+  c64* G = (mat == 0 ? GA : GB) + (size_t)b * nc * nc;
+  G[(size_t)i * nc + j] = mk(sr, si);
+  if (ti != tj) G[(size_t)j * nc + i] = mk(sr, -si);
 }
 
 // ------------------------------------------------------------------------------------
@@ -283,27 +312,26 @@ __global__ void k_random_block(c64* S, size_t n, int kstride, int col0, int ncol
 // ------------------------------------------------------------------------------------
 // host launchers
 // ------------------------------------------------------------------------------------
-int gram(const c64* A, int akstride, int acol0, int p, const c64* B, int bkstride, int bcol0, int q, size_t n,
-         int nb, DevBuf& part, c64* G, const int* kskip, hipStream_t s) {
-  // row chunk so that the grid has a few thousand waves in total
-  constexpr int TA = 3, TB = 3;
-  const int ntb_a = (p + 16 * TA - 1) / (16 * TA);
-  const int ntb_b = (q + 16 * TB - 1) / (16 * TB);
+int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
+          const int* kskip, hipStream_t s) {
+  const int T = (nc + 15) / 16;
+  const int ntile = T * (T + 1);
+  if (nc > 64 || ntile > 20) {
+    set_error("gram2: too many columns");
+    return KC_ERR_INVALID_ARG;
+  }
   const size_t target_wg = 2048;
-  size_t per_tile_wg = std::max<size_t>(1, target_wg / ((size_t)nb * ntb_a * ntb_b));
-  size_t rows = (n + per_tile_wg - 1) / per_tile_wg;
-  rows = std::max<size_t>(rows, 256);
-  rows = (rows + 15) & ~(size_t)15;
-  const int ksplit = (int)((n + rows - 1) / rows);
-  const int nsplit = ksplit * 4;
-  KC_TRY(part.ensure((size_t)nb * nsplit * p * q * sizeof(c64)));
-  dim3 grid(ksplit, ntb_a * ntb_b, nb);
-  k_gram<TA, TB><<<grid, 256, 0, s>>>(A, B, n, p, q, akstride, acol0, bkstride, bcol0, ntb_b, (int)rows,
-                                      part.as<c64>(), kskip);
+  const size_t per_k = std::max<size_t>(1, target_wg / (size_t)nb);
+  size_t rows = (n + per_k - 1) / per_k;
+  rows = std::max<size_t>(rows, 64);
+  rows = (rows + G2_ROWS - 1) / G2_ROWS * G2_ROWS;
+  const int nchunk = (int)((n + rows - 1) / rows);
+  KC_TRY(part.ensure((size_t)nb * nchunk * ntile * 256 * sizeof(c64)));
+  dim3 grid(nchunk, nb);
+  k_gram2<<<grid, 256, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part.as<c64>(), kskip);
   KC_LAUNCHED();
-  const int pq = p * q;
-  dim3 g2((pq + 255) / 256, nb);
-  k_gram_reduce<<<g2, 256, 0, s>>>(part.as<c64>(), nsplit, pq, G, kskip);
+  dim3 g2(1, ntile, nb);
+  k_gram2_reduce<<<g2, 256, 0, s>>>(part.as<c64>(), nchunk, ntile, nc, GA, GB, kskip);
   KC_LAUNCHED();
   return KC_OK;
 }

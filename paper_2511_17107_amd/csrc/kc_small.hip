@@ -193,78 +193,6 @@ __device__ void jacobi(c64* A, c64* V, int n) {
 }
 
 // ------------------------------------------------------------------------------------
-// W orthogonalisation + Cholesky QR.  G1 rows: [X^H W; W^H W; P^H W].
-// ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_small_ortho(const c64* __restrict__ G1, int mb,
-                                                     const int* __restrict__ xmask, const int* __restrict__ pmask,
-                                                     int* __restrict__ wmask, c64* __restrict__ Cw,
-                                                     int* __restrict__ flags, const int* __restrict__ kskip) {
-  const int b = blockIdx.x;
-  if (kskip && kskip[b]) return;
-  __shared__ c64 Gp[LD * LD];        // projected Gram (mb x mb) -> L
-  __shared__ c64 Rh[LD * LD];        // RHS (mb x 3mb): [-CX^H, I, -CP^H], leading dim LD
-  __shared__ int act[LD], xa[LD], pa[LD];
-  __shared__ double d0[LD];
-  __shared__ int brk;
-  const int n = 3 * mb;
-  const c64* G = G1 + (size_t)b * n * mb;
-  for (int i = threadIdx.x; i < mb; i += blockDim.x) {
-    act[i] = wmask[b * mb + i];
-    xa[i] = xmask[b * mb + i];
-    pa[i] = pmask[b * mb + i];
-  }
-  if (threadIdx.x == 0) brk = 0;
-  __syncthreads();
-  // G' = W^H W - CX^H CX - CP^H CP, CX = X^H W (active X rows), CP = P^H W (active P rows)
-  for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {
-    const int i = e / mb, j = e % mb;
-    c64 s = G[(size_t)(mb + i) * mb + j];
-    for (int k = 0; k < mb; ++k) {
-      if (xa[k]) s = s - cmulc(G[(size_t)k * mb + i], G[(size_t)k * mb + j]);
-      if (pa[k]) s = s - cmulc(G[(size_t)(2 * mb + k) * mb + i], G[(size_t)(2 * mb + k) * mb + j]);
-    }
-    Gp[i * LD + j] = s;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {
-    const int i = e / mb, j = e % mb;
-    if (i < j) {
-      const c64 a = Gp[i * LD + j], c = Gp[j * LD + i];
-      c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
-      if (!act[i] || !act[j]) h = mk(0.0, 0.0);
-      Gp[i * LD + j] = h;
-      Gp[j * LD + i] = conj(h);
-    } else if (i == j) {
-      Gp[i * LD + i] = act[i] ? mk(Gp[i * LD + i].re, 0.0) : mk(1.0, 0.0);
-    }
-  }
-  for (int i = threadIdx.x; i < mb; i += blockDim.x) {
-    const double w2 = G[(size_t)(mb + i) * mb + i].re;
-    d0[i] = (w2 > 0.0 && std::isfinite(w2)) ? w2 : 1.0;
-  }
-  __syncthreads();
-  chol_masked(Gp, mb, act, d0, 1e-10, nullptr, &brk);
-  // RHS = [-CX^H, I, -CP^H] (mb x 3mb), then L^{-1} RHS = (Cw)^H
-  for (int e = threadIdx.x; e < mb * n; e += blockDim.x) {
-    const int i = e / n, c = e % n;
-    c64 v;
-    if (c < mb) v = xa[c] ? mk(-G[(size_t)c * mb + i].re, G[(size_t)c * mb + i].im) : mk(0.0, 0.0);
-    else if (c < 2 * mb) v = (c - mb == i) ? mk(1.0, 0.0) : mk(0.0, 0.0);
-    else v = pa[c - 2 * mb] ? mk(-G[(size_t)c * mb + i].re, G[(size_t)c * mb + i].im) : mk(0.0, 0.0);
-    Rh[i * LD + c] = v;
-  }
-  __syncthreads();
-  trsm_lower(Gp, mb, Rh, LD, n);
-  c64* out = Cw + (size_t)b * n * mb;
-  for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {
-    const int r = e / mb, j = e % mb;
-    out[e] = act[j] ? conj(Rh[j * LD + r]) : mk(0.0, 0.0);
-  }
-  for (int i = threadIdx.x; i < mb; i += blockDim.x) wmask[b * mb + i] = act[i];
-  if (threadIdx.x == 0 && brk) atomicOr(&flags[b], 1);
-}
-
-// ------------------------------------------------------------------------------------
 // Rayleigh-Ritz.  Dynamic LDS: Am (LD x LD), Bm (LD x LD), C1 (LD x mb).
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, const c64* __restrict__ GB, int mb,
@@ -281,7 +209,7 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
   constexpr int LDC = 24;       // leading dim of n x mb blocks (mb <= 21)
   c64* C1 = sm + 2 * LD * LD;  // n x mb
   __shared__ int act[LD], prot[LD], ord[LD], pact[LD];
-  __shared__ double ev[LD], d0[LD];
+  __shared__ double ev[LD], d0[LD], sc[LD];
   __shared__ int brk, nact;
   __shared__ double fro;
   const int n = 3 * mb;
@@ -306,9 +234,21 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
     Bm[i * LD + j] = h;
   }
   __syncthreads();
+  // scale the pencil to unit diagonal (columns of S are not normalised); a zero or non-finite
+  // column is dropped (an X column dropping is a breakdown)
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double d = Bm[i * LD + i].re;
-    d0[i] = (d > 0.0 && std::isfinite(d)) ? d : 1.0;
+    const bool ok = d > 1e-300 && std::isfinite(d);
+    if (!ok && act[i] && prot[i]) brk = 1;
+    if (!ok) act[i] = 0;
+    sc[i] = (ok && act[i]) ? 1.0 / sqrt(d) : 1.0;
+    d0[i] = 1.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    Bm[i * LD + j] = (!act[i] || !act[j]) ? (i == j ? mk(1.0, 0.0) : mk(0.0, 0.0))
+                                          : (sc[i] * sc[j]) * Bm[i * LD + j];
   }
   __syncthreads();
   chol_masked(Bm, n, act, d0, 1e-8, prot, &brk);
@@ -319,7 +259,7 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
     c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
     if (i == j) h = mk(h.re, 0.0);
     if (!act[i] || !act[j]) h = mk(0.0, 0.0);
-    Am[i * LD + j] = h;
+    Am[i * LD + j] = (sc[i] * sc[j]) * h;
   }
   __syncthreads();
   // Am <- L^{-1} Am L^{-H}
@@ -393,7 +333,7 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
     c64 h = mk(0.5 * (a.re + c.re), 0.5 * (a.im - c.im));
     if (i == j) h = act[i] ? mk(h.re, 0.0) : mk(1.0, 0.0);
     else if (!act[i] || !act[j]) h = mk(0.0, 0.0);
-    Bm[i * LD + j] = h;
+    Bm[i * LD + j] = (act[i] && act[j]) ? (sc[i] * sc[j]) * h : h;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {  // GY = GB Y
@@ -478,21 +418,10 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
     c64 v;
     if (j < mb) v = C1[i * LDC + j];
     else v = pact[j - mb] ? conj(YH[(j - mb) * LD + i]) : mk(0.0, 0.0);
-    out[e] = v;
+    out[e] = sc[i] * v;  // back to the unscaled columns of S
   }
   for (int j = threadIdx.x; j < mb; j += blockDim.x) pvalid[b * mb + j] = pact[j];
   if (threadIdx.x == 0 && brk) atomicOr(&flags[b], 1);
-}
-
-int small_ortho(const c64* G1, int mb, int nb, const int* xmask, const int* pmask, int* wmask, c64* Cw,
-                int* flags, const int* kskip, hipStream_t s) {
-  if (3 * mb > RR_NMAX) {
-    set_error("block size too large");
-    return KC_ERR_INVALID_ARG;
-  }
-  k_small_ortho<<<nb, 256, 0, s>>>(G1, mb, xmask, pmask, wmask, Cw, flags, kskip);
-  KC_LAUNCHED();
-  return KC_OK;
 }
 
 int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,

@@ -6,10 +6,11 @@
 //   1. R = AX - X Theta, Res_j = |r_j| / |x_j|, W = K_P^{-1} R            (k_resid_precond)
 //   2. soft locking: columns with Res_j <= tol (j < m) get no new W; k-points whose
 //      m bands all satisfy the test are verified with a fresh FP64 application and retired
-//   3. W <- (W - X X^H W - P P^H W) R^{-1}  (one projection + Cholesky QR; Gram on MFMA)
-//   4. AW = Op W (FP32 while the mixed-precision phase lasts, FP64 after)
-//   5. GA = S^H AS, GB = S^H S; Rayleigh-Ritz: X = S C1, P = S Cp with P orthonormal and
-//      orthogonal to X (Cp from the W and P parts of C1), same coefficients for AX, AP.
+//   3. AW = Op W (FP32 while the mixed-precision phase lasts, FP64 after)
+//   4. GA = S^H AS, GB = S^H S (one pass over S and AS, MFMA); Rayleigh-Ritz on the pencil
+//      scaled to unit diagonal (W is neither normalised nor orthogonalised in the large
+//      space: the explicit GB takes care of it): X = S C1, P = S Cp with P orthonormal and
+//      orthogonal to X (Cp from the W and P parts of C1); the same coefficients give AX, AP.
 // At k = 0 the preconditioner removes the DC frequency from every direction, so the
 // constant fields (Prop 2.5 (1)) never enter the search space and the reported eigenvalues
 // are the smallest positive ones.
@@ -26,7 +27,7 @@ namespace kc {
 struct SolverWork {
   DevBuf S, AS;
   DevBuf part_gram, part_res;
-  DevBuf G1, GA, GB, Cw, Cu, Lsave;
+  DevBuf GA, GB, Cu, Lsave;
   DevBuf theta, res, xn2;
   DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal [nb each]
 };
@@ -62,21 +63,9 @@ int apply_cols(Batch& B, int col0, const int* active, int prec) {
   return apply_op(B.op, B.ik0, B.nb * B.mb, vm, B.S + (size_t)col0 * B.n, B.AS + (size_t)col0 * B.n, prec, B.s);
 }
 
-int ortho_w(Batch& B) {
-  KC_TRY(gram(B.S, B.nc, 0, B.nc, B.S, B.nc, B.mb, B.mb, B.n, B.nb, B.w->part_gram, B.w->G1.as<c64>(), B.kskip,
-              B.s));
-  KC_TRY(small_ortho(B.w->G1.as<c64>(), B.mb, B.nb, B.xmask, B.pmask, B.wmask, B.w->Cw.as<c64>(), B.flags,
-                     B.kskip, B.s));
-  KC_TRY(update(B.S, B.nc, 0, B.nc, B.S, B.nc, B.mb, B.mb, B.mb, B.mb, B.w->Cw.as<c64>(), B.n, B.nb, B.kskip,
-                B.s));
-  return KC_OK;
-}
-
 int rayleigh_ritz(Batch& B) {
-  KC_TRY(gram(B.S, B.nc, 0, B.nc, B.AS, B.nc, 0, B.nc, B.n, B.nb, B.w->part_gram, B.w->GA.as<c64>(), B.kskip,
-              B.s));
-  KC_TRY(gram(B.S, B.nc, 0, B.nc, B.S, B.nc, 0, B.nc, B.n, B.nb, B.w->part_gram, B.w->GB.as<c64>(), B.kskip,
-              B.s));
+  KC_TRY(gram2(B.S, B.AS, B.nc, B.nc, B.n, B.nb, B.w->part_gram, B.w->GA.as<c64>(), B.w->GB.as<c64>(), B.kskip,
+               B.s));
   KC_TRY(small_rr(B.w->GA.as<c64>(), B.w->GB.as<c64>(), B.mb, B.nb, B.xmask, B.wmask, B.pmask,
                   B.w->theta.as<double>(), B.w->Cu.as<c64>(), B.pvalid, B.w->Lsave.as<c64>(), B.flags, B.kskip,
                   B.s));
@@ -114,10 +103,8 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   const size_t colbytes = n * sizeof(c64);
   KC_TRY(w->S.ensure((size_t)nb * nc * colbytes));
   KC_TRY(w->AS.ensure((size_t)nb * nc * colbytes));
-  KC_TRY(w->G1.ensure((size_t)nb * nc * mb * sizeof(c64)));
   KC_TRY(w->GA.ensure((size_t)nb * nc * nc * sizeof(c64)));
   KC_TRY(w->GB.ensure((size_t)nb * nc * nc * sizeof(c64)));
-  KC_TRY(w->Cw.ensure((size_t)nb * nc * mb * sizeof(c64)));
   KC_TRY(w->Cu.ensure((size_t)nb * nc * 2 * mb * sizeof(c64)));
   KC_TRY(w->Lsave.ensure((size_t)nb * RR_NMAX * RR_NMAX * sizeof(c64)));
   KC_TRY(w->theta.ensure((size_t)nb * mb * sizeof(double)));
@@ -156,8 +143,6 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(upload_ints(B.xmask, hx, s));
   KC_TRY(upload_ints(B.wmask, hw, s));
   KC_TRY(upload_ints(B.pmask, hp, s));
-  KC_TRY(ortho_w(B));
-  KC_TRY(ortho_w(B));
   int prec = o.prec;
   bool mixed = (o.prec == KC_PREC_FP32);
   double nmv64 = 0, nmv32 = 0;
@@ -303,7 +288,6 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
     KC_TRY(upload_ints(B.wmask, hw, s));
     KC_TRY(upload_ints(B.pmask, hp, s));
     KC_TRY(upload_ints(B.kskip, hskip, s));
-    KC_TRY(ortho_w(B));
     KC_TRY(apply_cols(B, mb, B.wmask, prec));
     (prec == KC_PREC_FP64 ? nmv64 : nmv32) += nact;
     KC_TRY(rayleigh_ritz(B));
