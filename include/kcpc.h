@@ -134,6 +134,9 @@ int kc_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void
  */
 int kc_fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, void* stream);
 
+/* Preconditioner of kc_solve. */
+enum { KC_PRECOND_DIAG = 0, KC_PRECOND_LEARNED = 1 };
+
 /* Solver options for kc_solve (LOBPCG with soft locking, Section 4). */
 typedef struct kc_solve_opts {
   int m;              /* bands wanted (smallest positive eigenvalues)                      */
@@ -147,6 +150,7 @@ typedef struct kc_solve_opts {
   int batch_k;        /* k-points solved together in one set of launches (>= 1)            */
   uint64_t seed;      /* seed of the random initial block                                  */
   int verbose;        /* 1: print per-iteration residuals to stderr                        */
+  int precond;        /* KC_PRECOND_DIAG, or KC_PRECOND_LEARNED (needs kc_attach_net)      */
 } kc_solve_opts;
 
 /* Fill opts with defaults (m = 10, guard = 0, tol = 1e-8, maxit = 500, FP64, batch_k = 1). */
@@ -166,11 +170,48 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
              double* res_host, int* iters_host, void* X_out, void* stream);
 
 /* Statistics of the last kc_solve: float64 [8] = {matvecs FP64 (vector count), matvecs FP32,
- * seconds total, iterations (sum over k-points), 0, 0, 0, 0}. */
+ * seconds total, iterations (sum over k-points), k-points that kept the learned correction
+ * to the end, 0, 0, 0}. */
 int kc_last_solve_stats(const kc_op* op, double* stats_host);
 
 /* Release the handle and every device buffer it owns.  NULL is allowed. */
 void kc_destroy(kc_op* op);
+
+/*
+ * Learned preconditioner.  A three-layer periodic 3D convolution network (3x3x3 kernels,
+ * 18 -> 32 -> 32 -> 6 channels, leaky ReLU slope 0.01, BF16 weights and activations with FP32
+ * accumulation) maps the normalised real-space residual F3 r (6 channels), the inverse
+ * permittivity (9 channels: diagonal at the x/y/z-edge points, Re/Im of the upper off-diagonals
+ * at the volume point) and k/pi (3 channels) to a correction of the diagonal-block
+ * preconditioner of eqs (2.31)-(2.32): z = K_P^{-1} r + F3^H net(F3 r).  Grids need N % 16 == 0.
+ *
+ * Tensors: network input bf16 [batch][N^3][32] (channels-last, channels 18..31 zero), output
+ * float32 [batch][N^3][16] (channels 6..15 zero); parameters float32 in the order
+ * W1 b1 W2 b2 W3 b3 with W[co][ci][dz][dy][dx] (tap offsets d-1, circular) and b[co].
+ */
+typedef struct kc_net kc_net;
+int kc_net_create(uint64_t seed, kc_net** out);         /* He-normal init, last layer ~0    */
+size_t kc_net_param_count(void);
+int kc_net_get_params(const kc_net* net, float* host, size_t n);
+int kc_net_set_params(kc_net* net, const float* host, size_t n);
+int kc_net_forward(kc_net* net, int N, int batch, const void* in_bf16, void* out_f32, void* stream);
+/* Mean-squared-error loss over the 6 output channels and its gradient for every parameter
+ * (grads_host float32 [kc_net_param_count()] or NULL to keep them on the device for
+ * kc_net_adam_step).  Blocks until done. */
+int kc_net_gradients(kc_net* net, int N, int batch, const void* in_bf16, const void* target_f32,
+                     double* loss_host, float* grads_host, void* stream);
+/* One Adam step (Kingma & Ba) with the gradients of the last kc_net_gradients call. */
+int kc_net_adam_step(kc_net* net, float lr, float beta1, float beta2, float eps, void* stream);
+void kc_net_destroy(kc_net* net);
+/* Attach (or detach with NULL) a network to an operator; the operator does not own it. */
+int kc_attach_net(kc_op* op, kc_net* net);
+/* Network input of nvec k-space vectors r (device complex128 [nvec][3][N^3]): the real-space
+ * residual F3 r scaled by sqrt(3 N^3)/|r| plus the fixed channels; feat_bf16 [nvec][N^3][32]. */
+int kc_net_features(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* feat_bf16,
+                    void* stream);
+/* z = K_P^{-1} r + F3^H net(F3 r) with the attached network; r, z device complex128. */
+int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z,
+                       void* stream);
 
 /* Human-readable name of a status code. */
 const char* kc_status_string(int status);

@@ -12,7 +12,10 @@ from ._binding import (  # noqa: F401
     KC_EPS_TRIVIAL,
     KC_PREC_FP32,
     KC_PREC_FP64,
+    KC_PRECOND_DIAG,
+    KC_PRECOND_LEARNED,
     KcError,
+    Net,
     Op,
     kc_create,
     kc_fft3d,

@@ -13,6 +13,7 @@ lib_path = os.path.join(HERE, "libkcpc.so")
 KC_EPS_DIAGONAL, KC_EPS_TRIVIAL, KC_EPS_CROSSDOF = 0, 1, 2
 KC_PREC_FP64, KC_PREC_FP32 = 0, 1
 KC_OK, KC_ERR_NO_CONVERGENCE = 0, 6
+KC_PRECOND_DIAG, KC_PRECOND_LEARNED = 0, 1
 
 _lib = None
 
@@ -34,6 +35,7 @@ class KcSolveOpts(ctypes.Structure):
         ("batch_k", ctypes.c_int),
         ("seed", ctypes.c_uint64),
         ("verbose", ctypes.c_int),
+        ("precond", ctypes.c_int),
     ]
 
 
@@ -64,6 +66,19 @@ def lib():
         L.kc_last_solve_stats.argtypes = [vp, vp]
         L.kc_destroy.argtypes = [vp]
         L.kc_destroy.restype = None
+        L.kc_net_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
+        L.kc_net_param_count.argtypes = []
+        L.kc_net_param_count.restype = ctypes.c_size_t
+        L.kc_net_get_params.argtypes = [vp, vp, ctypes.c_size_t]
+        L.kc_net_set_params.argtypes = [vp, vp, ctypes.c_size_t]
+        L.kc_net_forward.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.kc_net_gradients.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+        L.kc_net_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
+        L.kc_net_destroy.argtypes = [vp]
+        L.kc_net_destroy.restype = None
+        L.kc_attach_net.argtypes = [vp, vp]
+        L.kc_net_features.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+        L.kc_precond_learned.argtypes = [vp, i32, i32, i32, vp, vp, vp]
         L.kc_status_string.argtypes = [i32]
         L.kc_status_string.restype = ctypes.c_char_p
         L.kc_last_error.argtypes = []
@@ -200,7 +215,8 @@ class Op:
 
     def solve(self, m: int, ik0: int = 0, nk: Optional[int] = None, tol: float = 1e-8, maxit: int = 500,
               prec: int = KC_PREC_FP64, switch_tol: float = 1e-3, batch_k: int = 1, guard: int = 0,
-              seed: int = 1234, X_out=None, verbose: int = 0, stream=None, check: bool = True):
+              seed: int = 1234, X_out=None, verbose: int = 0, stream=None, check: bool = True,
+              precond: int = KC_PRECOND_DIAG):
         """Smallest positive eigenvalues for k-points ik0 .. ik0+nk-1.  Returns
         (eig (nk, m), res (nk, m), iters (nk,), status)."""
         nk = self.nk - ik0 if nk is None else int(nk)
@@ -208,6 +224,7 @@ class Op:
         lib().kc_solve_opts_default(ctypes.byref(o))
         o.m, o.guard, o.tol, o.maxit, o.prec = int(m), int(guard), float(tol), int(maxit), int(prec)
         o.switch_tol, o.batch_k, o.seed, o.verbose = float(switch_tol), int(batch_k), int(seed), int(verbose)
+        o.precond = int(precond)
         eig = np.zeros((nk, m))
         res = np.zeros((nk, m))
         its = np.zeros(nk, dtype=np.int32)
@@ -223,6 +240,90 @@ class Op:
         s = np.zeros(8)
         _check(lib().kc_last_solve_stats(self._h, s.ctypes.data_as(ctypes.c_void_p)), "kc_last_solve_stats")
         return s
+
+
+    def attach_net(self, net: Optional["Net"]):
+        _check(lib().kc_attach_net(self._h, None if net is None else net._h), "kc_attach_net")
+        self._net = net  # keep the network alive while attached
+
+    def net_features(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, out=None, stream=None):
+        """Network input (bf16 [nvec][N^3][32]) for k-space vectors r (complex128 [nvec][3][N^3])."""
+        import torch
+
+        nvec = r.shape[0]
+        if out is None:
+            out = torch.empty((nvec, self.N ** 3, 32), dtype=torch.bfloat16, device=r.device)
+        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _check(lib().kc_net_features(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(r, "torch.complex128", "r"),
+                                     _dev_ptr(out, "torch.bfloat16", "feat"), _stream(stream)), "kc_net_features")
+        return out
+
+    def precond_learned(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, out=None, stream=None):
+        import torch
+
+        nvec = r.shape[0]
+        if out is None:
+            out = torch.empty_like(r)
+        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _check(lib().kc_precond_learned(self._h, int(ik0), int(nvec), max(vpk, 1),
+                                        _dev_ptr(r, "torch.complex128", "r"), _dev_ptr(out, "torch.complex128", "z"),
+                                        _stream(stream)), "kc_precond_learned")
+        return out
+
+
+class Net:
+    """Learned preconditioner network (kc_net)."""
+
+    def __init__(self, seed: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().kc_net_create(ctypes.c_uint64(int(seed)), ctypes.byref(h)), "kc_net_create")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.kc_net_destroy(h)
+            self._h = None
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().kc_net_param_count())
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.param_count(), dtype=np.float32)
+        _check(lib().kc_net_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size), "kc_net_get_params")
+        return p
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.param_count()
+        _check(lib().kc_net_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size), "kc_net_set_params")
+
+    def forward(self, x, N: int, out=None, stream=None):
+        """x: bf16 [batch][N^3][32] -> float32 [batch][N^3][16]."""
+        import torch
+
+        batch = x.shape[0]
+        if out is None:
+            out = torch.empty((batch, N ** 3, 16), dtype=torch.float32, device=x.device)
+        _check(lib().kc_net_forward(self._h, int(N), int(batch), _dev_ptr(x, "torch.bfloat16", "x"),
+                                    _dev_ptr(out, "torch.float32", "out"), _stream(stream)), "kc_net_forward")
+        return out
+
+    def gradients(self, x, target, N: int, host_grads: bool = True, stream=None):
+        """MSE loss and parameter gradients (numpy float32, or None with host_grads=False)."""
+        batch = x.shape[0]
+        loss = ctypes.c_double(0.0)
+        g = np.zeros(self.param_count(), dtype=np.float32) if host_grads else None
+        _check(lib().kc_net_gradients(self._h, int(N), int(batch), _dev_ptr(x, "torch.bfloat16", "x"),
+                                      _dev_ptr(target, "torch.float32", "target"), ctypes.byref(loss),
+                                      None if g is None else g.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+               "kc_net_gradients")
+        return loss.value, g
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+        _check(lib().kc_net_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream(stream)),
+               "kc_net_adam_step")
 
 
 def kc_create(N: int, scheme: int, ids: np.ndarray, table: np.ndarray) -> Op:

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
                                                        const c64* __restrict__ ktab64,
                                                        const double* __restrict__ gamma, int N, int kstride,
                                                        int xcol0, int wcol0, int mb, double* __restrict__ part,
-                                                       const int* __restrict__ kskip) {
+                                                       const int* __restrict__ kskip, c64* __restrict__ Rout) {
   const int b = blockIdx.z, j = blockIdx.y;
   if (kskip && kskip[b]) return;
   const size_t N3 = (size_t)N * N * N, n = 3 * N3;
@@ -231,6 +231,7 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
   const double th = theta[b * mb + j];
   const c64* K = ktab64 + (size_t)b * 3 * N;
   const double g = gamma[b];
+  c64* rout = Rout ? Rout + ((size_t)b * mb + j) * n : nullptr;
   double rr = 0.0, xx = 0.0;
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N3; p += (size_t)gridDim.x * blockDim.x) {
     const int qx = (int)(p % N), qy = (int)((p / N) % N), qz = (int)(p / ((size_t)N * N));
@@ -238,6 +239,11 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
     const c64 x1 = x[p], x2 = x[N3 + p], x3 = x[2 * N3 + p];
     const c64 r1 = ax[p] - th * x1, r2 = ax[N3 + p] - th * x2, r3 = ax[2 * N3 + p] - th * x3;
     rr += abs2(r1) + abs2(r2) + abs2(r3);
+    if (rout) {
+      rout[p] = r1;
+      rout[N3 + p] = r2;
+      rout[2 * N3 + p] = r3;
+    }
     xx += abs2(x1) + abs2(x2) + abs2(x3);
     const double s = abs2(K1) + abs2(K2) + abs2(K3);
     if (s == 0.0) {
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
 }
 
 __global__ void k_resid_reduce(const double* __restrict__ part, int nblk, int nvec, double* __restrict__ res,
-                               double* __restrict__ xnorm2) {
+                               double* __restrict__ xnorm2, double* __restrict__ rnorm2) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvec) return;
   double a = 0.0, c = 0.0;
@@ -282,6 +288,7 @@ __global__ void k_resid_reduce(const double* __restrict__ part, int nblk, int nv
   }
   res[v] = (c > 0.0) ? sqrt(a / c) : 0.0;
   if (xnorm2) xnorm2[v] = c;
+  if (rnorm2) rnorm2[v] = a;
 }
 
 // ------------------------------------------------------------------------------------
@@ -358,16 +365,16 @@ int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, i
 
 int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
                   const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
-                  double* res, double* xnorm2, const int* kskip, hipStream_t s) {
+                  double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout, double* rnorm2) {
   const size_t N3 = (size_t)N * N * N;
   const int nblk = (int)std::max<size_t>(1, std::min<size_t>((N3 + 255) / 256, 256));
   KC_TRY(part.ensure((size_t)nb * mb * nblk * 2 * sizeof(double)));
   dim3 grid(nblk, mb, nb);
   k_resid_precond<<<grid, 256, 0, s>>>(S, AS, W, theta, ktab64, gamma, N, kstride, xcol0, wcol0, mb,
-                                       part.as<double>(), kskip);
+                                       part.as<double>(), kskip, Rout);
   KC_LAUNCHED();
   const int nv = nb * mb;
-  k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2);
+  k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2, rnorm2);
   KC_LAUNCHED();
   return KC_OK;
 }

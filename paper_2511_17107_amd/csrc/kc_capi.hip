@@ -7,7 +7,7 @@
 #include <mutex>
 #include <string>
 
-#include "kc_state.h"
+#include "kc_nn.h"
 
 namespace kc {
 
@@ -239,6 +239,7 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
       }
     }
   }
+  KC_TRY(upload(op->kdev, op->kvec));
   KC_TRY(upload(op->ktab64, kt));
   KC_TRY(upload(op->ktab32, kf));
   KC_TRY(upload(op->gamma_d, op->gamma));
@@ -367,5 +368,94 @@ const char* kc_status_string(int status) {
 }
 
 const char* kc_last_error(void) { return get_error(); }
+
+// ---------------------------------------------------------------- learned preconditioner
+struct kc_net : kc::Net {};
+
+int kc_net_create(uint64_t seed, kc_net** out) {
+  KC_ARG(out != nullptr, "out is NULL");
+  kc_net* n = new kc_net();
+  int st = nn_init(n, seed);
+  if (st != KC_OK) {
+    delete n;
+    return st;
+  }
+  *out = n;
+  return KC_OK;
+}
+
+size_t kc_net_param_count(void) { return nn_param_count(); }
+
+int kc_net_get_params(const kc_net* net, float* host, size_t n) {
+  KC_ARG(net != nullptr && host != nullptr && n == nn_param_count(), "net, host buffer and size");
+  KC_HIP(hipMemcpy(host, net->params.p, n * sizeof(float), hipMemcpyDeviceToHost));
+  return KC_OK;
+}
+
+int kc_net_set_params(kc_net* net, const float* host, size_t n) {
+  KC_ARG(net != nullptr && host != nullptr && n == nn_param_count(), "net, host buffer and size");
+  KC_HIP(hipMemcpy(net->params.p, host, n * sizeof(float), hipMemcpyHostToDevice));
+  return nn_pack(net, nullptr);
+}
+
+int kc_net_forward(kc_net* net, int N, int batch, const void* in_bf16, void* out_f32, void* stream) {
+  KC_ARG(net != nullptr && in_bf16 != nullptr && out_f32 != nullptr, "NULL argument");
+  KC_ARG(N >= 16 && N % 16 == 0 && batch >= 1, "N must be a multiple of 16, batch >= 1");
+  return nn_forward(net, N, batch, (const uint16_t*)in_bf16, (float*)out_f32, (hipStream_t)stream);
+}
+
+int kc_net_gradients(kc_net* net, int N, int batch, const void* in_bf16, const void* target_f32, double* loss_host,
+                     float* grads_host, void* stream) {
+  KC_ARG(net != nullptr && in_bf16 != nullptr && target_f32 != nullptr, "NULL argument");
+  KC_ARG(N >= 16 && N % 16 == 0 && batch >= 1, "N must be a multiple of 16, batch >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  KC_TRY(nn_gradients(net, N, batch, (const uint16_t*)in_bf16, (const float*)target_f32, loss_host, s));
+  if (grads_host) {
+    KC_HIP(hipMemcpyAsync(grads_host, net->grads.p, nn_param_count() * sizeof(float), hipMemcpyDeviceToHost, s));
+    KC_HIP(hipStreamSynchronize(s));
+  }
+  return KC_OK;
+}
+
+int kc_net_adam_step(kc_net* net, float lr, float beta1, float beta2, float eps, void* stream) {
+  KC_ARG(net != nullptr && lr > 0.f, "net and lr > 0");
+  return nn_adam(net, lr, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+void kc_net_destroy(kc_net* net) { delete net; }
+
+int kc_attach_net(kc_op* op, kc_net* net) {
+  KC_ARG(op != nullptr, "op is NULL");
+  if (net) KC_ARG(op->N % 16 == 0, "the learned preconditioner needs N % 16 == 0");
+  op->net = net;
+  if (net && op->epsfeat.p == nullptr) KC_TRY(nn_build_eps_features(op));
+  return KC_OK;
+}
+
+int kc_net_features(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* feat_bf16, void* stream) {
+  KC_ARG(op != nullptr && op->net != nullptr, "op with an attached network");
+  KC_ARG(nvec >= 1 && vecs_per_k >= 1 && r != nullptr && feat_bf16 != nullptr, "arguments");
+  KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = 3 * (size_t)op->N * op->N * op->N;
+  KC_TRY(op->net->rr.ensure((size_t)nvec * sizeof(double)));
+  KC_TRY(norm2((const c64*)r, n, nvec, op->net->npart, op->net->rr.as<double>(), s));
+  return nn_features(op, ik0, nvec, vecs_per_k, (const c64*)r, op->net->rr.as<double>(), (uint16_t*)feat_bf16, s);
+}
+
+int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z, void* stream) {
+  KC_ARG(op != nullptr && op->net != nullptr, "op with an attached network");
+  KC_ARG(nvec >= 1 && vecs_per_k >= 1 && r != nullptr && z != nullptr && r != z, "arguments");
+  KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n = 3 * (size_t)op->N * op->N * op->N;
+  KC_TRY(apply_precond(op, ik0, nvec, vecs_per_k, (const c64*)r, (c64*)z, s));
+  KC_TRY(op->net->rr.ensure((size_t)nvec * sizeof(double)));
+  KC_TRY(norm2((const c64*)r, n, nvec, op->net->npart, op->net->rr.as<double>(), s));
+  VecMap vm;
+  vm.vpk = vecs_per_k;
+  vm.kstride = vecs_per_k;
+  return nn_correct(op, ik0, nvec, vecs_per_k, (const c64*)r, op->net->rr.as<double>(), (c64*)z, vm, s);
+}
 
 }  // extern "C"

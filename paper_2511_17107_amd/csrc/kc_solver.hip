@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "kc_blas.h"
+#include "kc_nn.h"
 
 namespace kc {
 
@@ -28,7 +29,8 @@ struct SolverWork {
   DevBuf S, AS;
   DevBuf part_gram, part_res;
   DevBuf GA, GB, Cu, Lsave;
-  DevBuf theta, res, xn2;
+  DevBuf theta, res, xn2, rn2;
+  DevBuf R, lmask;  // residuals and per-vector switch for the learned correction
   DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal [nb each]
 };
 
@@ -47,6 +49,7 @@ struct Batch {
   hipStream_t s;
   int *xmask, *wmask, *pmask, *pvalid, *kskip, *flags, *kglobal;
   c64 *S, *AS;
+  bool learned = false;
 };
 
 int upload_ints(int* dst, const std::vector<int>& v, hipStream_t s) {
@@ -77,10 +80,21 @@ int rayleigh_ritz(Batch& B) {
   return KC_OK;
 }
 
-int residuals(Batch& B) {
-  return resid_precond(B.S, B.AS, B.S, B.w->theta.as<double>(), B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N,
+// R, Res and W = K_P^{-1} R (+ the learned correction for the k-points whose lmask is set)
+int residuals(Batch& B, bool learned) {
+  c64* R = learned ? B.w->R.as<c64>() : nullptr;
+  double* rn2 = learned ? B.w->rn2.as<double>() : nullptr;
+  KC_TRY(resid_precond(B.S, B.AS, B.S, B.w->theta.as<double>(), B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N,
                        B.op->gamma_d.as<double>() + B.ik0, B.N, B.nc, 0, B.mb, B.mb, B.nb, B.w->part_res,
-                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s);
+                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, R, rn2));
+  if (learned) {
+    VecMap zm;
+    zm.vpk = B.mb;
+    zm.kstride = B.nc;
+    zm.active = B.w->lmask.as<int>();
+    KC_TRY(nn_correct(B.op, B.ik0, B.nb * B.mb, B.mb, R, rn2, B.S + (size_t)B.mb * B.n, zm, B.s));
+  }
+  return KC_OK;
 }
 
 int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig, double* res_out, int* iters,
@@ -110,6 +124,16 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(w->theta.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->res.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->xn2.ensure((size_t)nb * mb * sizeof(double)));
+  KC_TRY(w->rn2.ensure((size_t)nb * mb * sizeof(double)));
+  B.learned = (o.precond == KC_PRECOND_LEARNED);
+  if (B.learned) {
+    if (!op->net) {
+      set_error("learned preconditioner requested but no network is attached");
+      return KC_ERR_INVALID_ARG;
+    }
+    KC_TRY(w->R.ensure((size_t)nb * mb * colbytes));
+    KC_TRY(w->lmask.ensure((size_t)nb * mb * sizeof(int)));
+  }
   KC_TRY(w->ints.ensure((size_t)(4 * nb * mb + 3 * nb) * sizeof(int)));
   B.S = w->S.as<c64>();
   B.AS = w->AS.as<c64>();
@@ -139,7 +163,18 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   // initial block: W = K_P^{-1} (random), using the residual pass with AX = 0, theta = -1
   KC_TRY(random_block(B.S, n, nc, 0, mb, nb, o.seed, B.kglobal, s));
   KC_HIP(hipMemcpyAsync(w->theta.p, htheta.data(), htheta.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  KC_TRY(residuals(B));
+  KC_TRY(residuals(B, false));
+  // learned correction on per k-point; a k-point falls back to the diagonal preconditioner
+  // when its residual stops decreasing
+  std::vector<int> lon(nb, B.learned ? 1 : 0), hl(nb * mb, 0);
+  std::vector<double> lbest(nb, 1e300);
+  std::vector<int> lstall(nb, 0);
+  auto upload_lmask = [&]() -> int {
+    for (int b = 0; b < nb; ++b)
+      for (int j = 0; j < mb; ++j) hl[b * mb + j] = lon[b] && !done[b];
+    return upload_ints(B.w->lmask.as<int>(), hl, s);
+  };
+  if (B.learned) KC_TRY(upload_lmask());
   KC_TRY(upload_ints(B.xmask, hx, s));
   KC_TRY(upload_ints(B.wmask, hw, s));
   KC_TRY(upload_ints(B.pmask, hp, s));
@@ -157,7 +192,9 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   int stall = 0;
   bool verify_pending = false;
   while (true) {
-    KC_TRY(residuals(B));
+    bool use_learned = false;
+    for (int b = 0; b < nb; ++b) use_learned = use_learned || (lon[b] && !done[b]);
+    KC_TRY(residuals(B, use_learned));
     KC_HIP(hipMemcpyAsync(hres.data(), w->res.p, hres.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     KC_HIP(hipMemcpyAsync(hpv.data(), B.pvalid, hpv.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     KC_HIP(hipMemcpyAsync(hflags.data(), B.flags, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -216,6 +253,23 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
         cand[b] = 1;
         ++ncand;
       }
+    }
+    if (B.learned) {
+      bool changed = false;
+      for (int b = 0; b < nb; ++b) {
+        if (done[b] || !lon[b]) continue;
+        double mb_res = 0.0;
+        for (int j = 0; j < m; ++j) mb_res = std::max(mb_res, hres[b * mb + j]);
+        if (mb_res < 0.9 * lbest[b]) {
+          lbest[b] = mb_res;
+          lstall[b] = 0;
+        } else if (++lstall[b] >= 6) {
+          lon[b] = 0;  // fall back to the diagonal-block preconditioner
+          changed = true;
+          if (o.verbose) fprintf(stderr, "[kc_solve] k %d: learned preconditioner off\n", ik0 + b);
+        }
+      }
+      if (changed) KC_TRY(upload_lmask());
     }
     if (verify_pending) {
       // residuals above come from a fresh FP64 application of Op to X
@@ -315,6 +369,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   op->stats[0] += nmv64;
   op->stats[1] += nmv32;
   op->stats[3] += (double)it * nb;
+  for (int b = 0; b < nb; ++b) op->stats[4] += lon[b];  // k-points that kept the learned correction
   *all_conv = allc;
   return KC_OK;
 }
@@ -335,6 +390,7 @@ void kc_solve_opts_default(kc_solve_opts* o) {
   o->batch_k = 1;
   o->seed = 1234;
   o->verbose = 0;
+  o->precond = KC_PRECOND_DIAG;
 }
 
 int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_host, double* res_host,
@@ -347,6 +403,7 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   KC_ARG((size_t)3 * (o.m + o.guard) <= 3 * (size_t)op->N * op->N * op->N, "block larger than the space");
   KC_ARG(o.tol > 0.0 && o.maxit >= 1 && o.batch_k >= 1, "tol > 0, maxit >= 1, batch_k >= 1");
   KC_ARG(o.prec == KC_PREC_FP64 || o.prec == KC_PREC_FP32, "prec");
+  KC_ARG(o.precond == KC_PRECOND_DIAG || o.precond == KC_PRECOND_LEARNED, "precond");
   hipStream_t s = (hipStream_t)stream;
   auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < 8; ++i) op->stats[i] = 0.0;

@@ -33,6 +33,7 @@ struct DevBuf {
 };
 
 struct SolverWork;  // LOBPCG buffers (kc_solver.hip)
+struct Net;         // learned preconditioner (kc_nn.hip)
 
 // Addressing of the vectors of a block operation: vector v belongs to k-point v / vpk and is
 // column v % vpk of that k-point's group, stored at (v / vpk) * kstride + v % vpk (in units of
@@ -61,6 +62,9 @@ struct kc_op {
   kc::DevBuf gamma_d;               // double [nk]
   kc::DevBuf work_a, work_b;        // operator intermediates
   kc::SolverWork* solver = nullptr;
+  kc::Net* net = nullptr;     // attached learned preconditioner (not owned)
+  kc::DevBuf epsfeat;         // f32 [N^3][9] inverse-permittivity features for the network
+  kc::DevBuf kdev;            // double [nk][3] wave vectors
   double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
