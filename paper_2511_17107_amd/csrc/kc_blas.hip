@@ -70,15 +70,36 @@ __global__ __launch_bounds__(256) void k_gram2(const c64* __restrict__ S, const 
   const size_t r_begin = (size_t)chunk * rows_per_chunk;
   const size_t r_end = std::min(n, r_begin + rows_per_chunk);
   const int ncol2 = 2 * nc;
-  for (size_t r0 = r_begin; r0 < r_end; r0 += G2_ROWS) {
-    for (int e = threadIdx.x; e < G2_ROWS * ncol2; e += 256) {
-      const int c = e / G2_ROWS, r = e % G2_ROWS;
-      const size_t row = r0 + r;
+  constexpr int PER = (G2_ROWS * 2 * 64 + 255) / 256;  // staged entries per thread
+  c64 nxt[PER];
+  auto fetch = [&](size_t r0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * 256;
       c64 v = mk(0.0, 0.0);
-      if (row < r_end) v = (c < nc) ? Sb[(size_t)c * n + row] : ASb[(size_t)(c - nc) * n + row];
-      st[r * G2_PITCH + c] = v;
+      if (e < G2_ROWS * ncol2) {
+        const int c = e / G2_ROWS, r = e % G2_ROWS;
+        const size_t row = r0 + r;
+        if (row < r_end) v = (c < nc) ? Sb[(size_t)c * n + row] : ASb[(size_t)(c - nc) * n + row];
+      }
+      nxt[q] = v;
     }
-    __syncthreads();
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * 256;
+      if (e < G2_ROWS * ncol2) st[(e % G2_ROWS) * G2_PITCH + e / G2_ROWS] = nxt[q];
+    }
+  };
+  if (r_begin < r_end) {
+    fetch(r_begin);
+    stash();
+  }
+  __syncthreads();
+  for (size_t r0 = r_begin; r0 < r_end; r0 += G2_ROWS) {
+    const bool more = r0 + G2_ROWS < r_end;
+    if (more) fetch(r0 + G2_ROWS);  // next stage in flight while this one is multiplied
 #pragma unroll
     for (int kb = 0; kb < G2_ROWS; kb += 4) {
       const c64* srow = st + (kb + lk) * G2_PITCH;
@@ -90,12 +111,14 @@ __global__ __launch_bounds__(256) void k_gram2(const c64* __restrict__ S, const 
           const c64 av = (ca < nc) ? srow[ca] : mk(0.0, 0.0);
           const c64 bv = (cb < nc) ? srow[(tmat[t] == 0 ? nc : 0) + cb] : mk(0.0, 0.0);
           re[t] = mfma(av.re, bv.re, re[t]);
-          re[t] = mfma(av.im, bv.im, re[t]);
           im[t] = mfma(av.re, bv.im, im[t]);
+          re[t] = mfma(av.im, bv.im, re[t]);
           im[t] = mfma(av.im, -bv.re, im[t]);
         }
       }
     }
+    __syncthreads();
+    if (more) stash();
     __syncthreads();
   }
   // partial tiles: [b][chunk][tile][256], tile id = wave + 4 t
@@ -159,7 +182,8 @@ template <int TQ>
 __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64* __restrict__ C, size_t n,
                                                 int p, int q, int skstride, int scol0, int ykstride, int q1,
                                                 int ycol0, int ycol1, const int* __restrict__ kskip) {
-  extern __shared__ c64 csh[];  // C_b, p x q
+  constexpr int PK = RR_NMAX / 4;  // input columns in groups of 4 (p <= 64)
+  extern __shared__ c64 csh[];     // C_b, p x q
   const int b = blockIdx.y;
   if (kskip && kskip[b]) return;
   const c64* Cb = C + (size_t)b * p * q;
@@ -174,27 +198,34 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
   for (size_t rb = (size_t)blockIdx.x * 4 + wave; rb < nblk; rb += (size_t)gridDim.x * 4) {
     const size_t row = rb * 16 + li;
     const bool rok = row < n;
+    // all inputs of this wave's 16 rows first (many loads in flight), then the MFMAs
+    c64 sv[PK];
+#pragma unroll
+    for (int kb = 0; kb < PK; ++kb) {
+      const int c = kb * 4 + lk;
+      sv[kb] = (kb < pk && rok && c < p) ? Sb[(size_t)c * n + row] : mk(0.0, 0.0);
+    }
     d4 re[TQ], im[TQ];
 #pragma unroll
     for (int t = 0; t < TQ; ++t) {
       re[t] = d4{0, 0, 0, 0};
       im[t] = d4{0, 0, 0, 0};
     }
-    for (int kb = 0; kb < pk; ++kb) {
-      const int c = kb * 4 + lk;
-      const c64 s = (rok && c < p) ? Sb[(size_t)c * n + row] : mk(0.0, 0.0);
 #pragma unroll
-      for (int t = 0; t < TQ; ++t) {
-        const int j = t * 16 + li;
+    for (int kb = 0; kb < PK; ++kb) {
+      if (kb < pk) {
         const int ca = kb * 4 + lk;
-        const c64 cv = (ca < p && j < q) ? csh[ca * q + j] : mk(0.0, 0.0);
-        // A operand lane (i = li -> output column, k = lk -> input column): C[k][i]
-        // B operand lane (k = lk -> input column, j = li -> row): S[row][k]
-        // both use lane index li for their 16-wide dimension, lk for k.
-        re[t] = mfma(cv.re, s.re, re[t]);
-        re[t] = mfma(-cv.im, s.im, re[t]);
-        im[t] = mfma(cv.re, s.im, im[t]);
-        im[t] = mfma(cv.im, s.re, im[t]);
+#pragma unroll
+        for (int t = 0; t < TQ; ++t) {
+          const int j = t * 16 + li;
+          // A operand lane (i = li -> output column, k = lk -> input column): C[k][i];
+          // B operand lane (k = lk -> input column, j = li -> row): S[row][k]
+          const c64 cv = (ca < p && j < q) ? csh[ca * q + j] : mk(0.0, 0.0);
+          re[t] = mfma(cv.re, sv[kb].re, re[t]);
+          im[t] = mfma(cv.re, sv[kb].im, im[t]);
+          re[t] = mfma(-cv.im, sv[kb].im, re[t]);
+          im[t] = mfma(cv.im, sv[kb].re, im[t]);
+        }
       }
     }
     // output lane holds D[lk + 4r][li]: output column t*16 + lk + 4r, row rb*16 + li

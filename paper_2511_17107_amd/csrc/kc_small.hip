@@ -98,24 +98,36 @@ __device__ void conj_transpose(c64* A, int n) {
   __syncthreads();
 }
 
-// Cyclic Jacobi for the Hermitian n x n matrix A (LD), accumulating V <- V J.  A rotation of
-// the pair (p, q) with a_pq = |a_pq| u, tau = (a_qq - a_pp)/(2|a_pq|),
+// Cyclic Jacobi for the Hermitian n x n matrix A (LD) restricted to the active indices (the
+// others are isolated: zero rows and columns off the diagonal), accumulating V <- V J.  A
+// rotation of the pair (p, q) with a_pq = |a_pq| u, tau = (a_qq - a_pp)/(2|a_pq|),
 // t = sign(tau)/(|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c, uses
 // J = [[c, s u], [-s conj(u), c]] on the (p, q) plane and annihilates a_pq.  Pairs come from
-// the round-robin schedule (n-1 rounds of n/2 disjoint pairs per sweep); rotations with
-// |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) are skipped and sweeps stop when none is applied.
-__device__ void jacobi(c64* A, c64* V, int n) {
+// the round-robin schedule (na-1 rounds of na/2 disjoint pairs per sweep over the na active
+// indices); one round updates every 2x2 block A[{p_k,q_k},{p_l,q_l}] <- J_k^H A J_l at once.
+// Rotations with |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) are skipped; sweeps stop when none is applied.
+__device__ void jacobi(c64* A, c64* V, int n, const int* act) {
+  __shared__ int idx[LD];
+  __shared__ int na;
   __shared__ int pp[LD / 2], qq[LD / 2];
   __shared__ double cc[LD / 2], ss[LD / 2];
   __shared__ c64 uu[LD / 2];
   __shared__ int nrot;
-  const int ne = (n + 1) & ~1;  // even number of players (index n is a dummy when n is odd)
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int i = 0; i < n; ++i)
+      if (act[i]) idx[c++] = i;
+    na = c;
+  }
+  __syncthreads();
+  const int ne = (na + 1) & ~1;  // even number of players (position na is a dummy when na is odd)
   const int half = ne / 2;
+  if (ne < 2) return;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) nrot = 0;
     __syncthreads();
     for (int r = 0; r < ne - 1; ++r) {
-      // circle method: player ne-1 fixed, pairs (r, ne-1) and ((r+k) mod (ne-1), (r-k) mod (ne-1))
+      // circle method: position ne-1 fixed, pairs (r, ne-1) and ((r+k) mod (ne-1), (r-k) mod (ne-1))
       for (int k = threadIdx.x; k < half; k += blockDim.x) {
         int a, b;
         if (k == 0) {
@@ -125,10 +137,11 @@ __device__ void jacobi(c64* A, c64* V, int n) {
           a = (r + k) % (ne - 1);
           b = (r - k + (ne - 1)) % (ne - 1);
         }
-        int p = min(a, b), q = max(a, b);
+        const int lo = min(a, b), hi = max(a, b);
+        int p = idx[lo], q = (hi < na) ? idx[hi] : -1;  // q < 0: p is paired with the dummy
         double c = 1.0, s = 0.0;
         c64 u = mk(1.0, 0.0);
-        if (q < n) {
+        if (q >= 0) {
           const c64 apq = A[p * LD + q];
           const double g = sqrt(abs2(apq));
           const double app = A[p * LD + p].re, aqq = A[q * LD + q].re;
@@ -139,8 +152,6 @@ __device__ void jacobi(c64* A, c64* V, int n) {
             s = t * c;
             u = mk(apq.re / g, apq.im / g);
             atomicAdd(&nrot, 1);
-          } else {
-            q = n;  // mark as no-op
           }
         }
         pp[k] = p;
@@ -150,40 +161,43 @@ __device__ void jacobi(c64* A, c64* V, int n) {
         uu[k] = u;
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J
+      // all 2x2 blocks at once: B <- J_k^H B J_l (rows of pair k, columns of pair l)
+      for (int e = threadIdx.x; e < half * half; e += blockDim.x) {
+        const int k = e / half, l = e % half;
+        const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
+        const double ck = cc[k], sk = ss[k], cl = cc[l], sl = ss[l];
+        const c64 uk = uu[k], ul = uu[l];
+        c64 b00 = A[pk * LD + pl];
+        c64 b01 = (ql >= 0) ? A[pk * LD + ql] : mk(0.0, 0.0);
+        c64 b10 = (qk >= 0) ? A[qk * LD + pl] : mk(0.0, 0.0);
+        c64 b11 = (qk >= 0 && ql >= 0) ? A[qk * LD + ql] : mk(0.0, 0.0);
+        // columns: B J_l
+        const c64 c00 = cl * b00 - sl * cmulc(ul, b01), c01 = sl * (ul * b00) + cl * b01;
+        const c64 c10 = cl * b10 - sl * cmulc(ul, b11), c11 = sl * (ul * b10) + cl * b11;
+        // rows: J_k^H (.)
+        c64 d00 = ck * c00 - sk * (uk * c10), d01 = ck * c01 - sk * (uk * c11);
+        c64 d10 = sk * cmulc(uk, c00) + ck * c10, d11 = sk * cmulc(uk, c01) + ck * c11;
+        if (k == l) {  // the rotated pair: exact zero off the diagonal, real diagonal
+          d00 = mk(d00.re, 0.0);
+          d11 = mk(d11.re, 0.0);
+          d01 = mk(0.0, 0.0);
+          d10 = mk(0.0, 0.0);
+        }
+        A[pk * LD + pl] = d00;
+        if (ql >= 0) A[pk * LD + ql] = d01;
+        if (qk >= 0) A[qk * LD + pl] = d10;
+        if (qk >= 0 && ql >= 0) A[qk * LD + ql] = d11;
+      }
+      // eigenvectors: V <- V J (all rows)
       for (int e = threadIdx.x; e < half * n; e += blockDim.x) {
-        const int k = e / n, i = e % n;
-        const int p = pp[k], q = qq[k];
-        if (q >= n) continue;
-        const double c = cc[k], s = ss[k];
-        const c64 u = uu[k];
-        const c64 ap = A[i * LD + p], aq = A[i * LD + q];
-        A[i * LD + p] = c * ap - s * cmulc(u, aq);  // c a_p - s conj(u) a_q
-        A[i * LD + q] = s * (u * ap) + c * aq;
+        const int l = e / n, i = e % n;
+        const int p = pp[l], q = qq[l];
+        if (q < 0) continue;
+        const double c = cc[l], s = ss[l];
+        const c64 u = uu[l];
         const c64 vp = V[i * LD + p], vq = V[i * LD + q];
         V[i * LD + p] = c * vp - s * cmulc(u, vq);
         V[i * LD + q] = s * (u * vp) + c * vq;
-      }
-      __syncthreads();
-      // rows: A <- J^H A, J^H = [[c, -s u], [s conj(u), c]]
-      for (int e = threadIdx.x; e < half * n; e += blockDim.x) {
-        const int k = e / n, j = e % n;
-        const int p = pp[k], q = qq[k];
-        if (q >= n) continue;
-        const double c = cc[k], s = ss[k];
-        const c64 u = uu[k];
-        const c64 ap = A[p * LD + j], aq = A[q * LD + j];
-        A[p * LD + j] = c * ap - s * (u * aq);
-        A[q * LD + j] = s * cmulc(u, ap) + c * aq;
-      }
-      __syncthreads();
-      for (int k = threadIdx.x; k < half; k += blockDim.x) {
-        const int p = pp[k], q = qq[k];
-        if (q >= n) continue;
-        A[p * LD + q] = mk(0.0, 0.0);
-        A[q * LD + p] = mk(0.0, 0.0);
-        A[p * LD + p] = mk(A[p * LD + p].re, 0.0);
-        A[q * LD + q] = mk(A[q * LD + q].re, 0.0);
       }
       __syncthreads();
     }
@@ -300,7 +314,7 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
     Bm[i * LD + j] = (i == j) ? mk(1.0, 0.0) : mk(0.0, 0.0);
   }
   __syncthreads();
-  jacobi(Am, Bm, n);
+  jacobi(Am, Bm, n, act);
   // ascending order by rank (ties by index)
   for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = Am[i * LD + i].re;
   __syncthreads();
