@@ -209,7 +209,10 @@ int kc_attach_net(kc_op* op, kc_net* net);
  * residual F3 r scaled by sqrt(3 N^3)/|r| plus the fixed channels; feat_bf16 [nvec][N^3][32]. */
 int kc_net_features(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* feat_bf16,
                     void* stream);
-/* z = K_P^{-1} r + F3^H net(F3 r) with the attached network; r, z device complex128. */
+/* z = K_P^{-1} r + F3^H net(F3 r) |K_P^{-1} r| / sqrt(3 N^3) with the attached network (the
+ * network's 6 output channels are the real and imaginary parts of the correction's three
+ * components in units of the diagonal-block preconditioned residual); the correction is left out
+ * at frequencies where K_P is singular (the DC term at k = 0).  r, z device complex128. */
 int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z,
                        void* stream);
 

@@ -450,12 +450,13 @@ int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void*
   hipStream_t s = (hipStream_t)stream;
   const size_t n = 3 * (size_t)op->N * op->N * op->N;
   KC_TRY(apply_precond(op, ik0, nvec, vecs_per_k, (const c64*)r, (c64*)z, s));
+  // the network reads z = K_P^{-1} r (through its real-space copy) before z is corrected in place
   KC_TRY(op->net->rr.ensure((size_t)nvec * sizeof(double)));
-  KC_TRY(norm2((const c64*)r, n, nvec, op->net->npart, op->net->rr.as<double>(), s));
+  KC_TRY(norm2((const c64*)z, n, nvec, op->net->npart, op->net->rr.as<double>(), s));
   VecMap vm;
   vm.vpk = vecs_per_k;
   vm.kstride = vecs_per_k;
-  return nn_correct(op, ik0, nvec, vecs_per_k, (const c64*)r, op->net->rr.as<double>(), (c64*)z, vm, s);
+  return nn_correct(op, ik0, nvec, vecs_per_k, (const c64*)z, op->net->rr.as<double>(), (c64*)z, vm, s);
 }
 
 }  // extern "C"

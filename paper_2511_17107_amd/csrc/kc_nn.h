@@ -25,8 +25,9 @@ int nn_gradients(Net* net, int N, int batch, const uint16_t* in, const float* ta
                  hipStream_t s);
 int nn_adam(Net* net, float lr, float b1, float b2, float eps, hipStream_t s);
 int norm2(const c64* r, size_t n, int nvec, DevBuf& part, double* out, hipStream_t s);
-int nn_features(kc_op* op, int ik0, int nvec, int vpk, const c64* R, const double* rr, uint16_t* F, hipStream_t s);
-int nn_correct(kc_op* op, int ik0, int nvec, int vpk, const c64* R, const double* rr, c64* z, const VecMap& zmap,
+int nn_features(kc_op* op, int ik0, int nvec, int vpk, const c64* V, const double* vv, uint16_t* F,
+                hipStream_t s);
+int nn_correct(kc_op* op, int ik0, int nvec, int vpk, const c64* V, const double* vv, c64* z, const VecMap& zmap,
                hipStream_t s);
 int nn_build_eps_features(kc_op* op);
 

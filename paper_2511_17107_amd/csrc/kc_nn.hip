@@ -280,8 +280,8 @@ __global__ void k_unpack_grad(const float* __restrict__ gpad, int co_n, int ci_n
 // ------------------------------------------------------------------------------------
 // features and correction (k-space <-> network)
 // ------------------------------------------------------------------------------------
-// R (real space, unnormalised inverse DFT of the k-space residual), scale per vector ->
-// bf16 [B][N3][32]: r (6), inverse-permittivity features (9), k/pi (3), zeros.
+// V (real space, unnormalised inverse DFT of the k-space input vectors), scale per vector ->
+// bf16 [B][N3][32]: v (6), inverse-permittivity features (9), k/pi (3), zeros.
 __global__ void k_features(const c64* __restrict__ Rr, const float* __restrict__ epsf,
                            const double* __restrict__ scale, const double* __restrict__ kv, int vpk, int N,
                            int nvec, uint16_t* __restrict__ F) {
@@ -346,12 +346,13 @@ __global__ void k_add_vecs(c64* __restrict__ z, const c64* __restrict__ a, int N
   }
 }
 
-// scale_in[v] = sqrt(3)/|r_v|, scale_out[v] = |r_v| / (sqrt(3) N^3), from |r_v|^2
-__global__ void k_scales(const double* __restrict__ rr, int nvec, double N3, double* __restrict__ sin_,
+// scale_in[v] = sqrt(3)/|v_v| and scale_out[v] = |v_v| / (sqrt(3) N^3) from |v_v|^2: the network
+// sees the input in units of its RMS value, and its output is measured in the same units
+__global__ void k_scales(const double* __restrict__ vv, int nvec, double N3, double* __restrict__ sin_,
                          double* __restrict__ sout) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvec) return;
-  const double r = sqrt(rr[v]);
+  const double r = sqrt(vv[v]);
   sin_[v] = (r > 0.0) ? 1.7320508075688772 / r : 0.0;
   sout[v] = r / (1.7320508075688772 * N3);
 }
@@ -554,16 +555,17 @@ int norm2(const c64* r, size_t n, int nvec, DevBuf& part, double* out, hipStream
 
 int fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, const void* tw, hipStream_t s);
 
-// features of contiguous k-space residuals R [nvec][3][N3] (|r|^2 given in rr, device)
-int nn_features(kc_op* op, int ik0, int nvec, int vpk, const c64* R, const double* rr, uint16_t* F, hipStream_t s) {
+// features of contiguous k-space vectors V [nvec][3][N3] (|v|^2 given in vv, device)
+int nn_features(kc_op* op, int ik0, int nvec, int vpk, const c64* V, const double* vv, uint16_t* F,
+                hipStream_t s) {
   Net* net = op->net;
   const int N = op->N;
   const size_t N3 = (size_t)N * N * N;
   KC_TRY(net->rreal.ensure((size_t)nvec * 3 * N3 * sizeof(c64)));
   KC_TRY(net->scales.ensure((size_t)nvec * 2 * sizeof(double)));
-  KC_TRY(fft3d(N, 3 * nvec, +1, KC_PREC_FP64, R, net->rreal.p, op->tw64.p, s));
+  KC_TRY(fft3d(N, 3 * nvec, +1, KC_PREC_FP64, V, net->rreal.p, op->tw64.p, s));
   double* sin_ = net->scales.as<double>();
-  k_scales<<<(nvec + 255) / 256, 256, 0, s>>>(rr, nvec, (double)N3, sin_, sin_ + nvec);
+  k_scales<<<(nvec + 255) / 256, 256, 0, s>>>(vv, nvec, (double)N3, sin_, sin_ + nvec);
   KC_LAUNCHED();
   const unsigned g = (unsigned)std::min<size_t>((N3 * nvec + 255) / 256, 65535);
   k_features<<<g, 256, 0, s>>>(net->rreal.as<c64>(), op->epsfeat.as<float>(), sin_,
@@ -572,15 +574,16 @@ int nn_features(kc_op* op, int ik0, int nvec, int vpk, const c64* R, const doubl
   return KC_OK;
 }
 
-// z[v] += learned correction for residuals R (contiguous), rr = |r_v|^2 (device)
-int nn_correct(kc_op* op, int ik0, int nvec, int vpk, const c64* R, const double* rr, c64* z, const VecMap& zmap,
+// z[v] += F3^H net(features of V) * |v_v| / (sqrt(3) N^3) for the diagonal-block preconditioned
+// residuals V (contiguous, |v|^2 in vv) whose strided copies z are corrected in place
+int nn_correct(kc_op* op, int ik0, int nvec, int vpk, const c64* V, const double* vv, c64* z, const VecMap& zmap,
                hipStream_t s) {
   Net* net = op->net;
   const int N = op->N;
   const size_t N3 = (size_t)N * N * N;
   KC_TRY(net->feat.ensure((size_t)nvec * N3 * 32 * 2));
   KC_TRY(net->out.ensure((size_t)nvec * N3 * 16 * 4));
-  KC_TRY(nn_features(op, ik0, nvec, vpk, R, rr, net->feat.as<uint16_t>(), s));
+  KC_TRY(nn_features(op, ik0, nvec, vpk, V, vv, net->feat.as<uint16_t>(), s));
   KC_TRY(nn_forward(net, N, nvec, net->feat.as<uint16_t>(), net->out.as<float>(), s));
   const double* sout = net->scales.as<double>() + nvec;
   const unsigned g = (unsigned)std::min<size_t>((N3 * nvec + 255) / 256, 65535);

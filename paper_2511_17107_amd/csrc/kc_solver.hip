@@ -29,8 +29,8 @@ struct SolverWork {
   DevBuf S, AS;
   DevBuf part_gram, part_res;
   DevBuf GA, GB, Cu, Lsave;
-  DevBuf theta, res, xn2, rn2;
-  DevBuf R, lmask;  // residuals and per-vector switch for the learned correction
+  DevBuf theta, res, xn2, wn2;
+  DevBuf R, lmask;  // copy of W (the network's input) and per-vector switch for the learned correction
   DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal [nb each]
 };
 
@@ -80,19 +80,20 @@ int rayleigh_ritz(Batch& B) {
   return KC_OK;
 }
 
-// R, Res and W = K_P^{-1} R (+ the learned correction for the k-points whose lmask is set)
+// Res and W = K_P^{-1} R (+ the learned correction, computed from a contiguous copy of W, for
+// the k-points whose lmask is set)
 int residuals(Batch& B, bool learned) {
-  c64* R = learned ? B.w->R.as<c64>() : nullptr;
-  double* rn2 = learned ? B.w->rn2.as<double>() : nullptr;
+  c64* Wc = learned ? B.w->R.as<c64>() : nullptr;
+  double* wn2 = learned ? B.w->wn2.as<double>() : nullptr;
   KC_TRY(resid_precond(B.S, B.AS, B.S, B.w->theta.as<double>(), B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N,
                        B.op->gamma_d.as<double>() + B.ik0, B.N, B.nc, 0, B.mb, B.mb, B.nb, B.w->part_res,
-                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, R, rn2));
+                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, Wc, nullptr, wn2));
   if (learned) {
     VecMap zm;
     zm.vpk = B.mb;
     zm.kstride = B.nc;
     zm.active = B.w->lmask.as<int>();
-    KC_TRY(nn_correct(B.op, B.ik0, B.nb * B.mb, B.mb, R, rn2, B.S + (size_t)B.mb * B.n, zm, B.s));
+    KC_TRY(nn_correct(B.op, B.ik0, B.nb * B.mb, B.mb, Wc, wn2, B.S + (size_t)B.mb * B.n, zm, B.s));
   }
   return KC_OK;
 }
@@ -124,7 +125,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(w->theta.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->res.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->xn2.ensure((size_t)nb * mb * sizeof(double)));
-  KC_TRY(w->rn2.ensure((size_t)nb * mb * sizeof(double)));
+  KC_TRY(w->wn2.ensure((size_t)nb * mb * sizeof(double)));
   B.learned = (o.precond == KC_PRECOND_LEARNED);
   if (B.learned) {
     if (!op->net) {
@@ -165,7 +166,8 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_HIP(hipMemcpyAsync(w->theta.p, htheta.data(), htheta.size() * sizeof(double), hipMemcpyHostToDevice, s));
   KC_TRY(residuals(B, false));
   // learned correction on per k-point; a k-point falls back to the diagonal preconditioner
-  // when its residual stops decreasing
+  // when the geometric mean of its band residuals (each floored at tol) stops decreasing or
+  // grows
   std::vector<int> lon(nb, B.learned ? 1 : 0), hl(nb * mb, 0);
   std::vector<double> lbest(nb, 1e300);
   std::vector<int> lstall(nb, 0);
@@ -258,12 +260,13 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       bool changed = false;
       for (int b = 0; b < nb; ++b) {
         if (done[b] || !lon[b]) continue;
-        double mb_res = 0.0;
-        for (int j = 0; j < m; ++j) mb_res = std::max(mb_res, hres[b * mb + j]);
-        if (mb_res < 0.9 * lbest[b]) {
-          lbest[b] = mb_res;
+        double lg = 0.0;
+        for (int j = 0; j < m; ++j) lg += std::log(std::max(hres[b * mb + j], o.tol));
+        const double gm = std::exp(lg / m);
+        if (gm < 0.95 * lbest[b]) {
+          lbest[b] = gm;
           lstall[b] = 0;
-        } else if (++lstall[b] >= 6) {
+        } else if (++lstall[b] >= 8 || gm > 100.0 * lbest[b]) {
           lon[b] = 0;  // fall back to the diagonal-block preconditioner
           changed = true;
           if (o.verbose) fprintf(stderr, "[kc_solve] k %d: learned preconditioner off\n", ik0 + b);
