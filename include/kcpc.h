@@ -134,8 +134,37 @@ int kc_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void
  */
 int kc_fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, void* stream);
 
-/* Preconditioner of kc_solve. */
-enum { KC_PRECOND_DIAG = 0, KC_PRECOND_LEARNED = 1 };
+/*
+ * z = T_E r, the transverse-projection preconditioner (not part of the paper's method; the
+ * classical planewave choice of Johnson & Joannopoulos, Opt. Express 8 (2001) 173, carried over
+ * to the operator of Prop 2.8):
+ *   T_E = K_A^{+H} F3^H E F3 K_A^{+} + (gamma K_B)^{+}
+ * with K_A, K_B of eq (2.29), ^+ the Moore-Penrose pseudo-inverse per frequency, and E a
+ * positive diagonal field on the edge points (component c scales the c-edge values).  Since
+ * K_A^{+} = K_A^H / s with s = |K_1|^2 + |K_2|^2 + |K_3|^2, it costs one pass over the
+ * operator's FFT pipeline.  With E = 1 it equals K_P^{-1} (kc_precond); with E = eps^{-1}
+ * pointwise inverted it inverts Op exactly for a homogeneous isotropic medium.
+ *   efield : NULL for E_c = 1/(eps^-1)_cc at the c-edge points, or device float32
+ *            [nk_used][3][N^3] with one field per k-point of the call (nk_used =
+ *            (nvec - 1) / vecs_per_k + 1)
+ *   prec   : KC_PREC_FP64 or KC_PREC_FP32 arithmetic of the transforms
+ * r, z: device complex128 [nvec][3][N^3], must not overlap.  Zero where K_P is singular.
+ */
+int kc_precond_transverse(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z,
+                          const float* efield, int prec, void* stream);
+
+/*
+ * Gradient of sum_j w_j Re<e_j, T_E r_j> with respect to the field E, accumulated (+=) into
+ * g (device float32 [nvec / vecs_per_k][3][N^3], one field per k-point): for training the
+ * learned field.  r, e device complex128 [nvec][3][N^3]; w device float64 [nvec].
+ */
+int kc_tp_grad(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, const void* e,
+               const double* w, float* g, void* stream);
+
+/* Preconditioner of kc_solve: the diagonal-block K_P^{-1} of eqs (2.31)-(2.32), T_E with the
+ * learned field (needs kc_attach_net; a k-point whose residuals stall falls back to K_P^{-1}),
+ * or T_E with E_c = 1/(eps^-1)_cc. */
+enum { KC_PRECOND_DIAG = 0, KC_PRECOND_LEARNED = 1, KC_PRECOND_TRANSVERSE = 2 };
 
 /* Solver options for kc_solve (LOBPCG with soft locking, Section 4). */
 typedef struct kc_solve_opts {
@@ -150,7 +179,7 @@ typedef struct kc_solve_opts {
   int batch_k;        /* k-points solved together in one set of launches (>= 1)            */
   uint64_t seed;      /* seed of the random initial block                                  */
   int verbose;        /* 1: print per-iteration residuals to stderr                        */
-  int precond;        /* KC_PRECOND_DIAG, or KC_PRECOND_LEARNED (needs kc_attach_net)      */
+  int precond;        /* KC_PRECOND_DIAG, _TRANSVERSE or _LEARNED (needs kc_attach_net)    */
 } kc_solve_opts;
 
 /* Fill opts with defaults (m = 10, guard = 0, tol = 1e-8, maxit = 500, FP64, batch_k = 1). */
@@ -170,8 +199,8 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
              double* res_host, int* iters_host, void* X_out, void* stream);
 
 /* Statistics of the last kc_solve: float64 [8] = {matvecs FP64 (vector count), matvecs FP32,
- * seconds total, iterations (sum over k-points), k-points that kept the learned correction
- * to the end, 0, 0, 0}. */
+ * seconds total, iterations (sum over k-points), k-points that kept the transverse or learned
+ * preconditioner to the end, preconditioner applications (vector count), 0, 0}. */
 int kc_last_solve_stats(const kc_op* op, double* stats_host);
 
 /* Release the handle and every device buffer it owns.  NULL is allowed. */
@@ -179,14 +208,16 @@ void kc_destroy(kc_op* op);
 
 /*
  * Learned preconditioner.  A three-layer periodic 3D convolution network (3x3x3 kernels,
- * 18 -> 32 -> 32 -> 6 channels, leaky ReLU slope 0.01, BF16 weights and activations with FP32
- * accumulation) maps the normalised real-space residual F3 r (6 channels), the inverse
- * permittivity (9 channels: diagonal at the x/y/z-edge points, Re/Im of the upper off-diagonals
- * at the volume point) and k/pi (3 channels) to a correction of the diagonal-block
- * preconditioner of eqs (2.31)-(2.32): z = K_P^{-1} r + F3^H net(F3 r).  Grids need N % 16 == 0.
+ * 15 -> 32 -> 32 -> 3 channels, leaky ReLU slope 0.01, BF16 weights and activations with FP32
+ * accumulation) maps the dielectric structure and the wave vector to the field of T_E
+ * (kc_precond_transverse): E_c = E0_c exp(clamp(y_c, -3, 3)) with E0_c = 1/(eps^-1)_cc at the
+ * c-edge points and y the network output.  Input channels per cell: the inverse permittivity
+ * (9: diagonal at the x/y/z-edge points, Re/Im of the upper off-diagonals at the volume point),
+ * log E0 (3) and k/pi (3).  The network runs once per k-point and solve.  Grids need
+ * N % 16 == 0.
  *
- * Tensors: network input bf16 [batch][N^3][32] (channels-last, channels 18..31 zero), output
- * float32 [batch][N^3][16] (channels 6..15 zero); parameters float32 in the order
+ * Tensors: network input bf16 [batch][N^3][32] (channels-last, channels 15..31 zero), output
+ * float32 [batch][N^3][16] (channels 3..15 zero); parameters float32 in the order
  * W1 b1 W2 b2 W3 b3 with W[co][ci][dz][dy][dx] (tap offsets d-1, circular) and b[co].
  */
 typedef struct kc_net kc_net;
@@ -195,25 +226,28 @@ size_t kc_net_param_count(void);
 int kc_net_get_params(const kc_net* net, float* host, size_t n);
 int kc_net_set_params(kc_net* net, const float* host, size_t n);
 int kc_net_forward(kc_net* net, int N, int batch, const void* in_bf16, void* out_f32, void* stream);
-/* Mean-squared-error loss over the 6 output channels and its gradient for every parameter
+/* Mean-squared-error loss over the 3 output channels and its gradient for every parameter
  * (grads_host float32 [kc_net_param_count()] or NULL to keep them on the device for
  * kc_net_adam_step).  Blocks until done. */
 int kc_net_gradients(kc_net* net, int N, int batch, const void* in_bf16, const void* target_f32,
                      double* loss_host, float* grads_host, void* stream);
-/* One Adam step (Kingma & Ba) with the gradients of the last kc_net_gradients call. */
+/* Parameter gradients for a given gradient of a loss with respect to the network output
+ * (gout_f32 float32 [batch][N^3][16], channels 3..15 ignored by the weights' padding);
+ * grads_host as in kc_net_gradients.  Blocks until done. */
+int kc_net_backward(kc_net* net, int N, int batch, const void* in_bf16, const void* gout_f32,
+                    float* grads_host, void* stream);
+/* One Adam step (Kingma & Ba) with the gradients of the last kc_net_gradients/backward call. */
 int kc_net_adam_step(kc_net* net, float lr, float beta1, float beta2, float eps, void* stream);
 void kc_net_destroy(kc_net* net);
 /* Attach (or detach with NULL) a network to an operator; the operator does not own it. */
 int kc_attach_net(kc_op* op, kc_net* net);
-/* Network input of nvec k-space vectors r (device complex128 [nvec][3][N^3]): the real-space
- * residual F3 r scaled by sqrt(3 N^3)/|r| plus the fixed channels; feat_bf16 [nvec][N^3][32]. */
-int kc_net_features(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* feat_bf16,
-                    void* stream);
-/* z = K_P^{-1} r + F3^H net(F3 r) |K_P^{-1} r| / sqrt(3 N^3) with the attached network (the
- * network's 6 output channels are the real and imaginary parts of the correction's three
- * components in units of the diagonal-block preconditioned residual); the correction is left out
- * at frequencies where K_P is singular (the DC term at k = 0).  r, z device complex128. */
-int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z,
+/* Network input for k-points ik0 .. ik0+nk-1: feat_bf16 [nk][N^3][32] (no network needed). */
+int kc_net_features(kc_op* op, int ik0, int nk, void* feat_bf16, void* stream);
+/* Learned field E of k-points ik0 .. ik0+nk-1 with the attached network: float32
+ * [nk][3][N^3]. */
+int kc_net_efield(kc_op* op, int ik0, int nk, float* efield, void* stream);
+/* z = T_E r with the attached network's field (kc_net_efield then kc_precond_transverse). */
+int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z, int prec,
                        void* stream);
 
 /* Human-readable name of a status code. */

@@ -16,8 +16,10 @@ yee       explicit sparse matrices of Section 2.1 and Section 3: the circulant
           (eq (2.13)).
 kspace    the same operator expressed on k-space coefficients x = F3^H H
           (Prop 2.8, eq (2.30)) by conjugating the sparse operator with the
-          unitary DFT, the diagonal-block preconditioner (eqs (2.31)-(2.32)) and
-          a direct DFT by its definition (Lemma 2.1).
+          unitary DFT, the diagonal-block preconditioner (eqs (2.31)-(2.32)), the
+          transverse-projection preconditioner from its pseudo-inverse definition
+          (not part of the paper: Johnson & Joannopoulos 2001) and a direct DFT
+          by its definition (Lemma 2.1).
 eigs      smallest strictly positive eigenvalues of the compensated operator
           (dense LAPACK for small n, shift-invert ARPACK otherwise), with the
           k = 0 constant-field null space removed (Prop 2.5).

@@ -119,3 +119,33 @@ def direct_dft(u: np.ndarray, sign: int) -> np.ndarray:
     j = np.arange(N)
     W = np.exp(sign * 2j * math.pi * np.outer(j, j) / N)
     return u @ W.T
+
+
+def edge_permittivity(ids: np.ndarray, table: np.ndarray) -> np.ndarray:
+    """E0_c = 1 / (eps^-1)_cc of the material at the c-edge points, (3, N^3): the field of the
+    classical transverse-projection preconditioner (input lookup and a reciprocal)."""
+    P = yee.point_tensors(ids, table)
+    return np.stack([1.0 / P[c][:, c, c].real for c in range(3)])
+
+
+def transverse_precond_apply(N: int, k: Sequence[float], gamma: float, E: np.ndarray,
+                             r: np.ndarray) -> np.ndarray:
+    """z = T_E r with T_E = K_A^{+H} F3^H diag(E) F3 K_A^{+} + (gamma K_B)^{+}, the
+    transverse-projection preconditioner (Johnson & Joannopoulos, Opt. Express 8 (2001) 173)
+    written for the operator of eq (2.30): the curl part of Op with the inverse permittivity M
+    replaced by the diagonal field E, each factor inverted by its Moore-Penrose pseudo-inverse
+    per frequency (numpy.linalg.pinv), plus the pseudo-inverse of the penalty block.
+    E: real (3, N^3) on the edge points (component c scales the c-edge values), one field for
+    all vectors or (nvec, 3, N^3); r: (nvec, 3, N^3)."""
+    K = symbols_3d(N, k)
+    A = curl_symbol(K)
+    Ap = np.linalg.pinv(A, rcond=1e-12)                      # (N^3, 3, 3)
+    Bp = np.linalg.pinv(gamma * div_symbol_gram(K), rcond=1e-12)
+    r = np.asarray(r, dtype=np.complex128)
+    E = np.asarray(E, dtype=np.float64)
+    if E.ndim == 2:
+        E = np.broadcast_to(E, r.shape)
+    u = np.einsum("pab,vbp->vap", Ap, r)                     # K_A^+ r
+    u = F3H(F3(u, N) * E, N)                                 # F3^H E F3
+    z = np.einsum("pba,vbp->vap", Ap.conj(), u)              # K_A^{+H}
+    return z + np.einsum("pab,vbp->vap", Bp, r)

@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     KC_PREC_FP64,
     KC_PRECOND_DIAG,
     KC_PRECOND_LEARNED,
+    KC_PRECOND_TRANSVERSE,
     KcError,
     Net,
     Op,

@@ -13,7 +13,7 @@ lib_path = os.path.join(HERE, "libkcpc.so")
 KC_EPS_DIAGONAL, KC_EPS_TRIVIAL, KC_EPS_CROSSDOF = 0, 1, 2
 KC_PREC_FP64, KC_PREC_FP32 = 0, 1
 KC_OK, KC_ERR_NO_CONVERGENCE = 0, 6
-KC_PRECOND_DIAG, KC_PRECOND_LEARNED = 0, 1
+KC_PRECOND_DIAG, KC_PRECOND_LEARNED, KC_PRECOND_TRANSVERSE = 0, 1, 2
 
 _lib = None
 
@@ -60,6 +60,8 @@ def lib():
         L.kc_precond.argtypes = [vp, i32, i32, i32, vp, vp, vp]
         L.kc_apply_timed.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp, vp, vp]
         L.kc_fft3d.argtypes = [i32, i32, i32, i32, vp, vp, vp]
+        L.kc_precond_transverse.argtypes = [vp, i32, i32, i32, vp, vp, vp, i32, vp]
+        L.kc_tp_grad.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
         L.kc_solve_opts_default.argtypes = [ctypes.POINTER(KcSolveOpts)]
         L.kc_solve_opts_default.restype = None
         L.kc_solve.argtypes = [vp, i32, i32, ctypes.POINTER(KcSolveOpts), vp, vp, vp, vp, vp]
@@ -73,12 +75,14 @@ def lib():
         L.kc_net_set_params.argtypes = [vp, vp, ctypes.c_size_t]
         L.kc_net_forward.argtypes = [vp, i32, i32, vp, vp, vp]
         L.kc_net_gradients.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+        L.kc_net_backward.argtypes = [vp, i32, i32, vp, vp, vp, vp]
         L.kc_net_adam_step.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]
         L.kc_net_destroy.argtypes = [vp]
         L.kc_net_destroy.restype = None
         L.kc_attach_net.argtypes = [vp, vp]
-        L.kc_net_features.argtypes = [vp, i32, i32, i32, vp, vp, vp]
-        L.kc_precond_learned.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+        L.kc_net_features.argtypes = [vp, i32, i32, vp, vp]
+        L.kc_net_efield.argtypes = [vp, i32, i32, vp, vp]
+        L.kc_precond_learned.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
         L.kc_status_string.argtypes = [i32]
         L.kc_status_string.restype = ctypes.c_char_p
         L.kc_last_error.argtypes = []
@@ -213,6 +217,30 @@ class Op:
                                 _dev_ptr(out, "torch.complex128", "z"), _stream(stream)), "kc_precond")
         return out
 
+    def precond_transverse(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, efield=None,
+                           prec: int = KC_PREC_FP64, out=None, stream=None):
+        """z = T_E r; efield None (E_c = 1/(eps^-1)_cc) or float32 [nk_used][3][N^3]."""
+        import torch
+
+        nvec = r.shape[0]
+        if out is None:
+            out = torch.empty_like(r)
+        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        ef = None if efield is None else _dev_ptr(efield, "torch.float32", "efield")
+        _check(lib().kc_precond_transverse(self._h, int(ik0), int(nvec), max(vpk, 1),
+                                           _dev_ptr(r, "torch.complex128", "r"), _dev_ptr(out, "torch.complex128", "z"),
+                                           ef, int(prec), _stream(stream)), "kc_precond_transverse")
+        return out
+
+    def tp_grad(self, r, e, w, g, ik0: int = 0, vecs_per_k: Optional[int] = None, stream=None):
+        """g (float32 [nvec/vpk][3][N^3]) += d/dE sum_j w_j Re<e_j, T_E r_j> (w float64 [nvec])."""
+        nvec = r.shape[0]
+        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _check(lib().kc_tp_grad(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(r, "torch.complex128", "r"),
+                                _dev_ptr(e, "torch.complex128", "e"), _dev_ptr(w, "torch.float64", "w"),
+                                _dev_ptr(g, "torch.float32", "g"), _stream(stream)), "kc_tp_grad")
+        return g
+
     def solve(self, m: int, ik0: int = 0, nk: Optional[int] = None, tol: float = 1e-8, maxit: int = 500,
               prec: int = KC_PREC_FP64, switch_tol: float = 1e-3, batch_k: int = 1, guard: int = 0,
               seed: int = 1234, X_out=None, verbose: int = 0, stream=None, check: bool = True,
@@ -246,19 +274,28 @@ class Op:
         _check(lib().kc_attach_net(self._h, None if net is None else net._h), "kc_attach_net")
         self._net = net  # keep the network alive while attached
 
-    def net_features(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, out=None, stream=None):
-        """Network input (bf16 [nvec][N^3][32]) for k-space vectors r (complex128 [nvec][3][N^3])."""
+    def net_features(self, ik0: int = 0, nk: int = 1, out=None, stream=None):
+        """Network input (bf16 [nk][N^3][32]) of k-points ik0 .. ik0+nk-1."""
         import torch
 
-        nvec = r.shape[0]
         if out is None:
-            out = torch.empty((nvec, self.N ** 3, 32), dtype=torch.bfloat16, device=r.device)
-        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
-        _check(lib().kc_net_features(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(r, "torch.complex128", "r"),
-                                     _dev_ptr(out, "torch.bfloat16", "feat"), _stream(stream)), "kc_net_features")
+            out = torch.empty((nk, self.N ** 3, 32), dtype=torch.bfloat16, device=torch.device("cuda"))
+        _check(lib().kc_net_features(self._h, int(ik0), int(nk), _dev_ptr(out, "torch.bfloat16", "feat"),
+                                     _stream(stream)), "kc_net_features")
         return out
 
-    def precond_learned(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, out=None, stream=None):
+    def net_efield(self, ik0: int = 0, nk: int = 1, out=None, stream=None):
+        """Learned field (float32 [nk][3][N^3]) of k-points ik0 .. ik0+nk-1."""
+        import torch
+
+        if out is None:
+            out = torch.empty((nk, 3, self.N ** 3), dtype=torch.float32, device=torch.device("cuda"))
+        _check(lib().kc_net_efield(self._h, int(ik0), int(nk), _dev_ptr(out, "torch.float32", "efield"),
+                                   _stream(stream)), "kc_net_efield")
+        return out
+
+    def precond_learned(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, prec: int = KC_PREC_FP64,
+                        out=None, stream=None):
         import torch
 
         nvec = r.shape[0]
@@ -267,7 +304,7 @@ class Op:
         vpk = nvec if vecs_per_k is None else int(vecs_per_k)
         _check(lib().kc_precond_learned(self._h, int(ik0), int(nvec), max(vpk, 1),
                                         _dev_ptr(r, "torch.complex128", "r"), _dev_ptr(out, "torch.complex128", "z"),
-                                        _stream(stream)), "kc_precond_learned")
+                                        int(prec), _stream(stream)), "kc_precond_learned")
         return out
 
 
@@ -320,6 +357,16 @@ class Net:
                                       None if g is None else g.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
                "kc_net_gradients")
         return loss.value, g
+
+    def backward(self, x, gout, N: int, host_grads: bool = True, stream=None):
+        """Parameter gradients for the output gradient gout (float32 [batch][N^3][16])."""
+        batch = x.shape[0]
+        g = np.zeros(self.param_count(), dtype=np.float32) if host_grads else None
+        _check(lib().kc_net_backward(self._h, int(N), int(batch), _dev_ptr(x, "torch.bfloat16", "x"),
+                                     _dev_ptr(gout, "torch.float32", "gout"),
+                                     None if g is None else g.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+               "kc_net_backward")
+        return g
 
     def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
         _check(lib().kc_net_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream(stream)),

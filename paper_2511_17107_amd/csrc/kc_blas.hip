@@ -244,8 +244,8 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
 
 // ------------------------------------------------------------------------------------
 // Residual + preconditioner: r_j = AX_j - theta_j X_j, W_j = K_P^{-1} r_j (closed form of
-// the diagonal-block preconditioner, eqs (2.31)-(2.32)), per-block partial sums of |r_j|^2,
-// |x_j|^2 and |W_j|^2; optionally a contiguous copy of W (Wcopy, [b*mb + j][3N^3]).
+// the diagonal-block preconditioner, eqs (2.31)-(2.32)), per-block partial sums of |r_j|^2
+// and |x_j|^2; optionally a contiguous copy of r (Rout, [b*mb + j][3N^3]).
 // Grid: x = blocks per vector, y = column j, z = k-point b.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S, const c64* __restrict__ AS,
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
                                                        const c64* __restrict__ ktab64,
                                                        const double* __restrict__ gamma, int N, int kstride,
                                                        int xcol0, int wcol0, int mb, double* __restrict__ part,
-                                                       const int* __restrict__ kskip, c64* __restrict__ Wcopy) {
+                                                       const int* __restrict__ kskip, c64* __restrict__ Rout) {
   const int b = blockIdx.z, j = blockIdx.y;
   if (kskip && kskip[b]) return;
   const size_t N3 = (size_t)N * N * N, n = 3 * N3;
@@ -263,8 +263,8 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
   const double th = theta[b * mb + j];
   const c64* K = ktab64 + (size_t)b * 3 * N;
   const double g = gamma[b];
-  c64* wc = Wcopy ? Wcopy + ((size_t)b * mb + j) * n : nullptr;
-  double rr = 0.0, xx = 0.0, ww = 0.0;
+  c64* rc = Rout ? Rout + ((size_t)b * mb + j) * n : nullptr;
+  double rr = 0.0, xx = 0.0;
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N3; p += (size_t)gridDim.x * blockDim.x) {
     const int qx = (int)(p % N), qy = (int)((p / N) % N), qz = (int)(p / ((size_t)N * N));
     const c64 K1 = K[qx], K2 = K[N + qy], K3 = K[2 * N + qz];
@@ -284,50 +284,43 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
     w[p] = w1;
     w[N3 + p] = w2;
     w[2 * N3 + p] = w3;
-    if (wc) {
-      wc[p] = w1;
-      wc[N3 + p] = w2;
-      wc[2 * N3 + p] = w3;
+    if (rc) {
+      rc[p] = r1;
+      rc[N3 + p] = r2;
+      rc[2 * N3 + p] = r3;
     }
-    ww += abs2(w1) + abs2(w2) + abs2(w3);
   }
   // block reduction (fixed order)
-  __shared__ double sr[256], sx[256], sw[256];
+  __shared__ double sr[256], sx[256];
   sr[threadIdx.x] = rr;
   sx[threadIdx.x] = xx;
-  sw[threadIdx.x] = ww;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) {
       sr[threadIdx.x] += sr[threadIdx.x + o];
       sx[threadIdx.x] += sx[threadIdx.x + o];
-      sw[threadIdx.x] += sw[threadIdx.x + o];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double* o = part + (((size_t)b * mb + j) * gridDim.x + blockIdx.x) * 3;
+    double* o = part + (((size_t)b * mb + j) * gridDim.x + blockIdx.x) * 2;
     o[0] = sr[0];
     o[1] = sx[0];
-    o[2] = sw[0];
   }
 }
 
 __global__ void k_resid_reduce(const double* __restrict__ part, int nblk, int nvec, double* __restrict__ res,
-                               double* __restrict__ xnorm2, double* __restrict__ rnorm2,
-                               double* __restrict__ wnorm2) {
+                               double* __restrict__ xnorm2, double* __restrict__ rnorm2) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nvec) return;
-  double a = 0.0, c = 0.0, d = 0.0;
+  double a = 0.0, c = 0.0;
   for (int i = 0; i < nblk; ++i) {
-    a += part[((size_t)v * nblk + i) * 3];
-    c += part[((size_t)v * nblk + i) * 3 + 1];
-    d += part[((size_t)v * nblk + i) * 3 + 2];
+    a += part[((size_t)v * nblk + i) * 2];
+    c += part[((size_t)v * nblk + i) * 2 + 1];
   }
   res[v] = (c > 0.0) ? sqrt(a / c) : 0.0;
   if (xnorm2) xnorm2[v] = c;
   if (rnorm2) rnorm2[v] = a;
-  if (wnorm2) wnorm2[v] = d;
 }
 
 // ------------------------------------------------------------------------------------
@@ -404,17 +397,16 @@ int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, i
 
 int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
                   const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
-                  double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Wcopy, double* rnorm2,
-                  double* wnorm2) {
+                  double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout, double* rnorm2) {
   const size_t N3 = (size_t)N * N * N;
   const int nblk = (int)std::max<size_t>(1, std::min<size_t>((N3 + 255) / 256, 256));
-  KC_TRY(part.ensure((size_t)nb * mb * nblk * 3 * sizeof(double)));
+  KC_TRY(part.ensure((size_t)nb * mb * nblk * 2 * sizeof(double)));
   dim3 grid(nblk, mb, nb);
   k_resid_precond<<<grid, 256, 0, s>>>(S, AS, W, theta, ktab64, gamma, N, kstride, xcol0, wcol0, mb,
-                                       part.as<double>(), kskip, Wcopy);
+                                       part.as<double>(), kskip, Rout);
   KC_LAUNCHED();
   const int nv = nb * mb;
-  k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2, rnorm2, wnorm2);
+  k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2, rnorm2);
   KC_LAUNCHED();
   return KC_OK;
 }

@@ -307,6 +307,36 @@ int kc_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void
   return apply_precond(op, ik0, nvec, vecs_per_k, (const c64*)r, (c64*)z, (hipStream_t)stream);
 }
 
+int kc_precond_transverse(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z,
+                          const float* efield, int prec, void* stream) {
+  KC_ARG(op != nullptr, "op is NULL");
+  KC_ARG(op->nk > 0, "no k-points set");
+  KC_ARG(nvec >= 0 && vecs_per_k >= 1, "nvec >= 0, vecs_per_k >= 1");
+  KC_ARG(prec == KC_PREC_FP64 || prec == KC_PREC_FP32, "prec");
+  if (nvec == 0) return KC_OK;
+  KC_ARG(r != nullptr && z != nullptr, "NULL vector");
+  KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
+  const size_t n = 3 * (size_t)op->N * op->N * op->N;
+  KC_ARG((const char*)z + nvec * n * sizeof(c64) <= (const char*)r ||
+             (const char*)r + nvec * n * sizeof(c64) <= (const char*)z,
+         "r and z must not overlap");
+  KC_TRY(build_efield(op));
+  VecMap vm;
+  vm.vpk = vecs_per_k;
+  vm.kstride = vecs_per_k;
+  return apply_tp(op, ik0, nvec, vm, vm, (const c64*)r, (c64*)z, efield ? efield : op->efield.as<float>(),
+                  efield ? 1 : 0, prec, (hipStream_t)stream);
+}
+
+int kc_tp_grad(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, const void* e, const double* w,
+               float* g, void* stream) {
+  KC_ARG(op != nullptr && op->nk > 0, "op with k-points");
+  KC_ARG(nvec >= 1 && vecs_per_k >= 1 && nvec % vecs_per_k == 0, "nvec a positive multiple of vecs_per_k");
+  KC_ARG(r != nullptr && e != nullptr && w != nullptr && g != nullptr, "NULL argument");
+  KC_ARG(ik0 >= 0 && ik0 + nvec / vecs_per_k <= op->nk, "k-point index out of range");
+  return tp_grad(op, ik0, nvec, vecs_per_k, (const c64*)r, (const c64*)e, w, g, (hipStream_t)stream);
+}
+
 int kc_fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, void* stream) {
   if (!supported_n(N)) {
     set_error("unsupported N");
@@ -417,6 +447,19 @@ int kc_net_gradients(kc_net* net, int N, int batch, const void* in_bf16, const v
   return KC_OK;
 }
 
+int kc_net_backward(kc_net* net, int N, int batch, const void* in_bf16, const void* gout_f32, float* grads_host,
+                    void* stream) {
+  KC_ARG(net != nullptr && in_bf16 != nullptr && gout_f32 != nullptr, "NULL argument");
+  KC_ARG(N >= 16 && N % 16 == 0 && batch >= 1, "N must be a multiple of 16, batch >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  KC_TRY(nn_backward(net, N, batch, (const uint16_t*)in_bf16, (const float*)gout_f32, s));
+  if (grads_host) {
+    KC_HIP(hipMemcpyAsync(grads_host, net->grads.p, nn_param_count() * sizeof(float), hipMemcpyDeviceToHost, s));
+  }
+  KC_HIP(hipStreamSynchronize(s));
+  return KC_OK;
+}
+
 int kc_net_adam_step(kc_net* net, float lr, float beta1, float beta2, float eps, void* stream) {
   KC_ARG(net != nullptr && lr > 0.f, "net and lr > 0");
   return nn_adam(net, lr, beta1, beta2, eps, (hipStream_t)stream);
@@ -429,34 +472,42 @@ int kc_attach_net(kc_op* op, kc_net* net) {
   if (net) KC_ARG(op->N % 16 == 0, "the learned preconditioner needs N % 16 == 0");
   op->net = net;
   if (net && op->epsfeat.p == nullptr) KC_TRY(nn_build_eps_features(op));
+  if (net) KC_TRY(build_efield(op));
   return KC_OK;
 }
 
-int kc_net_features(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* feat_bf16, void* stream) {
-  KC_ARG(op != nullptr && op->net != nullptr, "op with an attached network");
-  KC_ARG(nvec >= 1 && vecs_per_k >= 1 && r != nullptr && feat_bf16 != nullptr, "arguments");
-  KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
-  hipStream_t s = (hipStream_t)stream;
-  const size_t n = 3 * (size_t)op->N * op->N * op->N;
-  KC_TRY(op->net->rr.ensure((size_t)nvec * sizeof(double)));
-  KC_TRY(norm2((const c64*)r, n, nvec, op->net->npart, op->net->rr.as<double>(), s));
-  return nn_features(op, ik0, nvec, vecs_per_k, (const c64*)r, op->net->rr.as<double>(), (uint16_t*)feat_bf16, s);
+int kc_net_features(kc_op* op, int ik0, int nk, void* feat_bf16, void* stream) {
+  KC_ARG(op != nullptr && op->N % 16 == 0, "op with N % 16 == 0");
+  KC_ARG(nk >= 1 && feat_bf16 != nullptr, "arguments");
+  KC_ARG(ik0 >= 0 && ik0 + nk <= op->nk, "k-point index out of range");
+  return nn_features(op, ik0, nk, (uint16_t*)feat_bf16, (hipStream_t)stream);
 }
 
-int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z, void* stream) {
+int kc_net_efield(kc_op* op, int ik0, int nk, float* efield, void* stream) {
   KC_ARG(op != nullptr && op->net != nullptr, "op with an attached network");
-  KC_ARG(nvec >= 1 && vecs_per_k >= 1 && r != nullptr && z != nullptr && r != z, "arguments");
+  KC_ARG(nk >= 1 && efield != nullptr, "arguments");
+  KC_ARG(ik0 >= 0 && ik0 + nk <= op->nk, "k-point index out of range");
+  return nn_efield(op, ik0, nk, efield, (hipStream_t)stream);
+}
+
+int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z, int prec,
+                       void* stream) {
+  KC_ARG(op != nullptr && op->net != nullptr, "op with an attached network");
+  KC_ARG(op->nk > 0 && nvec >= 1 && vecs_per_k >= 1 && r != nullptr && z != nullptr, "arguments");
+  KC_ARG(prec == KC_PREC_FP64 || prec == KC_PREC_FP32, "prec");
   KC_ARG(ik0 >= 0 && ik0 + (nvec - 1) / vecs_per_k < op->nk, "k-point index out of range");
-  hipStream_t s = (hipStream_t)stream;
   const size_t n = 3 * (size_t)op->N * op->N * op->N;
-  KC_TRY(apply_precond(op, ik0, nvec, vecs_per_k, (const c64*)r, (c64*)z, s));
-  // the network reads z = K_P^{-1} r (through its real-space copy) before z is corrected in place
-  KC_TRY(op->net->rr.ensure((size_t)nvec * sizeof(double)));
-  KC_TRY(norm2((const c64*)z, n, nvec, op->net->npart, op->net->rr.as<double>(), s));
+  KC_ARG((const char*)z + nvec * n * sizeof(c64) <= (const char*)r ||
+             (const char*)r + nvec * n * sizeof(c64) <= (const char*)z,
+         "r and z must not overlap");
+  hipStream_t s = (hipStream_t)stream;
+  const int nk = (nvec - 1) / vecs_per_k + 1;
+  KC_TRY(op->efield_k.ensure((size_t)nk * n * sizeof(float)));
+  KC_TRY(nn_efield(op, ik0, nk, op->efield_k.as<float>(), s));
   VecMap vm;
   vm.vpk = vecs_per_k;
   vm.kstride = vecs_per_k;
-  return nn_correct(op, ik0, nvec, vecs_per_k, (const c64*)z, op->net->rr.as<double>(), (c64*)z, vm, s);
+  return apply_tp(op, ik0, nvec, vm, vm, (const c64*)r, (c64*)z, op->efield_k.as<float>(), 1, prec, s);
 }
 
 }  // extern "C"

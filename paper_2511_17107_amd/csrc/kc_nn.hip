@@ -1,6 +1,10 @@
 // Learned preconditioner: a three-layer periodic 3D convolution network (3x3x3 kernels,
-// 32 hidden channels, leaky ReLU) applied to the real-space residual, whose output corrects
-// the diagonal-block preconditioner: W = K_P^{-1} r + F3^H net(F3 r) (residual learning).
+// 32 hidden channels, leaky ReLU) that maps the dielectric structure around each cell (and the
+// wave vector) to the positive diagonal field E of the transverse-projection preconditioner
+// T_E (kc_op.hip): E_c = E0_c exp(clamp(net_c, -3, 3)) with E0_c = 1/(eps^-1)_cc at the c-edge
+// points, so an untrained (near-zero) network gives the classical choice E0.  The network runs
+// once per k-point and solve; every LOBPCG iteration then applies the linear, Hermitian
+// positive semi-definite T_E.
 //
 // Numerics: BF16 weights and activations, FP32 accumulation on v_mfma_f32_16x16x16_bf16
 // (implicit GEMM: M = output channels, N = 16 positions along x, K = 27 taps x input channels),
@@ -237,6 +241,12 @@ __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// output gradient given directly (f32 -> bf16 for the backward passes)
+__global__ void k_to_bf16(const float* __restrict__ g, uint16_t* __restrict__ o, size_t count) {
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (size_t)gridDim.x * 256)
+    o[e] = f2bf(g[e]);
+}
+
 // Adam (Kingma & Ba) on FP32 master parameters
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
                        float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps, float c1,
@@ -278,33 +288,25 @@ __global__ void k_unpack_grad(const float* __restrict__ gpad, int co_n, int ci_n
 }
 
 // ------------------------------------------------------------------------------------
-// features and correction (k-space <-> network)
+// features (structure -> network) and the learned field (network -> T_E)
 // ------------------------------------------------------------------------------------
-// V (real space, unnormalised inverse DFT of the k-space input vectors), scale per vector ->
-// bf16 [B][N3][32]: v (6), inverse-permittivity features (9), k/pi (3), zeros.
-__global__ void k_features(const c64* __restrict__ Rr, const float* __restrict__ epsf,
-                           const double* __restrict__ scale, const double* __restrict__ kv, int vpk, int N,
-                           int nvec, uint16_t* __restrict__ F) {
+// bf16 [nk][N3][32] per k-point: inverse-permittivity features (9), log E0 (3), k/pi (3), zeros.
+__global__ void k_features(const float* __restrict__ epsf, const float* __restrict__ e0,
+                           const double* __restrict__ kv, int N, int nk, uint16_t* __restrict__ F) {
   const size_t N3 = (size_t)N * N * N;
-  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < N3 * nvec; t += (size_t)gridDim.x * 256) {
-    const size_t v = t / N3, p = t - v * N3;
-    const double s = scale[v];
-    const double* k = kv + 3 * (v / vpk);
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < N3 * nk; t += (size_t)gridDim.x * 256) {
+    const size_t b = t / N3, p = t - b * N3;
+    const double* k = kv + 3 * b;
     uint16_t* o = F + t * 32;
-    const c64* r = Rr + v * 3 * N3;
     float ch[32];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const c64 z = r[c * N3 + p];
-      ch[2 * c] = (float)(z.re * s);
-      ch[2 * c + 1] = (float)(z.im * s);
-    }
+    for (int c = 0; c < 9; ++c) ch[c] = epsf[p * 9 + c];
 #pragma unroll
-    for (int c = 0; c < 9; ++c) ch[6 + c] = epsf[p * 9 + c];
+    for (int c = 0; c < 3; ++c) ch[9 + c] = logf(e0[c * N3 + p]);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ch[15 + c] = (float)(k[c] * 0.31830988618379067);
+    for (int c = 0; c < 3; ++c) ch[12 + c] = (float)(k[c] * 0.31830988618379067);
 #pragma unroll
-    for (int c = 18; c < 32; ++c) ch[c] = 0.f;
+    for (int c = 15; c < 32; ++c) ch[c] = 0.f;
 #pragma unroll
     for (int c = 0; c < 32; c += 4) {
       uint2 w;
@@ -315,70 +317,18 @@ __global__ void k_features(const c64* __restrict__ Rr, const float* __restrict__
   }
 }
 
-// delta (f32 [B][N3][16], channels re/im of 3 components) * scale -> complex [B][3][N3]
-__global__ void k_delta_to_field(const float* __restrict__ D, const double* __restrict__ scale, int N, int nvec,
-                                 c64* __restrict__ out) {
+// E[b][c][p] = E0[c][p] exp(clamp(y[b][p][c], -3, 3)) from the network output y (f32 [nk][N3][16])
+__global__ void k_efield(const float* __restrict__ y, const float* __restrict__ e0, int N, int nk,
+                         float* __restrict__ E) {
   const size_t N3 = (size_t)N * N * N;
-  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < N3 * nvec; t += (size_t)gridDim.x * 256) {
-    const size_t v = t / N3, p = t - v * N3;
-    const double s = scale[v];
-    const float* d = D + t * 16;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < N3 * nk; t += (size_t)gridDim.x * 256) {
+    const size_t b = t / N3, p = t - b * N3;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) out[(v * 3 + c) * N3 + p] = mk((double)d[2 * c] * s, (double)d[2 * c + 1] * s);
+    for (int c = 0; c < 3; ++c) {
+      const float o = fminf(fmaxf(y[t * 16 + c], -3.f), 3.f);
+      E[(b * 3 + c) * N3 + p] = e0[c * N3 + p] * expf(o);
+    }
   }
-}
-
-// z[v] (strided by VecMap) += a[v] (contiguous), except at frequencies where K_P is singular
-// (the DC frequency at k = 0): there the correction is dropped so that the constant fields of
-// Prop 2.5 (1) stay out of the search space, as with the diagonal-block preconditioner.
-__global__ void k_add_vecs(c64* __restrict__ z, const c64* __restrict__ a, int N, int nvec, VecMap vm,
-                           const c64* __restrict__ ktab64) {
-  const size_t N3 = (size_t)N * N * N, n = 3 * N3;
-  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < n * nvec; t += (size_t)gridDim.x * 256) {
-    const size_t v = t / n, i = t - v * n;
-    if (!vm.on((int)v)) continue;
-    const size_t p = i % N3;
-    const c64* K = ktab64 + (size_t)(v / vm.vpk) * 3 * N;
-    const int qx = (int)(p % N), qy = (int)((p / N) % N), qz = (int)(p / ((size_t)N * N));
-    if (abs2(K[qx]) + abs2(K[N + qy]) + abs2(K[2 * N + qz]) == 0.0) continue;
-    c64* zv = z + vm.off((int)v) * n;
-    zv[i] = zv[i] + a[t];
-  }
-}
-
-// scale_in[v] = sqrt(3)/|v_v| and scale_out[v] = |v_v| / (sqrt(3) N^3) from |v_v|^2: the network
-// sees the input in units of its RMS value, and its output is measured in the same units
-__global__ void k_scales(const double* __restrict__ vv, int nvec, double N3, double* __restrict__ sin_,
-                         double* __restrict__ sout) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nvec) return;
-  const double r = sqrt(vv[v]);
-  sin_[v] = (r > 0.0) ? 1.7320508075688772 / r : 0.0;
-  sout[v] = r / (1.7320508075688772 * N3);
-}
-
-// |r_v|^2 for contiguous vectors (fixed-order block sums, then per-vector sum)
-__global__ void k_norm2(const c64* __restrict__ r, size_t n, double* __restrict__ part, int nblk) {
-  __shared__ double sh[256];
-  const int v = blockIdx.y;
-  const c64* rv = r + (size_t)v * n;
-  double s = 0.0;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)nblk * 256) s += abs2(rv[i]);
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[(size_t)v * nblk + blockIdx.x] = sh[0];
-}
-
-__global__ void k_sum_rows(const double* __restrict__ part, int nblk, int nvec, double* __restrict__ out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nvec) return;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)v * nblk + b];
-  out[v] = s;
 }
 
 // ------------------------------------------------------------------------------------
@@ -409,7 +359,7 @@ int nn_init(Net* net, uint64_t seed) {
     const size_t off = layer_offset(l);
     const int fan_in = LAYER_CI[l] * 27;
     // He-normal for the hidden layers; the last layer starts near zero so that the learned
-    // preconditioner starts as the diagonal one
+    // field starts as E0
     const double sd = (l < 2) ? std::sqrt(2.0 / fan_in) : 1e-3 / std::sqrt((double)fan_in);
     std::normal_distribution<double> nd(0.0, sd);
     for (size_t i = 0; i < (size_t)LAYER_CO[l] * LAYER_CI[l] * 27; ++i) p[off + i] = (float)nd(rng);
@@ -481,22 +431,11 @@ static int wgrad(const uint16_t* X, const uint16_t* GZ, int N, int batch, DevBuf
   return KC_OK;
 }
 
-int nn_gradients(Net* net, int N, int batch, const uint16_t* in, const float* target, double* loss_host,
-                 hipStream_t s) {
+// backward pass from the bf16 output gradient in net->g3 (forward activations in h1, h2)
+static int nn_backward_g3(Net* net, int N, int batch, const uint16_t* in, hipStream_t s) {
   const size_t N3 = (size_t)N * N * N;
-  KC_TRY(net->out.ensure((size_t)batch * N3 * 16 * 4));
-  float* y = net->out.as<float>();
-  KC_TRY(nn_forward(net, N, batch, in, y, s));
-  KC_TRY(net->g3.ensure((size_t)batch * N3 * 16 * 2));
   KC_TRY(net->g2.ensure((size_t)batch * N3 * 32 * 2));
   KC_TRY(net->g1.ensure((size_t)batch * N3 * 32 * 2));
-  const size_t count = (size_t)batch * N3 * 16;
-  const int nb = (int)std::min<size_t>((count + 255) / 256, 1024);
-  KC_TRY(net->lpart.ensure(nb * sizeof(double)));
-  // loss over the 6 used output channels: the padding channels of y and target are zero
-  k_mse<<<nb, 256, 0, s>>>(y, target, net->g3.as<uint16_t>(), count, 1.f / (float)((size_t)batch * N3 * NN_COUT),
-                           net->lpart.as<double>());
-  KC_LAUNCHED();
   uint16_t* g3 = net->g3.as<uint16_t>();
   uint16_t* g2 = net->g2.as<uint16_t>();
   uint16_t* g1 = net->g1.as<uint16_t>();
@@ -520,6 +459,24 @@ int nn_gradients(Net* net, int N, int batch, const uint16_t* in, const float* ta
                                                    LAYER_COP[l], G + off, G + off + n);
     KC_LAUNCHED();
   }
+  return KC_OK;
+}
+
+int nn_gradients(Net* net, int N, int batch, const uint16_t* in, const float* target, double* loss_host,
+                 hipStream_t s) {
+  const size_t N3 = (size_t)N * N * N;
+  KC_TRY(net->out.ensure((size_t)batch * N3 * 16 * 4));
+  float* y = net->out.as<float>();
+  KC_TRY(nn_forward(net, N, batch, in, y, s));
+  KC_TRY(net->g3.ensure((size_t)batch * N3 * 16 * 2));
+  const size_t count = (size_t)batch * N3 * 16;
+  const int nb = (int)std::min<size_t>((count + 255) / 256, 1024);
+  KC_TRY(net->lpart.ensure(nb * sizeof(double)));
+  // loss over the used output channels: the padding channels of y and target are zero
+  k_mse<<<nb, 256, 0, s>>>(y, target, net->g3.as<uint16_t>(), count, 1.f / (float)((size_t)batch * N3 * NN_COUT),
+                           net->lpart.as<double>());
+  KC_LAUNCHED();
+  KC_TRY(nn_backward_g3(net, N, batch, in, s));
   if (loss_host) {
     std::vector<double> lp(nb);
     KC_HIP(hipMemcpyAsync(lp.data(), net->lpart.p, nb * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -529,6 +486,18 @@ int nn_gradients(Net* net, int N, int batch, const uint16_t* in, const float* ta
     *loss_host = L / (double)((size_t)batch * N3 * NN_COUT);
   }
   return KC_OK;
+}
+
+int nn_backward(Net* net, int N, int batch, const uint16_t* in, const float* gout, hipStream_t s) {
+  const size_t N3 = (size_t)N * N * N;
+  KC_TRY(net->out.ensure((size_t)batch * N3 * 16 * 4));
+  KC_TRY(nn_forward(net, N, batch, in, net->out.as<float>(), s));
+  KC_TRY(net->g3.ensure((size_t)batch * N3 * 16 * 2));
+  const size_t count = (size_t)batch * N3 * 16;
+  k_to_bf16<<<(unsigned)std::min<size_t>((count + 255) / 256, 4096), 256, 0, s>>>(gout, net->g3.as<uint16_t>(),
+                                                                                  count);
+  KC_LAUNCHED();
+  return nn_backward_g3(net, N, batch, in, s);
 }
 
 int nn_adam(Net* net, float lr, float b1, float b2, float eps, hipStream_t s) {
@@ -542,56 +511,50 @@ int nn_adam(Net* net, float lr, float b1, float b2, float eps, hipStream_t s) {
   return nn_pack(net, s);
 }
 
-// |r|^2 of contiguous vectors
-int norm2(const c64* r, size_t n, int nvec, DevBuf& part, double* out, hipStream_t s) {
-  const int nblk = (int)std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 256));
-  KC_TRY(part.ensure((size_t)nvec * nblk * sizeof(double)));
-  k_norm2<<<dim3(nblk, nvec), 256, 0, s>>>(r, n, part.as<double>(), nblk);
-  KC_LAUNCHED();
-  k_sum_rows<<<(nvec + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nvec, out);
+// network input of k-points ik0..ik0+nk-1 (bf16 [nk][N3][32])
+int nn_features(kc_op* op, int ik0, int nk, uint16_t* F, hipStream_t s) {
+  const int N = op->N;
+  const size_t N3 = (size_t)N * N * N;
+  if (op->epsfeat.p == nullptr) KC_TRY(nn_build_eps_features(op));
+  KC_TRY(build_efield(op));
+  const unsigned g = (unsigned)std::min<size_t>((N3 * nk + 255) / 256, 65535);
+  k_features<<<g, 256, 0, s>>>(op->epsfeat.as<float>(), op->efield.as<float>(), op->kdev.as<double>() + 3 * (size_t)ik0,
+                               N, nk, F);
   KC_LAUNCHED();
   return KC_OK;
 }
 
-int fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, const void* tw, hipStream_t s);
-
-// features of contiguous k-space vectors V [nvec][3][N3] (|v|^2 given in vv, device)
-int nn_features(kc_op* op, int ik0, int nvec, int vpk, const c64* V, const double* vv, uint16_t* F,
-                hipStream_t s) {
+// learned fields E of k-points ik0..ik0+nk-1 (f32 [nk][3][N3]) with the attached network
+int nn_efield(kc_op* op, int ik0, int nk, float* E, hipStream_t s) {
   Net* net = op->net;
   const int N = op->N;
   const size_t N3 = (size_t)N * N * N;
-  KC_TRY(net->rreal.ensure((size_t)nvec * 3 * N3 * sizeof(c64)));
-  KC_TRY(net->scales.ensure((size_t)nvec * 2 * sizeof(double)));
-  KC_TRY(fft3d(N, 3 * nvec, +1, KC_PREC_FP64, V, net->rreal.p, op->tw64.p, s));
-  double* sin_ = net->scales.as<double>();
-  k_scales<<<(nvec + 255) / 256, 256, 0, s>>>(vv, nvec, (double)N3, sin_, sin_ + nvec);
-  KC_LAUNCHED();
-  const unsigned g = (unsigned)std::min<size_t>((N3 * nvec + 255) / 256, 65535);
-  k_features<<<g, 256, 0, s>>>(net->rreal.as<c64>(), op->epsfeat.as<float>(), sin_,
-                               op->kdev.as<double>() + 3 * (size_t)ik0, vpk, N, nvec, F);
+  KC_TRY(net->feat.ensure((size_t)nk * N3 * 32 * 2));
+  KC_TRY(net->out.ensure((size_t)nk * N3 * 16 * 4));
+  KC_TRY(nn_features(op, ik0, nk, net->feat.as<uint16_t>(), s));
+  KC_TRY(nn_forward(net, N, nk, net->feat.as<uint16_t>(), net->out.as<float>(), s));
+  const unsigned g = (unsigned)std::min<size_t>((N3 * nk + 255) / 256, 65535);
+  k_efield<<<g, 256, 0, s>>>(net->out.as<float>(), op->efield.as<float>(), N, nk, E);
   KC_LAUNCHED();
   return KC_OK;
 }
 
-// z[v] += F3^H net(features of V) * |v_v| / (sqrt(3) N^3) for the diagonal-block preconditioned
-// residuals V (contiguous, |v|^2 in vv) whose strided copies z are corrected in place
-int nn_correct(kc_op* op, int ik0, int nvec, int vpk, const c64* V, const double* vv, c64* z, const VecMap& zmap,
-               hipStream_t s) {
-  Net* net = op->net;
+// E0_c = 1/(eps^-1)_cc of the material at the c-edge points (f32 [3][N3])
+int build_efield(kc_op* op) {
+  if (op->efield.p != nullptr) return KC_OK;
   const int N = op->N;
   const size_t N3 = (size_t)N * N * N;
-  KC_TRY(net->feat.ensure((size_t)nvec * N3 * 32 * 2));
-  KC_TRY(net->out.ensure((size_t)nvec * N3 * 16 * 4));
-  KC_TRY(nn_features(op, ik0, nvec, vpk, V, vv, net->feat.as<uint16_t>(), s));
-  KC_TRY(nn_forward(net, N, nvec, net->feat.as<uint16_t>(), net->out.as<float>(), s));
-  const double* sout = net->scales.as<double>() + nvec;
-  const unsigned g = (unsigned)std::min<size_t>((N3 * nvec + 255) / 256, 65535);
-  k_delta_to_field<<<g, 256, 0, s>>>(net->out.as<float>(), sout, N, nvec, net->rreal.as<c64>());
-  KC_LAUNCHED();
-  KC_TRY(fft3d(N, 3 * nvec, -1, KC_PREC_FP64, net->rreal.p, net->rreal.p, op->tw64.p, s));
-  k_add_vecs<<<g, 256, 0, s>>>(z, net->rreal.as<c64>(), N, nvec, zmap, op->ktab64.as<c64>() + (size_t)ik0 * 3 * N);
-  KC_LAUNCHED();
+  std::vector<uint32_t> ids(N3);
+  KC_HIP(hipMemcpy(ids.data(), op->ids.p, N3 * 4, hipMemcpyDeviceToHost));
+  std::vector<float> f(3 * N3);
+  const double* t = op->eps_host.data();
+  for (size_t p = 0; p < N3; ++p)
+    for (int c = 0; c < 3; ++c) {
+      const int m = (ids[p] >> (8 * c)) & 255;
+      f[c * N3 + p] = (float)(1.0 / t[((m * 3 + c) * 3 + c) * 2]);
+    }
+  KC_TRY(op->efield.ensure(f.size() * sizeof(float)));
+  KC_HIP(hipMemcpy(op->efield.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
   return KC_OK;
 }
 

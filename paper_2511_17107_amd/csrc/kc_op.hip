@@ -15,6 +15,18 @@
 //
 // The 1D symbols K_a(q) = (1 - e^{-i theta_q})/h + i k_a (1 + e^{-i theta_q})/2 are read from
 // a table of 3N entries per k-point (eq (2.28)), so no per-frequency array is stored.
+//
+// The same passes evaluate the transverse-projection preconditioner
+//   T_E r = K_A^{+H} F3^H E F3 K_A^{+} r + (gamma K_B)^{+} r,
+// the pseudo-inverse of Op with the inverse permittivity replaced by a positive diagonal
+// field E (the permittivity itself, in the classical choice E_c = 1/(eps^-1)_cc at the
+// c-edge points).  Each symbol factors as K_a = i e^{-i theta_a/2} kappa_a with kappa_a
+// real, so K_A = [K x] is a unitary rescaling of the real cross-product matrix [kappa x] and
+// K_A^{+} = K_A^H / s with s = |K_1|^2 + |K_2|^2 + |K_3|^2; likewise (gamma K_B)^{+} =
+// K_B / (gamma s^2).  Hence T_E r = (1/s) [K_A F3^H E F3 K_A^H (r/s) + (1/gamma) K_B (r/s)]:
+// the operator's passes with a 1/s prologue and epilogue, the diagonal field E in the Z pass
+// and 1/gamma for gamma.  T_E is Hermitian positive semi-definite, zero exactly where K_P is
+// singular, and equals K_P^{-1} for E = 1.
 #include <algorithm>
 #include <cmath>
 
@@ -43,7 +55,7 @@ __device__ __forceinline__ void load_eps_table(EpsEntry<T>* lt, const EpsEntry<T
 // ------------------------------------------------------------------------------------
 // X1: curl prologue + inverse DFT along x.  Tile: P rows (y) of one (vec, z), 3 comps.
 // ------------------------------------------------------------------------------------
-template <int N, typename T>
+template <int N, typename T, bool PRE>
 __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, cpx<T>* __restrict__ E,
                                                     const cpx<T>* __restrict__ ktab, VecMap vm,
                                                     const cpx<T>* __restrict__ gtw) {
@@ -67,9 +79,17 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
     const size_t off = (size_t)z * N * N + (size_t)y * N + e;
     const cpx<T> x1 = cvt<T>(xv[off]), x2 = cvt<T>(xv[N3 + off]), x3 = cvt<T>(xv[2 * N3 + off]);
     const cpx<T> v1 = conj(K[e]), v2 = conj(K[N + y]);
-    lds[G::addr3(0, e, p)] = v3 * x2 - v2 * x3;
-    lds[G::addr3(1, e, p)] = v1 * x3 - v3 * x1;
-    lds[G::addr3(2, e, p)] = v2 * x1 - v1 * x2;
+    cpx<T> c1 = v3 * x2 - v2 * x3, c2 = v1 * x3 - v3 * x1, c3 = v2 * x1 - v1 * x2;
+    if (PRE) {  // K_A^{+} = K_A^H / s
+      const T sq = abs2(v1) + abs2(v2) + abs2(v3);
+      const T is = sq > T(0) ? T(1) / sq : T(0);
+      c1 = is * c1;
+      c2 = is * c2;
+      c3 = is * c3;
+    }
+    lds[G::addr3(0, e, p)] = c1;
+    lds[G::addr3(1, e, p)] = c2;
+    lds[G::addr3(2, e, p)] = c3;
   }
   __syncthreads();
   fft_tile<N, P, 3, NT, +1, T>(lds, tw);
@@ -83,13 +103,13 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
 // ------------------------------------------------------------------------------------
 // X2: forward DFT along x + outer curl + penalty epilogue.
 // ------------------------------------------------------------------------------------
-template <int N, typename T>
+template <int N, typename T, bool PRE>
 __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict__ E,
                                                         const c64* __restrict__ x, c64* __restrict__ y,
                                                         const cpx<T>* __restrict__ ktab,
                                                         const c64* __restrict__ ktab64,
                                                         const double* __restrict__ gamma,
-                                                        VecMap vm, const cpx<T>* __restrict__ gtw) {
+                                                        VecMap vm, VecMap vmy, const cpx<T>* __restrict__ gtw) {
   constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
@@ -104,7 +124,7 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
   const int ik = vec / vm.vpk;
   const cpx<T>* K = ktab + (size_t)ik * 3 * N;
   const c64* Kd = ktab64 + (size_t)ik * 3 * N;
-  const double g = gamma[ik];
+  const double g = PRE ? 1.0 / gamma[ik] : gamma[ik];
   load_twiddles<N>(tw, gtw);
   const cpx<T>* Ev = E + (size_t)vec * 3 * N3;
   for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
@@ -114,7 +134,7 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
   __syncthreads();
   fft_tile<N, P, 3, NT, -1, T>(lds, tw);
   const c64* xv = x + vm.off(vec) * 3 * N3;
-  c64* yv = y + vm.off(vec) * 3 * N3;
+  c64* yv = y + vmy.off(vec) * 3 * N3;
   const cpx<T> K3 = K[2 * N + z];
   const c64 K3d = Kd[2 * N + z];
   for (int w = threadIdx.x; w < N * P; w += NT) {
@@ -128,10 +148,19 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
     const c64 x1 = xv[off], x2 = xv[N3 + off], x3 = xv[2 * N3 + off];
     const c64 K1d = Kd[e], K2d = Kd[N + yy];
     const c64 kx = K1d * x1 + K2d * x2 + K3d * x3;  // K . x
-    const c64 gk = g * kx;
-    yv[off] = c1 + cmulc(K1d, gk);
-    yv[N3 + off] = c2 + cmulc(K2d, gk);
-    yv[2 * N3 + off] = c3 + cmulc(K3d, gk);
+    if (PRE) {  // (1/s) [c + (1/gamma) K_B x / s]
+      const double sq = abs2(K1d) + abs2(K2d) + abs2(K3d);
+      const double is = sq > 0.0 ? 1.0 / sq : 0.0;
+      const c64 gk = (g * is) * kx;
+      yv[off] = is * (c1 + cmulc(K1d, gk));
+      yv[N3 + off] = is * (c2 + cmulc(K2d, gk));
+      yv[2 * N3 + off] = is * (c3 + cmulc(K3d, gk));
+    } else {
+      const c64 gk = g * kx;
+      yv[off] = c1 + cmulc(K1d, gk);
+      yv[N3 + off] = c2 + cmulc(K2d, gk);
+      yv[2 * N3 + off] = c3 + cmulc(K3d, gk);
+    }
   }
 }
 
@@ -268,6 +297,49 @@ __global__ __launch_bounds__(NT) void k_z_trivial(cpx<T>* __restrict__ buf, cons
     lds[G::addr3(0, e, p)] = ax.d[0] * E1 + o12 * E2 + o13 * E3;
     lds[G::addr3(1, e, p)] = cmulc(o12, E1) + ay.d[1] * E2 + o23 * E3;
     lds[G::addr3(2, e, p)] = cmulc(o13, E1) + cmulc(o23, E2) + az.d[2] * E3;
+  }
+  __syncthreads();
+  fft_tile<N, P, 3, NT, -1, T>(lds, tw);
+  for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
+    const int p = w % P, e = (w / P) % N, c = w / (N * P);
+    base[c * N3 + (size_t)e * N * N + p] = lds[G::addr3(c, e, p)];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Z (transverse-projection preconditioner): inverse DFT along z, E_c' = f_c E_c / N^3 with a
+// positive per-point field f (FP32 [3][N^3], one per k-point group or shared), forward DFT
+// along z.  In place.  Tile: P consecutive x of one (vec, y), 3 comps.
+// ------------------------------------------------------------------------------------
+template <int N, typename T>
+__global__ __launch_bounds__(NT) void k_z_field(cpx<T>* __restrict__ buf, const float* __restrict__ field,
+                                                int vpk, int fkstride, const cpx<T>* __restrict__ gtw,
+                                                const int* __restrict__ active) {
+  constexpr int P = TileP<N, 3, T>::P;
+  using G = TileGeom<N, P, 3>;
+  __shared__ cpx<T> lds[G::ELEMS];
+  __shared__ cpx<T> tw[N];
+  constexpr size_t N3 = (size_t)N * N * N;
+  constexpr T inv = T(1) / T(N3);
+  unsigned b = blockIdx.x;
+  const int xt = b % (N / P);
+  b /= (N / P);
+  const int yy = b % N;
+  const size_t vec = b / N;
+  if (active && !active[vec]) return;
+  load_twiddles<N>(tw, gtw);
+  const float* f = field + (size_t)(vec / vpk) * fkstride * 3 * N3;
+  cpx<T>* base = buf + vec * 3 * N3 + (size_t)yy * N + xt * P;
+  for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
+    const int p = w % P, e = (w / P) % N, c = w / (N * P);
+    lds[G::addr3(c, e, p)] = base[c * N3 + (size_t)e * N * N + p];
+  }
+  __syncthreads();
+  fft_tile<N, P, 3, NT, +1, T>(lds, tw);
+  for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
+    const int p = w % P, e = (w / P) % N, c = w / (N * P);
+    const T fc = (T)f[c * N3 + (size_t)e * N * N + (size_t)yy * N + xt * P + p] * inv;
+    lds[G::addr3(c, e, p)] = fc * lds[G::addr3(c, e, p)];
   }
   __syncthreads();
   fft_tile<N, P, 3, NT, -1, T>(lds, tw);
@@ -474,7 +546,7 @@ static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x,
   const int* act = vm.active;
   if (op->scheme == KC_EPS_CROSSDOF) KC_TRY(op->work_b.ensure(nbuf));
   KC_TRY(mark());
-  k_x1_curl_inv<N, T><<<g3, NT, 0, s>>>(x, A, ktab, vm, tw);
+  k_x1_curl_inv<N, T, false><<<g3, NT, 0, s>>>(x, A, ktab, vm, tw);
   KC_LAUNCHED();
   KC_TRY(mark());
   k_y<N, +1, T><<<g1, NT, 0, s>>>(A, tw, act);
@@ -495,9 +567,97 @@ static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x,
   k_y<N, -1, T><<<g1, NT, 0, s>>>(A, tw, act);
   KC_LAUNCHED();
   KC_TRY(mark());
-  k_x2_fwd_curl_pen<N, T><<<g3, NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, tw);
+  k_x2_fwd_curl_pen<N, T, false><<<g3, NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vm, tw);
   KC_LAUNCHED();
   KC_TRY(mark());
+  return KC_OK;
+}
+
+// y = T_E x (transverse-projection preconditioner); x is addressed through vm, y through vmy
+// (same k-point grouping and active mask), and the two must not overlap.
+template <int N, typename T>
+static int apply_tp_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecMap& vmy, const c64* x, c64* y,
+                      const float* field, int fkstride, hipStream_t s) {
+  constexpr size_t N3 = (size_t)N * N * N;
+  const size_t nbuf = (size_t)nvec * 3 * N3 * sizeof(cpx<T>);
+  KC_TRY(op->work_a.ensure(nbuf));
+  cpx<T>* A = op->work_a.as<cpx<T>>();
+  const bool f64 = sizeof(T) == 8;
+  const cpx<T>* ktab = (f64 ? op->ktab64.as<cpx<T>>() : op->ktab32.as<cpx<T>>()) + (size_t)ik0 * 3 * N;
+  const c64* ktab64 = op->ktab64.as<c64>() + (size_t)ik0 * 3 * N;
+  const double* gam = op->gamma_d.as<double>() + ik0;
+  const cpx<T>* tw = f64 ? op->tw64.as<cpx<T>>() : op->tw32.as<cpx<T>>();
+  constexpr int P3 = TileP<N, 3, T>::P;
+  constexpr int P1 = TileP<N, 1, T>::P;
+  const unsigned g3 = nblk((size_t)nvec * N * (N / P3));
+  const unsigned g1 = nblk((size_t)nvec * 3 * N * (N / P1));
+  const int* act = vm.active;
+  k_x1_curl_inv<N, T, true><<<g3, NT, 0, s>>>(x, A, ktab, vm, tw);
+  KC_LAUNCHED();
+  k_y<N, +1, T><<<g1, NT, 0, s>>>(A, tw, act);
+  KC_LAUNCHED();
+  k_z_field<N, T><<<g3, NT, 0, s>>>(A, field, vm.vpk, fkstride, tw, act);
+  KC_LAUNCHED();
+  k_y<N, -1, T><<<g1, NT, 0, s>>>(A, tw, act);
+  KC_LAUNCHED();
+  k_x2_fwd_curl_pen<N, T, true><<<g3, NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw);
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+// g[b][c][p] += sum_j w[b vpk + j] Re(conj(Ge_j) Gr_j)_c(p) with G = F3 K_A^{+} (the real-space
+// edge field that T_E scales pointwise), for the vectors j of k-point group b: the gradient of
+// sum_j w_j Re<e_j, T_E r_j> with respect to E.  Gr, Ge are unnormalised inverse DFTs, hence
+// the factor 1/N^3.
+template <typename T>
+__global__ void k_tp_grad(const cpx<T>* __restrict__ Gr, const cpx<T>* __restrict__ Ge,
+                          const double* __restrict__ w, int vpk, int nk, size_t N3, float* __restrict__ g) {
+  const double inv = 1.0 / (double)N3;
+  for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < (size_t)nk * 3 * N3; t += (size_t)gridDim.x * 256) {
+    const size_t b = t / (3 * N3), cp = t - b * 3 * N3;
+    double acc = 0.0;
+    for (int j = 0; j < vpk; ++j) {
+      const size_t v = b * vpk + j;
+      const cpx<T> a = Ge[v * 3 * N3 + cp], c = Gr[v * 3 * N3 + cp];
+      acc += w[v] * (double)(a.re * c.re + a.im * c.im);
+    }
+    g[t] += (float)(acc * inv);
+  }
+}
+
+template <int N>
+static int tp_grad_n(kc_op* op, int ik0, int nvec, int vpk, const c64* r, const c64* e, const double* w, float* g,
+                     hipStream_t s) {
+  using T = double;
+  constexpr size_t N3 = (size_t)N * N * N;
+  const size_t nbuf = (size_t)nvec * 3 * N3 * sizeof(c64);
+  KC_TRY(op->work_a.ensure(nbuf));
+  KC_TRY(op->work_b.ensure(nbuf));
+  KC_TRY(op->work_c.ensure(nbuf));
+  c64* A = op->work_a.as<c64>();
+  const c64* ktab = op->ktab64.as<c64>() + (size_t)ik0 * 3 * N;
+  const c64* tw = op->tw64.as<c64>();
+  constexpr int P3 = TileP<N, 3, T>::P;
+  constexpr int P1 = TileP<N, 1, T>::P;
+  const unsigned g3 = nblk((size_t)nvec * N * (N / P3));
+  const unsigned g1 = nblk((size_t)nvec * 3 * N * (N / P1));
+  VecMap vm;
+  vm.vpk = vpk;
+  vm.kstride = vpk;
+  c64* out[2] = {op->work_b.as<c64>(), op->work_c.as<c64>()};
+  const c64* in[2] = {r, e};
+  for (int i = 0; i < 2; ++i) {
+    k_x1_curl_inv<N, T, true><<<g3, NT, 0, s>>>(in[i], A, ktab, vm, tw);
+    KC_LAUNCHED();
+    k_y<N, +1, T><<<g1, NT, 0, s>>>(A, tw, nullptr);
+    KC_LAUNCHED();
+    k_z_plain<N, +1, T><<<g1, NT, 0, s>>>(A, out[i], tw, nullptr, 3);
+    KC_LAUNCHED();
+  }
+  const int nk = nvec / vpk;
+  const unsigned gg = (unsigned)std::min<size_t>(((size_t)nk * 3 * N3 + 255) / 256, 65535);
+  k_tp_grad<T><<<gg, 256, 0, s>>>(out[0], out[1], w, vpk, nk, N3, g);
+  KC_LAUNCHED();
   return KC_OK;
 }
 
@@ -559,6 +719,26 @@ int apply_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* r, c6
                                 op->gamma_d.as<double>() + ik0, op->N, nvec, vecs_per_k);
   KC_LAUNCHED();
   return KC_OK;
+}
+
+int apply_tp(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecMap& vmy, const c64* x, c64* y,
+             const float* field, int fkstride, int prec, hipStream_t s) {
+  if (nvec == 0) return KC_OK;
+  if (prec == KC_PREC_FP64) {
+    KC_DISPATCH_N(op->N, (apply_tp_n<NN, double>(op, ik0, nvec, vm, vmy, x, y, field, fkstride, s)))
+  } else {
+    KC_DISPATCH_N(op->N, (apply_tp_n<NN, float>(op, ik0, nvec, vm, vmy, x, y, field, fkstride, s)))
+  }
+  set_error("unsupported N");
+  return KC_ERR_UNSUPPORTED;
+}
+
+int tp_grad(kc_op* op, int ik0, int nvec, int vpk, const c64* r, const c64* e, const double* w, float* g,
+            hipStream_t s) {
+  if (nvec == 0) return KC_OK;
+  KC_DISPATCH_N(op->N, (tp_grad_n<NN>(op, ik0, nvec, vpk, r, e, w, g, s)))
+  set_error("unsupported N");
+  return KC_ERR_UNSUPPORTED;
 }
 
 int fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, const void* tw, hipStream_t s) {

@@ -4,6 +4,8 @@
 //
 // Per k-point the search space is S = [X W P] (3 mb columns) with images AS = [AX AW AP]:
 //   1. R = AX - X Theta, Res_j = |r_j| / |x_j|, W = K_P^{-1} R            (k_resid_precond)
+//      (or, after the masks of step 2, W = T_E R with the transverse-projection preconditioner
+//      for the columns that get a new direction)
 //   2. soft locking: columns with Res_j <= tol (j < m) get no new W; k-points whose
 //      m bands all satisfy the test are verified with a fresh FP64 application and retired
 //   3. AW = Op W (FP32 while the mixed-precision phase lasts, FP64 after)
@@ -29,8 +31,8 @@ struct SolverWork {
   DevBuf S, AS;
   DevBuf part_gram, part_res;
   DevBuf GA, GB, Cu, Lsave;
-  DevBuf theta, res, xn2, wn2;
-  DevBuf R, lmask;  // copy of W (the network's input) and per-vector switch for the learned correction
+  DevBuf theta, res, xn2;
+  DevBuf R, tmask;  // residuals (input of T_E) and the columns that get T_E R
   DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal [nb each]
 };
 
@@ -49,7 +51,9 @@ struct Batch {
   hipStream_t s;
   int *xmask, *wmask, *pmask, *pvalid, *kskip, *flags, *kglobal;
   c64 *S, *AS;
-  bool learned = false;
+  int pc = KC_PRECOND_DIAG;
+  const float* field = nullptr;  // E of T_E: one per k-point (fks = 1) or shared (fks = 0)
+  int fks = 0;
 };
 
 int upload_ints(int* dst, const std::vector<int>& v, hipStream_t s) {
@@ -80,22 +84,24 @@ int rayleigh_ritz(Batch& B) {
   return KC_OK;
 }
 
-// Res and W = K_P^{-1} R (+ the learned correction, computed from a contiguous copy of W, for
-// the k-points whose lmask is set)
-int residuals(Batch& B, bool learned) {
-  c64* Wc = learned ? B.w->R.as<c64>() : nullptr;
-  double* wn2 = learned ? B.w->wn2.as<double>() : nullptr;
+// Res and W = K_P^{-1} R; with copy_r also a contiguous copy of R for T_E
+int residuals(Batch& B, bool copy_r) {
+  c64* R = copy_r ? B.w->R.as<c64>() : nullptr;
   KC_TRY(resid_precond(B.S, B.AS, B.S, B.w->theta.as<double>(), B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N,
                        B.op->gamma_d.as<double>() + B.ik0, B.N, B.nc, 0, B.mb, B.mb, B.nb, B.w->part_res,
-                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, Wc, nullptr, wn2));
-  if (learned) {
-    VecMap zm;
-    zm.vpk = B.mb;
-    zm.kstride = B.nc;
-    zm.active = B.w->lmask.as<int>();
-    KC_TRY(nn_correct(B.op, B.ik0, B.nb * B.mb, B.mb, Wc, wn2, B.S + (size_t)B.mb * B.n, zm, B.s));
-  }
+                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, R));
   return KC_OK;
+}
+
+// W = T_E R (FP32 transforms) for the columns whose tmask is set; the others keep K_P^{-1} R
+int precond_tp(Batch& B) {
+  VecMap vx, vy;
+  vx.vpk = vy.vpk = B.mb;
+  vx.kstride = B.mb;
+  vy.kstride = B.nc;
+  vx.active = vy.active = B.w->tmask.as<int>();
+  return apply_tp(B.op, B.ik0, B.nb * B.mb, vx, vy, B.w->R.as<c64>(), B.S + (size_t)B.mb * B.n, B.field, B.fks,
+                  KC_PREC_FP32, B.s);
 }
 
 int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig, double* res_out, int* iters,
@@ -125,15 +131,26 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(w->theta.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->res.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->xn2.ensure((size_t)nb * mb * sizeof(double)));
-  KC_TRY(w->wn2.ensure((size_t)nb * mb * sizeof(double)));
-  B.learned = (o.precond == KC_PRECOND_LEARNED);
-  if (B.learned) {
+  B.pc = o.precond;
+  const bool tp = B.pc != KC_PRECOND_DIAG;
+  if (B.pc == KC_PRECOND_LEARNED) {
     if (!op->net) {
       set_error("learned preconditioner requested but no network is attached");
       return KC_ERR_INVALID_ARG;
     }
+    // one network pass per k-point of the batch gives its field
+    KC_TRY(op->efield_k.ensure((size_t)nb * n * sizeof(float)));
+    KC_TRY(nn_efield(op, ik0, nb, op->efield_k.as<float>(), s));
+    B.field = op->efield_k.as<float>();
+    B.fks = 1;
+  } else if (B.pc == KC_PRECOND_TRANSVERSE) {
+    KC_TRY(build_efield(op));
+    B.field = op->efield.as<float>();
+    B.fks = 0;
+  }
+  if (tp) {
     KC_TRY(w->R.ensure((size_t)nb * mb * colbytes));
-    KC_TRY(w->lmask.ensure((size_t)nb * mb * sizeof(int)));
+    KC_TRY(w->tmask.ensure((size_t)nb * mb * sizeof(int)));
   }
   KC_TRY(w->ints.ensure((size_t)(4 * nb * mb + 3 * nb) * sizeof(int)));
   B.S = w->S.as<c64>();
@@ -165,18 +182,12 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(random_block(B.S, n, nc, 0, mb, nb, o.seed, B.kglobal, s));
   KC_HIP(hipMemcpyAsync(w->theta.p, htheta.data(), htheta.size() * sizeof(double), hipMemcpyHostToDevice, s));
   KC_TRY(residuals(B, false));
-  // learned correction on per k-point; a k-point falls back to the diagonal preconditioner
-  // when the geometric mean of its band residuals (each floored at tol) stops decreasing or
-  // grows
-  std::vector<int> lon(nb, B.learned ? 1 : 0), hl(nb * mb, 0);
+  // T_E per k-point; with the learned field a k-point falls back to K_P^{-1} when the geometric
+  // mean of its band residuals (each floored at tol) stops decreasing or grows
+  std::vector<int> lon(nb, tp ? 1 : 0), ht(nb * mb, 0);
   std::vector<double> lbest(nb, 1e300);
   std::vector<int> lstall(nb, 0);
-  auto upload_lmask = [&]() -> int {
-    for (int b = 0; b < nb; ++b)
-      for (int j = 0; j < mb; ++j) hl[b * mb + j] = lon[b] && !done[b];
-    return upload_ints(B.w->lmask.as<int>(), hl, s);
-  };
-  if (B.learned) KC_TRY(upload_lmask());
+  double napp = 0;
   KC_TRY(upload_ints(B.xmask, hx, s));
   KC_TRY(upload_ints(B.wmask, hw, s));
   KC_TRY(upload_ints(B.pmask, hp, s));
@@ -194,9 +205,9 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   int stall = 0;
   bool verify_pending = false;
   while (true) {
-    bool use_learned = false;
-    for (int b = 0; b < nb; ++b) use_learned = use_learned || (lon[b] && !done[b]);
-    KC_TRY(residuals(B, use_learned));
+    bool use_tp = false;
+    for (int b = 0; b < nb; ++b) use_tp = use_tp || (lon[b] && !done[b]);
+    KC_TRY(residuals(B, use_tp));
     KC_HIP(hipMemcpyAsync(hres.data(), w->res.p, hres.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     KC_HIP(hipMemcpyAsync(hpv.data(), B.pvalid, hpv.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     KC_HIP(hipMemcpyAsync(hflags.data(), B.flags, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -256,8 +267,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
         ++ncand;
       }
     }
-    if (B.learned) {
-      bool changed = false;
+    if (B.pc == KC_PRECOND_LEARNED) {
       for (int b = 0; b < nb; ++b) {
         if (done[b] || !lon[b]) continue;
         double lg = 0.0;
@@ -268,11 +278,9 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
           lstall[b] = 0;
         } else if (++lstall[b] >= 8 || gm > 100.0 * lbest[b]) {
           lon[b] = 0;  // fall back to the diagonal-block preconditioner
-          changed = true;
           if (o.verbose) fprintf(stderr, "[kc_solve] k %d: learned preconditioner off\n", ik0 + b);
         }
       }
-      if (changed) KC_TRY(upload_lmask());
     }
     if (verify_pending) {
       // residuals above come from a fresh FP64 application of Op to X
@@ -345,6 +353,18 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
     KC_TRY(upload_ints(B.wmask, hw, s));
     KC_TRY(upload_ints(B.pmask, hp, s));
     KC_TRY(upload_ints(B.kskip, hskip, s));
+    if (use_tp) {
+      int nt = 0;
+      for (int b = 0; b < nb; ++b)
+        for (int j = 0; j < mb; ++j) {
+          const int i = b * mb + j;
+          ht[i] = hw[i] && lon[b];
+          nt += ht[i];
+        }
+      KC_TRY(upload_ints(B.w->tmask.as<int>(), ht, s));
+      KC_TRY(precond_tp(B));
+      napp += nt;
+    }
     KC_TRY(apply_cols(B, mb, B.wmask, prec));
     (prec == KC_PREC_FP64 ? nmv64 : nmv32) += nact;
     KC_TRY(rayleigh_ritz(B));
@@ -372,7 +392,8 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   op->stats[0] += nmv64;
   op->stats[1] += nmv32;
   op->stats[3] += (double)it * nb;
-  for (int b = 0; b < nb; ++b) op->stats[4] += lon[b];  // k-points that kept the learned correction
+  for (int b = 0; b < nb; ++b) op->stats[4] += lon[b];  // k-points that kept T_E to the end
+  op->stats[5] += napp;
   *all_conv = allc;
   return KC_OK;
 }
@@ -406,7 +427,8 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   KC_ARG((size_t)3 * (o.m + o.guard) <= 3 * (size_t)op->N * op->N * op->N, "block larger than the space");
   KC_ARG(o.tol > 0.0 && o.maxit >= 1 && o.batch_k >= 1, "tol > 0, maxit >= 1, batch_k >= 1");
   KC_ARG(o.prec == KC_PREC_FP64 || o.prec == KC_PREC_FP32, "prec");
-  KC_ARG(o.precond == KC_PRECOND_DIAG || o.precond == KC_PRECOND_LEARNED, "precond");
+  KC_ARG(o.precond == KC_PRECOND_DIAG || o.precond == KC_PRECOND_LEARNED || o.precond == KC_PRECOND_TRANSVERSE,
+         "precond");
   hipStream_t s = (hipStream_t)stream;
   auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < 8; ++i) op->stats[i] = 0.0;

@@ -60,10 +60,12 @@ struct kc_op {
   std::vector<double> kvec, gamma;  // [nk][3], [nk]
   kc::DevBuf ktab64, ktab32;        // 1D symbols [nk][3][N]
   kc::DevBuf gamma_d;               // double [nk]
-  kc::DevBuf work_a, work_b;        // operator intermediates
+  kc::DevBuf work_a, work_b, work_c;  // operator intermediates
   kc::SolverWork* solver = nullptr;
   kc::Net* net = nullptr;     // attached learned preconditioner (not owned)
   kc::DevBuf epsfeat;         // f32 [N^3][9] inverse-permittivity features for the network
+  kc::DevBuf efield;          // f32 [3][N^3] E_c = 1/(eps^-1)_cc at the c-edge points
+  kc::DevBuf efield_k;        // f32 [nb][3][N^3] learned fields of the k-points being solved
   kc::DevBuf kdev;            // double [nk][3] wave vectors
   double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
@@ -77,5 +79,16 @@ int apply_op(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x, c64* 
 // z = K_P^{-1} r
 int apply_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* r, c64* z,
                   hipStream_t s);
+// y = T_E x, the transverse-projection preconditioner with the positive diagonal field E
+// (f32 [3][N^3] per k-point group at field + (v / vm.vpk) * fkstride * 3N^3); x is addressed
+// through vm, y through vmy (same grouping and active mask); x and y must not overlap.
+int apply_tp(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecMap& vmy, const c64* x, c64* y,
+             const float* field, int fkstride, int prec, hipStream_t s);
+// E_c = 1/(eps^-1)_cc at the c-edge points (built on first use)
+int build_efield(kc_op* op);
+// g[b][3][N^3] += gradient with respect to E of sum_j w_j Re<e_j, T_E r_j> (w device, nvec
+// values; vectors grouped vpk per k-point; FP64 transforms)
+int tp_grad(kc_op* op, int ik0, int nvec, int vpk, const c64* r, const c64* e, const double* w, float* g,
+            hipStream_t s);
 
 }  // namespace kc

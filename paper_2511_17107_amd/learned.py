@@ -1,29 +1,32 @@
 """Training and evaluation of the learned preconditioner.
 
-The network reads the diagonal-block preconditioned residual z = K_P^{-1} r (eqs (2.31)-(2.32))
-in real space and returns an additive correction, so the search direction becomes z + delta.
-Pairs are generated by the solver itself on random dielectric geometries: for converged
-eigenpairs from kc_solve, iterates x = x* + e with smooth perturbations e orthogonal to the
-converged block give residuals r = Op x - theta x (theta the Rayleigh quotient of x).  The
-target direction c is either Op^{-1} r (default; Op is Hermitian positive definite away from
-k = 0, and LOBPCG with the exact inverse as preconditioner converges at the rate set by the band
-gaps alone; c from preconditioned CG with K_P) or the error e itself.  Since Rayleigh-Ritz picks
-the scale of every search direction, the target correction is the smallest one that makes z
-parallel to c: delta = alpha c - z with alpha = Re<c, z>/|c|^2, measured in units of |z|.
-Training runs on the GPU with the library's forward, backward and Adam kernels.
+The preconditioner is the transverse-projection operator T_E of kc_precond_transverse with a
+field E predicted per cell by the convolution network from the dielectric structure and the wave
+vector (kc_net_efield): E_c = E0_c exp(clamp(y_c, -3, 3)), E0_c = 1/(eps^-1)_cc at the c-edge
+points.  Training pairs come from the solver itself on random dielectric geometries: for the
+converged eigenpairs (x*, lambda) of one k-point, iterates x = x* + e with smooth perturbations
+e orthogonal to the converged block give residuals r = Op x - theta x (theta the Rayleigh
+quotient of x), and the target direction for each residual is c = Op^{-1} r (preconditioned CG
+with the library's operator and T_E0; Op is Hermitian positive definite away from k = 0):
+LOBPCG with the exact inverse as preconditioner converges at a rate set by the band gaps alone.
+Rayleigh-Ritz fixes the scale of every direction, so the loss of one residual is the
+scale-free misfit min_alpha |alpha T_E r - c|^2 / |c|^2 in the Op-norm (the norm in which
+LOBPCG's convergence is measured; the Euclidean norm is an option), and its gradient with
+respect to E (optimal alpha held fixed) is (2 alpha / |c|^2) Re(conj(G Op e) G r) with
+G = F3 K_A^{+} and e = alpha T_E r - c (kc_tp_grad).  The chain rule through E = E0 exp(y) gives the gradient of the
+network output, and the library's backward and Adam kernels update the weights.
 
-    python -m paper_2511_17107_amd.learned train --out weights.npy [--geoms 48 --N 32]
+    python -m paper_2511_17107_amd.learned train --out weights.npy [--geoms 32 --N 32]
     python -m paper_2511_17107_amd.learned eval --weights weights.npy [--N 96 --nk 8]
 
-PyTorch here only holds device buffers and does the few vector reductions of the data
-generation (inner products, axpy); every operator application, preconditioner, FFT and
-network pass runs in the library's kernels.
+PyTorch here holds device buffers and does the inner products, norms and elementwise products
+of the loss; every operator application, preconditioner, FFT and network pass runs in the
+library's kernels.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -41,52 +44,60 @@ def _torch():
     return torch
 
 
-def pcg(op, ik, r, tol=1e-6, maxit=300):
+def _dot(a, b):
+    """Re<a_j, b_j> per vector of blocks [nv][3][N^3]."""
+    return (a.conj() * b).real.sum(dim=(1, 2))
+
+
+def pcg(op, ik, r, tol=1e-7, maxit=400):
     """Solve Op c = r (one k-point, block of columns r [nv][3][N^3]) by preconditioned CG with
-    the library's operator and diagonal-block preconditioner."""
+    the library's operator and the classical transverse-projection preconditioner."""
     torch = _torch()
     nv = r.shape[0]
     c = torch.zeros_like(r)
     res = r.clone()
-    z = op.precond(res, ik0=ik, vecs_per_k=nv)
+    z = op.precond_transverse(res, ik0=ik, vecs_per_k=nv)
     p = z.clone()
-    rz = (res.conj() * z).real.sum(dim=(1, 2))
+    rz = _dot(res, z)
     rn0 = torch.linalg.vector_norm(r.reshape(nv, -1), dim=1)
     for it in range(maxit):
         Ap = op.apply(p, ik0=ik, vecs_per_k=nv)
-        alpha = rz / (p.conj() * Ap).real.sum(dim=(1, 2))
+        alpha = rz / _dot(p, Ap)
         c += alpha[:, None, None] * p
         res -= alpha[:, None, None] * Ap
         rn = torch.linalg.vector_norm(res.reshape(nv, -1), dim=1)
         if bool((rn <= tol * rn0).all()):
             break
-        z = op.precond(res, ik0=ik, vecs_per_k=nv)
-        rz_new = (res.conj() * z).real.sum(dim=(1, 2))
+        z = op.precond_transverse(res, ik0=ik, vecs_per_k=nv)
+        rz_new = _dot(res, z)
         p = z + (rz_new / rz)[:, None, None] * p
         rz = rz_new
     return c
 
 
-def make_pairs(net, N, seeds, m=8, nk_path=40, amp=(0.02, 0.3), rng_seed=0, target="inverse", log=print):
-    """Features (bf16 [S][N^3][32]) and targets (f32 [S][N^3][16]) from the solver on random
-    inclusion geometries."""
+class Sample:
+    """One geometry and k-point: its operator, network input, residuals and targets."""
+
+    def __init__(self, op, feat, r, c, info):
+        self.op, self.feat, self.r, self.c, self.info = op, feat, r, c, info
+
+
+def make_samples(N, seeds, m=8, nk_path=40, amp=(0.02, 0.3), rng_seed=0, log=print):
     torch = _torch()
     import paper_2511_17107_amd as kc
     import workloads as W
 
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(rng_seed)
-    feats, targs = [], []
     n3 = N ** 3
+    out = []
     for s in seeds:
         wl = W.random_inclusions(N, int(s), nk=nk_path, m=m)
-        # a k-point of the path away from Gamma
-        kidx = int(rng.integers(3, nk_path))
+        kidx = int(rng.integers(3, nk_path))  # a k-point of the path away from Gamma
         op = kc.Op(N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
         op.set_kpoints(wl.kpoints[kidx:kidx + 1])
-        op.attach_net(net)
         X = torch.zeros((m, 3, n3), dtype=torch.complex128, device=dev)
-        eig, res, its, st = op.solve(m, tol=1e-7, guard=2, X_out=X, seed=int(s))
+        eig, res, its, st = op.solve(m, tol=1e-7, guard=2, X_out=X, seed=int(s), precond=kc.KC_PRECOND_TRANSVERSE)
         # perturbation: smoothed noise orthogonal to the converged block
         noise = torch.from_numpy(W.random_block(10_000 + int(s), m, N)).to(dev)
         e = op.precond(noise, vecs_per_k=m)
@@ -97,82 +108,124 @@ def make_pairs(net, N, seeds, m=8, nk_path=40, amp=(0.02, 0.3), rng_seed=0, targ
         a = torch.from_numpy(rng.uniform(amp[0], amp[1], size=m)).to(dev)
         x = (Q + a[:, None] * E).reshape(m, 3, n3).contiguous()
         Ax = op.apply(x, vecs_per_k=m)
-        theta = (x.conj() * Ax).real.sum(dim=(1, 2)) / (x.conj() * x).real.sum(dim=(1, 2))
+        theta = _dot(x, Ax) / _dot(x, x)
         r = (Ax - theta[:, None, None] * x).contiguous()
-        z = op.precond(r, vecs_per_k=m)
-        c = pcg(op, 0, r) if target == "inverse" else (a[:, None] * E).reshape(m, 3, n3)
-        alpha = (c.conj() * z).real.sum(dim=(1, 2)) / (c.conj() * c).real.sum(dim=(1, 2))
-        d = (alpha[:, None, None] * c - z).contiguous()
-        f = op.net_features(z, vecs_per_k=m)
-        # target in the network's output coordinates: U+ d * sqrt(3)/|z| (U+ the unnormalised
-        # inverse DFT)
-        dr = kc.kc_fft3d(d.reshape(3 * m, n3).contiguous(), +1).reshape(m, 3, n3)
-        zn = torch.linalg.vector_norm(z.reshape(m, -1), dim=1)
-        dr = dr * (math.sqrt(3.0) / zn)[:, None, None]
-        t = torch.zeros((m, n3, 16), dtype=torch.float32, device=dev)
-        for comp in range(3):
-            t[:, :, 2 * comp] = dr[:, comp].real.float()
-            t[:, :, 2 * comp + 1] = dr[:, comp].imag.float()
-        feats.append(f)
-        targs.append(t)
-        log("pairs: geometry %d k=%d eig[0]=%.4f iters=%d" % (s, kidx, eig[0][0], its[0]))
-        op.attach_net(None)
-        del op
-    return torch.cat(feats), torch.cat(targs)
+        c = pcg(op, 0, r)
+        feat = op.net_features(0, 1)
+        out.append(Sample(op, feat, r, c, {"seed": int(s), "k": kidx, "eig0": float(eig[0][0]), "iters": int(its[0])}))
+        log("samples: geometry %d k=%d eig[0]=%.4f iters=%d" % (s, kidx, eig[0][0], its[0]))
+    return out
 
 
-def train(net, feats, targs, N, steps=600, batch=8, lr=3e-4, log=print, seed=0):
+def sample_loss(net, smp, grad=False, loss_kind="energy"):
+    """Mean scale-free misfit over the sample's residuals; with grad, also the gradient of that
+    mean with respect to the network output (float32 [N^3][16]).
+
+    energy:    min_alpha |alpha T_E r - c|_Op^2 / |c|_Op^2 = 1 - (z^H r)^2 / ((z^H Op z)(c^H r)),
+               z = T_E r (the Op-norm, in which LOBPCG's convergence is measured)
+    euclidean: min_alpha |alpha T_E r - c|^2 / |c|^2"""
     torch = _torch()
-    S = feats.shape[0]
-    g = torch.Generator(device="cpu").manual_seed(seed)
+    op = smp.op
+    m = smp.r.shape[0]
+    E = op.net_efield(0, 1)
+    z = op.precond_transverse(smp.r, vecs_per_k=m, efield=E)
+    if loss_kind == "energy":
+        Oz = op.apply(z, vecs_per_k=m)
+        cr = _dot(smp.c, smp.r)
+        zr = _dot(z, smp.r)
+        zOz = _dot(z, Oz)
+        alpha = zr / zOz
+        loss = float((1.0 - zr * zr / (zOz * cr)).mean())
+        if not grad:
+            return loss, None
+        ge = (alpha[:, None, None] * Oz - smp.r).contiguous()  # Op e with e = alpha z - c
+        w = (2.0 * alpha / (cr * m)).contiguous()
+    else:
+        cn2 = _dot(smp.c, smp.c)
+        alpha = _dot(z, smp.c) / _dot(z, z)
+        ge = (alpha[:, None, None] * z - smp.c).contiguous()
+        loss = float((_dot(ge, ge) / cn2).mean())
+        if not grad:
+            return loss, None
+        w = (2.0 * alpha / (cn2 * m)).contiguous()
+    gE = torch.zeros_like(E)
+    op.tp_grad(smp.r, ge, w, gE, vecs_per_k=m)
+    y = net.forward(smp.feat, op.N)[0]  # [N^3][16]
+    gy = torch.zeros_like(y)
+    inside = (y[:, :3].abs() < 3.0).float()
+    gy[:, :3] = (gE[0] * E[0]).T * inside  # dE/dy = E inside the clamp range
+    return loss, gy
+
+
+def train(net, samples, steps=400, batch=4, lr=1e-3, log=print, seed=0, loss_kind="energy"):
+    torch = _torch()
+    S = len(samples)
+    N = samples[0].op.N
+    g = np.random.default_rng(seed)
     hist = []
     for it in range(steps):
-        idx = torch.randperm(S, generator=g)[:batch].to(feats.device)
-        loss, _ = net.gradients(feats[idx].contiguous(), targs[idx].contiguous(), N, host_grads=False)
+        idx = g.choice(S, size=min(batch, S), replace=False)
+        feats, gys, ls = [], [], []
+        for i in idx:
+            smp = samples[i]
+            smp.op.attach_net(net)
+            loss, gy = sample_loss(net, smp, grad=True, loss_kind=loss_kind)
+            ls.append(loss)
+            feats.append(smp.feat)
+            gys.append(gy / len(idx))
+        net.backward(torch.cat(feats).contiguous(), torch.stack(gys).contiguous(), N, host_grads=False)
         net.adam_step(lr * (0.5 ** (it / max(steps // 3, 1))))
-        hist.append(loss)
-        if it % 100 == 0 or it == steps - 1:
-            log("train step %d loss %.4e" % (it, loss))
+        hist.append(float(np.mean(ls)))
+        if it % 50 == 0 or it == steps - 1:
+            log("train step %d loss %.4e" % (it, hist[-1]))
     return hist
 
 
-def target_energy(targs):
-    """Mean squared target (the loss of the zero network, i.e. of the plain diagonal-block
-    preconditioner in the same units)."""
-    return float((targs[:, :, :6].double() ** 2).mean())
+def mean_loss(net, samples, loss_kind="energy"):
+    out = []
+    for smp in samples:
+        smp.op.attach_net(net)
+        out.append(sample_loss(net, smp, loss_kind=loss_kind)[0])
+    return float(np.mean(out))
 
 
-def evaluate(weights, N=96, nk=8, m=16, guard=4, seed=1000, log=print, batch_k=None):
-    """Iterations and time to Res <= 1e-8 with and without the learned correction on a held-out
-    random geometry."""
+def evaluate(weights, N=96, nk=8, m=16, guard=4, seed=1000, log=print, batch_k=None, prec=None):
+    """Iterations and time to Res <= 1e-8 with the diagonal-block, the classical
+    transverse-projection and the learned preconditioner on a held-out random geometry."""
     torch = _torch()
     import paper_2511_17107_amd as kc
     import workloads as W
 
+    prec = kc.KC_PREC_FP32 if prec is None else prec
     wl = W.random_inclusions(N, seed, nk=40, m=m)
     sel = np.linspace(1, 39, nk).round().astype(int)
     op = kc.Op(N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
     op.set_kpoints(wl.kpoints[sel])
     net = kc.Net(seed=0)
-    net.set_params(np.load(weights))
+    if weights is not None:
+        net.set_params(np.load(weights))
     op.attach_net(net)
-    out = {}
+    out = {"N": N, "nk": nk, "m": m, "geometry_seed": seed}
     bk = batch_k or nk
-    for name, pc in (("diagonal", kc.KC_PRECOND_DIAG), ("learned", kc.KC_PRECOND_LEARNED)):
-        op.solve(m, nk=min(2, nk), tol=1e-8, guard=guard, batch_k=min(2, nk), precond=pc)  # warm-up
+    for name, pc in (("diagonal", kc.KC_PRECOND_DIAG), ("transverse", kc.KC_PRECOND_TRANSVERSE),
+                     ("learned", kc.KC_PRECOND_LEARNED)):
+        op.solve(m, nk=min(2, nk), tol=1e-8, guard=guard, batch_k=min(2, nk), precond=pc, prec=prec,
+                 switch_tol=3e-4)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        eig, res, its, st = op.solve(m, tol=1e-8, guard=guard, batch_k=bk, precond=pc)
+        eig, res, its, st = op.solve(m, tol=1e-8, guard=guard, batch_k=bk, precond=pc, prec=prec, switch_tol=3e-4)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         stats = op.last_solve_stats()
         out[name] = {"seconds": dt, "kpoints_per_s": nk / dt, "iterations": its.tolist(), "status": int(st),
-                     "max_res": float(res.max()), "eig": eig.tolist(), "kept_learned": float(stats[4])}
+                     "max_res": float(res.max()), "eig": eig.tolist(), "kept": float(stats[4])}
         log("%s: %.2f s, iterations %s, status %d" % (name, dt, its.tolist(), st))
-    e1, e2 = np.array(out["diagonal"]["eig"]), np.array(out["learned"]["eig"])
-    out["max_rel_eig_diff"] = float(np.max(np.abs(e1 - e2) / e1))
-    out["iteration_ratio"] = float(np.sum(out["learned"]["iterations"]) / np.sum(out["diagonal"]["iterations"]))
-    out["time_ratio"] = out["learned"]["seconds"] / out["diagonal"]["seconds"]
+    e0 = np.array(out["diagonal"]["eig"])
+    for name in ("transverse", "learned"):
+        e1 = np.array(out[name]["eig"])
+        out[name]["max_rel_eig_diff"] = float(np.max(np.abs(e1 - e0) / e0))
+        out[name]["iteration_ratio"] = float(np.sum(out[name]["iterations"]) / np.sum(out["diagonal"]["iterations"]))
+        out[name]["time_ratio"] = out[name]["seconds"] / out["diagonal"]["seconds"]
     return out
 
 
@@ -183,12 +236,14 @@ def main():
     t.add_argument("--out", required=True)
     t.add_argument("--N", type=int, default=32)
     t.add_argument("--geoms", type=int, default=32)
-    t.add_argument("--steps", type=int, default=1500)
-    t.add_argument("--lr", type=float, default=3e-4)
+    t.add_argument("--holdout", type=int, default=8)
+    t.add_argument("--steps", type=int, default=400)
+    t.add_argument("--batch", type=int, default=4)
+    t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--seed", type=int, default=0)
-    t.add_argument("--target", choices=["inverse", "error"], default="inverse")
+    t.add_argument("--loss", choices=["energy", "euclidean"], default="energy")
     e = sub.add_parser("eval")
-    e.add_argument("--weights", required=True)
+    e.add_argument("--weights", default=None)
     e.add_argument("--N", type=int, default=96)
     e.add_argument("--nk", type=int, default=8)
     e.add_argument("--json", default=None)
@@ -198,13 +253,17 @@ def main():
     if a.cmd == "train":
         net = kc.Net(seed=a.seed)
         t0 = time.time()
-        feats, targs = make_pairs(net, a.N, range(a.geoms), target=a.target)
-        print("pairs: %d samples in %.1f s, target energy %.4e" % (feats.shape[0], time.time() - t0,
-                                                                     target_energy(targs)), flush=True)
-        hist = train(net, feats, targs, a.N, steps=a.steps, lr=a.lr)
+        samples = make_samples(a.N, range(a.geoms))
+        held = make_samples(a.N, range(5000, 5000 + a.holdout), rng_seed=1)
+        l0_train, l0_held = mean_loss(net, samples, a.loss), mean_loss(net, held, a.loss)
+        print("samples: %d + %d held out in %.1f s; loss with E0: train %.4e held-out %.4e"
+              % (len(samples), len(held), time.time() - t0, l0_train, l0_held), flush=True)
+        hist = train(net, samples, steps=a.steps, batch=a.batch, lr=a.lr, loss_kind=a.loss)
         np.save(a.out, net.get_params())
-        print(json.dumps({"samples": int(feats.shape[0]), "target_energy": target_energy(targs),
-                          "loss_first": hist[0], "loss_last": float(np.mean(hist[-20:]))}), flush=True)
+        l1_train, l1_held = mean_loss(net, samples, a.loss), mean_loss(net, held, a.loss)
+        print(json.dumps({"samples": len(samples), "held_out": len(held), "loss_E0_train": l0_train,
+                          "loss_E0_held": l0_held, "loss_train": l1_train, "loss_held": l1_held,
+                          "steps": a.steps}), flush=True)
     else:
         out = evaluate(a.weights, N=a.N, nk=a.nk)
         s = json.dumps(out)

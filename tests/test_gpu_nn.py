@@ -1,7 +1,7 @@
 """The learned preconditioner's HIP kernels (through the C ABI) against the FP64 conv-net
-reference in oracle/nn.py: forward, gradients, a short training run, the feature map and the
-preconditioner application; and the eigen-solve with the learned preconditioner attached
-against the oracle's eigenvalues."""
+reference in oracle/nn.py: forward, gradients (from a loss and from a given output gradient), a
+short training run, the feature map, the learned field and the preconditioner application; and
+the eigen-solve with the learned preconditioner attached against the oracle's eigenvalues."""
 import json
 import math
 import os
@@ -17,7 +17,8 @@ from gpu_util import note, rel_err, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-LAYERS = [(32, 18), (32, 32), (6, 32)]
+LAYERS = [(32, 15), (32, 32), (3, 32)]
+NIN, NOUT = 15, 3
 
 
 def split(p):
@@ -59,7 +60,7 @@ def rand_net(seed, scale=0.08):
 
 def feats(rng, batch, N):
     x = rng.standard_normal((batch, N ** 3, 32)).astype(np.float32)
-    x[:, :, 18:] = 0.0
+    x[:, :, NIN:] = 0.0
     xb = bf16(x).astype(np.float32)
     return xb
 
@@ -75,10 +76,10 @@ def test_forward_matches_oracle():
     y = to_host(net.forward(to_dev(x).to(torch.bfloat16), N))
     params = split(p)
     for b in range(batch):
-        xo = x[b, :, :18].T.reshape(18, N, N, N).astype(np.float64)
+        xo = x[b, :, :NIN].T.reshape(NIN, N, N, N).astype(np.float64)
         ref = forward_bf16(params, xo)
-        assert rel_err(y[b, :, :6], to_cl(ref)) < 5e-3
-        assert np.all(y[b, :, 6:] == 0.0)
+        assert rel_err(y[b, :, :NOUT], to_cl(ref)) < 5e-3
+        assert np.all(y[b, :, NOUT:] == 0.0)
 
 
 def test_gradients_match_oracle():
@@ -89,7 +90,7 @@ def test_gradients_match_oracle():
     rng = np.random.default_rng(6)
     x = feats(rng, batch, N)
     t = np.zeros((batch, N ** 3, 16), dtype=np.float32)
-    t[:, :, :6] = rng.standard_normal((batch, N ** 3, 6))
+    t[:, :, :NOUT] = rng.standard_normal((batch, N ** 3, NOUT))
     note("nn gradients")
     loss, g = net.gradients(to_dev(x).to(torch.bfloat16), to_dev(t), N)
     params = [(bf16(w), b) for w, b in split(p)]
@@ -97,22 +98,51 @@ def test_gradients_match_oracle():
     gsum = None
     L = 0.0
     for b in range(batch):
-        xo = x[b, :, :18].T.reshape(18, N, N, N).astype(np.float64)
-        to = t[b, :, :6].T.reshape(6, N, N, N).astype(np.float64)
+        xo = x[b, :, :NIN].T.reshape(NIN, N, N, N).astype(np.float64)
+        to = t[b, :, :NOUT].T.reshape(NOUT, N, N, N).astype(np.float64)
         y, cache = nn.forward(params, xo)
         L += np.sum((y - to) ** 2)
-        gy = 2.0 * (y - to) / (batch * N ** 3 * 6)
+        gy = 2.0 * (y - to) / (batch * N ** 3 * NOUT)
         gr, _ = nn.backward(params, xo, cache, gy)
         flat = np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in gr])
         gsum = flat if gsum is None else gsum + flat
-    L /= batch * N ** 3 * 6
+    L /= batch * N ** 3 * NOUT
     assert loss == pytest.approx(L, rel=2e-2)
+    _compare_grads(g, gsum)
+
+
+def _compare_grads(g, ref):
+    """Weights within 5%; biases within 10% (a bias gradient sums BF16 back-propagated values
+    over every cell of the batch, with heavy cancellation)."""
     off = 0
     for co, ci in LAYERS:
         nw = co * ci * 27
-        assert rel_err(g[off:off + nw], gsum[off:off + nw]) < 5e-2, (co, ci)
-        assert rel_err(g[off + nw:off + nw + co], gsum[off + nw:off + nw + co]) < 5e-2
+        assert rel_err(g[off:off + nw], ref[off:off + nw]) < 5e-2, (co, ci)
+        assert rel_err(g[off + nw:off + nw + co], ref[off + nw:off + nw + co]) < 1e-1, (co, ci)
         off += nw + co
+
+
+def test_backward_from_output_gradient_matches_oracle():
+    import torch
+
+    N, batch = 16, 2
+    net, p = rand_net(7)
+    rng = np.random.default_rng(8)
+    x = feats(rng, batch, N)
+    gout = np.zeros((batch, N ** 3, 16), dtype=np.float32)
+    gout[:, :, :NOUT] = bf16(1e-3 * rng.standard_normal((batch, N ** 3, NOUT)))  # the kernel's rounding
+    note("nn backward")
+    g = net.backward(to_dev(x).to(torch.bfloat16), to_dev(gout), N)
+    params = [(bf16(w), b) for w, b in split(p)]
+    gsum = None
+    for b in range(batch):
+        xo = x[b, :, :NIN].T.reshape(NIN, N, N, N).astype(np.float64)
+        y, cache = nn.forward(params, xo)
+        gy = gout[b, :, :NOUT].T.reshape(NOUT, N, N, N).astype(np.float64)
+        gr, _ = nn.backward(params, xo, cache, gy)
+        flat = np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in gr])
+        gsum = flat if gsum is None else gsum + flat
+    _compare_grads(g, gsum)
 
 
 def test_training_reduces_loss():
@@ -127,7 +157,7 @@ def test_training_reduces_loss():
     net = kc.Net(seed=13)
     note("nn training")
     l0, _ = net.gradients(x, t, N, host_grads=False)
-    for step in range(150):
+    for step in range(300):
         loss, _ = net.gradients(x, t, N, host_grads=False)
         net.adam_step(2e-3)
     assert loss < 0.2 * l0, (l0, loss)
@@ -140,61 +170,52 @@ def _op16():
     return wl, op
 
 
+def _ref_features(wl, ik):
+    """Network input by its definition: inverse permittivity (9), log E0 (3), k/pi (3)."""
+    N = wl.N
+    P = yee.point_tensors(wl.ids, wl.table)
+    ref = np.zeros((N ** 3, 32))
+    ref[:, 0] = P[0][:, 0, 0].real
+    ref[:, 1] = P[1][:, 1, 1].real
+    ref[:, 2] = P[2][:, 2, 2].real
+    for q, (a, b) in enumerate([(0, 1), (0, 2), (1, 2)]):
+        ref[:, 3 + 2 * q] = P[3][:, a, b].real
+        ref[:, 4 + 2 * q] = P[3][:, a, b].imag
+    ref[:, 9:12] = np.log(kspace.edge_permittivity(wl.ids, wl.table)).T
+    ref[:, 12:15] = wl.kpoints[ik] / math.pi
+    return ref
+
+
 def test_features_match_definition():
     import torch
 
     wl, op = _op16()
-    net, p = rand_net(21)
-    op.attach_net(net)
-    N = 16
-    r = W.random_block(22, 2, N)
     note("nn features")
-    f = to_host(op.net_features(to_dev(r), ik0=1, vecs_per_k=1).to(torch.float32))
-    P = yee.point_tensors(wl.ids, wl.table)
-    for v in range(2):
-        real = kspace.F3(r[v:v + 1], N)[0] * math.sqrt(3 * N ** 3) / np.linalg.norm(r[v])
-        ref = np.zeros((N ** 3, 32))
-        for c in range(3):
-            ref[:, 2 * c] = real[c].real
-            ref[:, 2 * c + 1] = real[c].imag
-        ref[:, 6] = P[0][:, 0, 0].real
-        ref[:, 7] = P[1][:, 1, 1].real
-        ref[:, 8] = P[2][:, 2, 2].real
-        for q, (a, b) in enumerate([(0, 1), (0, 2), (1, 2)]):
-            ref[:, 9 + 2 * q] = P[3][:, a, b].real
-            ref[:, 10 + 2 * q] = P[3][:, a, b].imag
-        ref[:, 15:18] = wl.kpoints[1 + v] / math.pi
-        assert np.max(np.abs(f[v] - ref)) <= 1e-2 * max(1.0, np.abs(ref).max())
+    f = to_host(op.net_features(ik0=1, nk=2).to(torch.float32))
+    for b in range(2):
+        ref = _ref_features(wl, 1 + b)
+        assert np.max(np.abs(f[b] - ref)) <= 1e-2 * max(1.0, np.abs(ref).max())
 
 
-def test_precond_learned_matches_definition():
-    import torch
-
+def test_learned_field_and_precond_match_definition():
+    """E = E0 exp(clamp(net, -3, 3)) against the oracle's conv net on the same features, and
+    kc_precond_learned = T_E with that field against the oracle's pseudo-inverse definition."""
     wl, op = _op16()
     net, p = rand_net(31, scale=0.05)
     op.attach_net(net)
     N = 16
-    r = W.random_block(32, 1, N)
+    note("nn efield")
+    E = to_host(op.net_efield(ik0=2, nk=1))[0].astype(np.float64)
+    x = bf16(_ref_features(wl, 2)[:, :NIN].T).reshape(NIN, N, N, N)
+    y = forward_bf16(split(p), x).reshape(NOUT, -1)
+    Eref = kspace.edge_permittivity(wl.ids, wl.table) * np.exp(np.clip(y, -3, 3))
+    assert rel_err(E, Eref) < 5e-3
+    assert np.abs(np.log(E / kspace.edge_permittivity(wl.ids, wl.table))).max() > 1e-2  # not trivial
+    r = W.random_block(32, 2, N)
     note("nn precond")
     z = to_host(op.precond_learned(to_dev(r), ik0=2))
-    g = op.gamma()[2]
-    base = kspace.precond_apply(N, wl.kpoints[2], g, r)
-    # the network reads the diagonal-block preconditioned residual, in units of its RMS value
-    real = kspace.F3(base, N)[0] * math.sqrt(3 * N ** 3) / np.linalg.norm(base[0])
-    P = yee.point_tensors(wl.ids, wl.table)
-    x = np.zeros((18, N ** 3))
-    for c in range(3):
-        x[2 * c], x[2 * c + 1] = real[c].real, real[c].imag
-    x[6], x[7], x[8] = P[0][:, 0, 0].real, P[1][:, 1, 1].real, P[2][:, 2, 2].real
-    for q, (a, b) in enumerate([(0, 1), (0, 2), (1, 2)]):
-        x[9 + 2 * q], x[10 + 2 * q] = P[3][:, a, b].real, P[3][:, a, b].imag
-    x[15:18] = (wl.kpoints[2] / math.pi)[:, None]
-    y = forward_bf16(split(p), bf16(x).reshape(18, N, N, N)).reshape(6, -1)
-    delta = np.stack([y[0] + 1j * y[1], y[2] + 1j * y[3], y[4] + 1j * y[5]])
-    delta *= np.linalg.norm(base) / math.sqrt(3 * N ** 3)
-    corr = kspace.F3H(delta[None], N)
-    assert rel_err(z - base, corr) < 3e-2
-    assert np.linalg.norm(corr) > 1e-3 * np.linalg.norm(base)
+    ref = kspace.transverse_precond_apply(N, wl.kpoints[2], op.gamma()[2], E, r)
+    assert rel_err(z, ref) < 1e-10
 
 
 def test_solve_with_learned_preconditioner_matches_oracle():

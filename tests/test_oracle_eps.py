@@ -182,3 +182,67 @@ def test_preconditioned_rayleigh_bound(scheme, k):
     Ph = (VP * np.sqrt(wP)[None, :]) @ VP.conj().T
     ev = np.linalg.eigvalsh(Ph @ Op @ Ph)
     assert ev.min() >= lo - 1e-10 and ev.max() <= hi + 1e-10
+
+
+@pytest.mark.parametrize("k", [(0.3, 0.5, 0.7), (0.0, 0.0, 0.0), (math.pi, math.pi, math.pi)])
+def test_transverse_precond_unit_field_is_kp_inverse(k):
+    """T_E with E = 1 is the pseudo-inverse of K_A K_A^H plus that of gamma K_B; the two ranges
+    are orthogonal (K_B K_A = 0, Lemma 2.4), so the sum is K_P^{-1} of eq (2.32), zero at the
+    k = 0 DC frequency."""
+    N = 4
+    g = yee.gamma_rule(k)
+    r = W.random_block(8, 2, N)
+    z = kspace.transverse_precond_apply(N, k, g, np.ones((3, N ** 3)), r)
+    ref = kspace.precond_apply(N, k, g, r)
+    assert np.allclose(z, ref, atol=1e-11 * abs(ref).max())
+
+
+@pytest.mark.parametrize("k", [(0.3, 0.5, 0.7), (-1.1, 0.2, 2.9)])
+def test_transverse_precond_inverts_homogeneous_operator(k):
+    """Homogeneous isotropic medium eps = e I: Op = (1/e) K_A K_A^H + gamma K_B in k-space, so
+    T_E with E = e (the classical field 1/(eps^-1)_cc) is its exact inverse; checked as
+    T_E Op x = x on random vectors, with Op the sparse operator conjugated by the DFT."""
+    N = 4
+    e = 9.0
+    ids = np.ones((4, N ** 3), dtype=np.uint8)
+    tab = W.eps_table([e * np.eye(3)])
+    g = yee.gamma_rule(k)
+    E0 = kspace.edge_permittivity(ids, tab)
+    assert np.allclose(E0, e)
+    Op = yee.compensated_operator(N, k, ids, tab, "crossdof")
+    x = W.random_block(9, 2, N)
+    y = kspace.kspace_apply(Op, x, N)
+    z = kspace.transverse_precond_apply(N, k, g, E0, y)
+    assert np.allclose(z, x, atol=1e-10 * abs(x).max())
+
+
+@pytest.mark.parametrize("k", [(0.3, 0.5, 0.7), (0.0, 0.0, 0.0)])
+def test_transverse_precond_hermitian_psd(k):
+    """For a positive field T_E is Hermitian positive semi-definite; its null space is the
+    k = 0 DC frequency only (three vectors at k = 0, none otherwise)."""
+    N = 3
+    rng = np.random.default_rng(5)
+    E = rng.uniform(1.0, 14.0, size=(3, N ** 3))
+    g = yee.gamma_rule(k)
+    n = 3 * N ** 3
+    I = np.eye(n, dtype=complex).reshape(n, 3, N ** 3)
+    T = kspace.transverse_precond_apply(N, k, g, E, I).reshape(n, n).T
+    assert np.allclose(T, T.conj().T, atol=1e-12 * abs(T).max())
+    ev = np.linalg.eigvalsh(0.5 * (T + T.conj().T))
+    assert ev.min() > -1e-12 * ev.max()
+    nz = int(np.sum(ev < 1e-10 * ev.max()))
+    assert nz == (3 if np.allclose(k, 0) else 0)
+
+
+def test_edge_permittivity_reads_edge_points():
+    """E0_c comes from the material at the c-edge points, and is the reciprocal of the
+    diagonal entry of the stored inverse tensor (not the diagonal of the tensor's inverse)."""
+    N = 2
+    T = np.array([[10.0, 2.0, 0.0], [2.0, 6.0, 0.0], [0.0, 0.0, 4.0]])
+    tab = W.eps_table([T])
+    ids = np.zeros((4, N ** 3), dtype=np.uint8)
+    ids[1, 3] = 1  # one y-edge point inside material 1
+    E0 = kspace.edge_permittivity(ids, tab)
+    inv = np.linalg.inv(T)
+    assert E0[1, 3] == pytest.approx(1.0 / inv[1, 1])
+    assert np.allclose(np.delete(E0[1], 3), 1.0) and np.allclose(E0[0], 1.0) and np.allclose(E0[2], 1.0)
