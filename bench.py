@@ -25,6 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of a pass, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0),
+# the factors read off a plain 1 GiB device copy in the same run
+# (profiles/matvec_woodpile128_fp32_16vec.md); keyed by pass, N, vectors, precision.
+MEASURED_TRAFFIC = {("X2", 128, 16, "fp32"): 4.030e9}
 
 
 def parse():
@@ -41,7 +45,12 @@ def parse():
     ap.add_argument("--switch-tol", type=float, default=3e-4)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=600)
+    ap.add_argument("--precond", choices=["diag", "transverse"], default="transverse",
+                    help="LOBPCG preconditioner: diagonal-block K_P^-1 or transverse-projection T_E")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only the operator application on one block (and a plain device copy of known "
+                         "size, the reference for hardware byte counters); for profiling")
     ap.add_argument("--verbose", type=int, default=0)
     return ap.parse_args()
 
@@ -90,6 +99,23 @@ def cpu_baseline(kpath):
                       "(%.1f s); the oracle cannot factor the N=128 operator" % dt}
 
 
+def matvec_only(a, op, prec, dev):
+    """Three operator applications on one block of a.m vectors, then three copies of a 1 GiB
+    buffer (torch's copy kernel: 1 GiB read + 1 GiB written per launch)."""
+    import torch
+
+    x = torch.randn((a.m, 3, a.N ** 3), dtype=torch.complex128, device=dev)
+    for r in range(3):
+        y = op.apply(x, prec=prec)
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for r in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"matvec_vectors": a.m, "N": a.N, "copy_bytes_each_way": src.numel() * 8,
+                      "checksum": float(y.abs().sum()) + float(dst[0])}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -108,6 +134,7 @@ def main():
     op = kc.Op(wl.N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
     op.set_kpoints(wl.kpoints)
     prec = kc.KC_PREC_FP32 if a.prec == "fp32" else kc.KC_PREC_FP64
+    pc = kc.KC_PRECOND_TRANSVERSE if a.precond == "transverse" else kc.KC_PRECOND_DIAG
     nsteps_path = a.nk // a.kpb
 
     # k-points reordered so that batch s holds path points s, s + P, s + 2P, ... (P = nk/kpb):
@@ -115,11 +142,15 @@ def main():
     order = np.concatenate([[(s + j * nsteps_path) for j in range(a.kpb)] for s in range(nsteps_path)])
     op.set_kpoints(wl.kpoints[order])
 
+    if a.matvec_only:
+        matvec_only(a, op, prec, dev)
+        return
+
     def run_step(step):
         ik0 = (step % nsteps_path) * a.kpb
         eig, res, its, st = op.solve(a.m, ik0=ik0, nk=a.kpb, tol=a.tol, maxit=a.maxit, prec=prec,
                                      switch_tol=a.switch_tol, batch_k=a.kpb, guard=a.guard,
-                                     verbose=a.verbose, check=True)
+                                     verbose=a.verbose, check=True, precond=pc)
         return ik0, eig, res, its, st, op.last_solve_stats()
 
     for w in range(a.warmup):
@@ -171,7 +202,7 @@ def main():
         "config": {"workload": "sc128-woodpile-gyrotropic-crossdof, 16 bands (+%d guard), "
                                "%d k-points/step of the 60-point G-X-M-G-R path" % (a.guard, a.kpb),
                    "N": a.N, "bands": a.m, "kpoints_per_step": a.kpb, "tol": a.tol,
-                   "precision": a.prec},
+                   "precision": a.prec, "preconditioner": a.precond},
         "converged": converged,
         "max_residual": maxres,
         "iterations": iters,
@@ -179,7 +210,9 @@ def main():
         "matvecs_fp32": mv32,
         "roofline": {"bound": "hbm", "kernel": "matvec pass " + names[dom],
                      "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs[dom] / HBM_PEAK_GBS, "traffic": None},
+                     "frac": gbs[dom] / HBM_PEAK_GBS,
+                     "traffic": MEASURED_TRAFFIC.get((names[dom], a.N, a.m, a.prec)),
+                     "alg_bytes": pbytes[dom]},
         "matvec": {"passes": names, "ms": [round(float(t), 4) for t in ms],
                    "alg_GBps": [round(g, 1) for g in gbs], "nvec": a.m,
                    "ms_per_band": mv_time / a.m,
