@@ -180,9 +180,13 @@ typedef struct kc_solve_opts {
   uint64_t seed;      /* seed of the random initial block                                  */
   int verbose;        /* 1: print per-iteration residuals to stderr                        */
   int precond;        /* KC_PRECOND_DIAG, _TRANSVERSE or _LEARNED (needs kc_attach_net)    */
+  int graph;          /* 1: capture each iteration's launches (preconditioner, operator,   */
+                      /* Rayleigh-Ritz, update, residuals) once per precision in a hipGraph */
+                      /* and replay it, on a private stream; 0: launch them one by one      */
 } kc_solve_opts;
 
-/* Fill opts with defaults (m = 10, guard = 0, tol = 1e-8, maxit = 500, FP64, batch_k = 1). */
+/* Fill opts with defaults (m = 10, guard = 0, tol = 1e-8, maxit = 500, FP64, batch_k = 1,
+ * diagonal-block preconditioner, graph = 1). */
 void kc_solve_opts_default(kc_solve_opts* opts);
 
 /*

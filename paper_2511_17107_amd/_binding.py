@@ -36,6 +36,7 @@ class KcSolveOpts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("verbose", ctypes.c_int),
         ("precond", ctypes.c_int),
+        ("graph", ctypes.c_int),
     ]
 
 
@@ -244,7 +245,7 @@ class Op:
     def solve(self, m: int, ik0: int = 0, nk: Optional[int] = None, tol: float = 1e-8, maxit: int = 500,
               prec: int = KC_PREC_FP64, switch_tol: float = 1e-3, batch_k: int = 1, guard: int = 0,
               seed: int = 1234, X_out=None, verbose: int = 0, stream=None, check: bool = True,
-              precond: int = KC_PRECOND_DIAG):
+              precond: int = KC_PRECOND_DIAG, graph: bool = True):
         """Smallest positive eigenvalues for k-points ik0 .. ik0+nk-1.  Returns
         (eig (nk, m), res (nk, m), iters (nk,), status)."""
         nk = self.nk - ik0 if nk is None else int(nk)
@@ -253,6 +254,7 @@ class Op:
         o.m, o.guard, o.tol, o.maxit, o.prec = int(m), int(guard), float(tol), int(maxit), int(prec)
         o.switch_tol, o.batch_k, o.seed, o.verbose = float(switch_tol), int(batch_k), int(seed), int(verbose)
         o.precond = int(precond)
+        o.graph = 1 if graph else 0
         eig = np.zeros((nk, m))
         res = np.zeros((nk, m))
         its = np.zeros(nk, dtype=np.int32)

@@ -34,6 +34,10 @@ struct SolverWork {
   DevBuf theta, res, xn2;
   DevBuf R, tmask;  // residuals (input of T_E) and the columns that get T_E R
   DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal [nb each]
+  hipStream_t gstream = nullptr;  // private stream of graph-captured solves (default priority)
+  ~SolverWork() {
+    if (gstream) (void)hipStreamDestroy(gstream);
+  }
 };
 
 void solver_release(kc_op* op) {
@@ -153,6 +157,10 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
     KC_TRY(w->tmask.ensure((size_t)nb * mb * sizeof(int)));
   }
   KC_TRY(w->ints.ensure((size_t)(4 * nb * mb + 3 * nb) * sizeof(int)));
+  // operator work buffers at their largest (FP64) size up front: captured iterations keep
+  // their pointers, so no buffer may move after a capture
+  KC_TRY(op->work_a.ensure((size_t)nb * mb * n * sizeof(c64)));
+  if (op->scheme == KC_EPS_CROSSDOF) KC_TRY(op->work_b.ensure((size_t)nb * mb * n * sizeof(c64)));
   B.S = w->S.as<c64>();
   B.AS = w->AS.as<c64>();
   int* ib = w->ints.as<int>();
@@ -200,14 +208,54 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   std::fill(hx.begin(), hx.end(), 1);
   KC_TRY(upload_ints(B.xmask, hx, s));
 
+  // One iteration's device work after the masks are uploaded: W = T_E R on the active
+  // columns, AW = Op W, Rayleigh-Ritz and update, then the next residuals.  With o.graph it is
+  // captured once per precision into a hipGraph and replayed; every launch has a fixed grid
+  // (masked columns exit early), reads its masks from device memory and writes to buffers
+  // sized before the first capture.
+  auto body = [&](int pr) -> int {
+    if (tp) KC_TRY(precond_tp(B));
+    KC_TRY(apply_cols(B, mb, B.wmask, pr));
+    KC_TRY(rayleigh_ritz(B));
+    return residuals(B, tp);
+  };
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  struct GraphGuard {
+    hipGraphExec_t* g;
+    ~GraphGuard() {
+      for (int i = 0; i < 2; ++i)
+        if (g[i]) (void)hipGraphExecDestroy(g[i]);
+    }
+  } gguard{gexec};
+  auto run_body = [&](int pr) -> int {
+    if (!o.graph) return body(pr);
+    const int slot = (pr == KC_PREC_FP64) ? 1 : 0;
+    if (!gexec[slot]) {
+      KC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      const int st = body(pr);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &g);
+      if (st != KC_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      KC_HIP(e);
+      const hipError_t ei = hipGraphInstantiate(&gexec[slot], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      KC_HIP(ei);
+    }
+    KC_HIP(hipGraphLaunch(gexec[slot], s));
+    return KC_OK;
+  };
+
   int it = 0;
   double best_max = 1e300;
   int stall = 0;
   bool verify_pending = false;
+  bool need_resid = true;
   while (true) {
-    bool use_tp = false;
-    for (int b = 0; b < nb; ++b) use_tp = use_tp || (lon[b] && !done[b]);
-    KC_TRY(residuals(B, use_tp));
+    if (need_resid) KC_TRY(residuals(B, tp));
+    need_resid = true;
     KC_HIP(hipMemcpyAsync(hres.data(), w->res.p, hres.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     KC_HIP(hipMemcpyAsync(hpv.data(), B.pvalid, hpv.size() * sizeof(int), hipMemcpyDeviceToHost, s));
     KC_HIP(hipMemcpyAsync(hflags.data(), B.flags, hflags.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -353,7 +401,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
     KC_TRY(upload_ints(B.wmask, hw, s));
     KC_TRY(upload_ints(B.pmask, hp, s));
     KC_TRY(upload_ints(B.kskip, hskip, s));
-    if (use_tp) {
+    if (tp) {
       int nt = 0;
       for (int b = 0; b < nb; ++b)
         for (int j = 0; j < mb; ++j) {
@@ -362,12 +410,11 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
           nt += ht[i];
         }
       KC_TRY(upload_ints(B.w->tmask.as<int>(), ht, s));
-      KC_TRY(precond_tp(B));
       napp += nt;
     }
-    KC_TRY(apply_cols(B, mb, B.wmask, prec));
+    KC_TRY(run_body(prec));
+    need_resid = false;
     (prec == KC_PREC_FP64 ? nmv64 : nmv32) += nact;
-    KC_TRY(rayleigh_ritz(B));
     ++it;
   }
   // results
@@ -415,6 +462,7 @@ void kc_solve_opts_default(kc_solve_opts* o) {
   o->seed = 1234;
   o->verbose = 0;
   o->precond = KC_PRECOND_DIAG;
+  o->graph = 1;
 }
 
 int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_host, double* res_host,
@@ -430,6 +478,14 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   KC_ARG(o.precond == KC_PRECOND_DIAG || o.precond == KC_PRECOND_LEARNED || o.precond == KC_PRECOND_TRANSVERSE,
          "precond");
   hipStream_t s = (hipStream_t)stream;
+  if (o.graph) {
+    // captured iterations run on a private stream (a capture cannot use the legacy default
+    // stream); the solve is synchronous, so ordering with the caller's stream is a sync
+    if (!op->solver) op->solver = new kc::SolverWork();
+    if (!op->solver->gstream) KC_HIP(hipStreamCreateWithFlags(&op->solver->gstream, hipStreamNonBlocking));
+    KC_HIP(hipStreamSynchronize(s));
+    s = op->solver->gstream;
+  }
   auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < 8; ++i) op->stats[i] = 0.0;
   bool allc = true;
@@ -442,6 +498,7 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
                            &c));
     allc = allc && c;
   }
+  KC_HIP(hipStreamSynchronize(s));
   op->stats[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (!allc) {
     kc::set_error("some k-points did not reach tol within maxit");

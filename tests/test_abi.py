@@ -86,3 +86,16 @@ def test_null_handle_arguments():
     assert L.kc_solve(None, 0, 1, None, None, None, None, None, None) == 1
     assert b"NULL" in L.kc_last_error() or b"invalid" in L.kc_last_error()
     L.kc_destroy(None)
+
+
+def test_solve_opts_defaults():
+    """kc_solve_opts_default is host-only: the struct layout of the binding matches the header."""
+    import ctypes
+
+    from paper_2511_17107_amd import _binding as B
+
+    o = B.KcSolveOpts()
+    B.lib().kc_solve_opts_default(ctypes.byref(o))
+    assert (o.m, o.guard, o.maxit, o.prec, o.batch_k, o.precond, o.graph) == (10, 0, 500, B.KC_PREC_FP64, 1,
+                                                                              B.KC_PRECOND_DIAG, 1)
+    assert o.tol == 1e-8 and o.seed == 1234

@@ -139,3 +139,21 @@ def test_no_convergence_status():
     eig, res, its, st = op.solve(4, tol=1e-12, maxit=2)
     assert st == 6
     assert np.all(np.isfinite(eig)) and its[0] == 2
+
+
+@pytest.mark.parametrize("prec,pc", [(kc.KC_PREC_FP32, kc.KC_PRECOND_TRANSVERSE), (kc.KC_PREC_FP64, kc.KC_PRECOND_DIAG)])
+def test_graph_replay_matches_eager(prec, pc):
+    """The hipGraph-captured iteration (replayed every iteration, with the host's mask uploads
+    and synchronisations in between) gives the same iterates as one-by-one launches: same
+    iteration counts, eigenvalues and residuals to rounding."""
+    wl = W.sphere_anisotropic(N=16, nk=9, m=10)
+    kpts = wl.kpoints[[0, 2, 4, 6, 8]]
+    res = {}
+    for graph in (False, True):
+        op = kc.Op(16, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+        op.set_kpoints(kpts)
+        note("solve graph=%s prec=%d pc=%d" % (graph, prec, pc))
+        res[graph] = op.solve(10, tol=TOL, batch_k=5, guard=2, prec=prec, switch_tol=1e-4, precond=pc, graph=graph)
+        assert res[graph][3] == 0 and res[graph][1].max() <= TOL
+    assert np.array_equal(res[True][2], res[False][2])
+    assert np.max(np.abs(res[True][0] - res[False][0]) / res[False][0]) <= 1e-12
