@@ -183,28 +183,39 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
                                                 int p, int q, int skstride, int scol0, int ykstride, int q1,
                                                 int ycol0, int ycol1, const int* __restrict__ kskip) {
   constexpr int PK = RR_NMAX / 4;  // input columns in groups of 4 (p <= 64)
-  extern __shared__ c64 csh[];     // C_b, p x q
+  constexpr int QP = TQ * 16;      // output columns padded to whole tiles
+  extern __shared__ c64 csh[];     // C_b zero-padded to (4 PK) x QP
   const int b = blockIdx.y;
   if (kskip && kskip[b]) return;
   const c64* Cb = C + (size_t)b * p * q;
-  for (int t = threadIdx.x; t < p * q; t += blockDim.x) csh[t] = Cb[t];
+  for (int t = threadIdx.x; t < 4 * PK * QP; t += blockDim.x) {
+    const int r = t / QP, c = t % QP;
+    csh[t] = (r < p && c < q) ? Cb[r * q + c] : mk(0.0, 0.0);
+  }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const c64* Sb = S + ((size_t)b * skstride + scol0) * n;
   c64* Yb = Y + (size_t)b * ykstride * n;
   const size_t nblk = (n + 15) / 16;
-  const int pk = (p + 3) / 4;
   for (size_t rb = (size_t)blockIdx.x * 4 + wave; rb < nblk; rb += (size_t)gridDim.x * 4) {
     const size_t row = rb * 16 + li;
     const bool rok = row < n;
-    // all inputs of this wave's 16 rows first (many loads in flight), then the MFMAs
+    // all inputs of this wave's 16 rows first (many loads in flight), then the MFMAs.  Loads
+    // are unconditional (row and column clamped into range): columns past p meet zero rows of
+    // the padded C, rows past n are not stored.
+    const size_t rowc = rok ? row : n - 1;
+    // C is re-read from LDS for every row block: kept in registers across the loop it would
+    // take 3/4 of the register file and halve the occupancy
+    asm volatile("" ::: "memory");
     c64 sv[PK];
 #pragma unroll
     for (int kb = 0; kb < PK; ++kb) {
-      const int c = kb * 4 + lk;
-      sv[kb] = (kb < pk && rok && c < p) ? Sb[(size_t)c * n + row] : mk(0.0, 0.0);
+      const int c = min(kb * 4 + lk, p - 1);
+      sv[kb] = Sb[(size_t)c * n + rowc];
     }
+    // keep every load issued ahead of the MFMAs (each MFMA group then waits only for its own)
+    asm volatile("" ::: "memory");
     d4 re[TQ], im[TQ];
 #pragma unroll
     for (int t = 0; t < TQ; ++t) {
@@ -213,19 +224,23 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
     }
 #pragma unroll
     for (int kb = 0; kb < PK; ++kb) {
-      if (kb < pk) {
-        const int ca = kb * 4 + lk;
+      const int ca = kb * 4 + lk;
+      // A operand lane (i = li -> output column, k = lk -> input column): C[k][i];
+      // B operand lane (k = lk -> input column, j = li -> row): S[row][k]
+      c64 cv[TQ];
 #pragma unroll
-        for (int t = 0; t < TQ; ++t) {
-          const int j = t * 16 + li;
-          // A operand lane (i = li -> output column, k = lk -> input column): C[k][i];
-          // B operand lane (k = lk -> input column, j = li -> row): S[row][k]
-          const c64 cv = (ca < p && j < q) ? csh[ca * q + j] : mk(0.0, 0.0);
-          re[t] = mfma(cv.re, sv[kb].re, re[t]);
-          im[t] = mfma(cv.re, sv[kb].im, im[t]);
-          re[t] = mfma(-cv.im, sv[kb].im, re[t]);
-          im[t] = mfma(cv.im, sv[kb].re, im[t]);
-        }
+      for (int t = 0; t < TQ; ++t) cv[t] = csh[ca * QP + t * 16 + li];
+      const double nsi = -sv[kb].im;
+      // the two products of each accumulator are TQ x 2 MFMAs apart
+#pragma unroll
+      for (int t = 0; t < TQ; ++t) {
+        re[t] = mfma(cv[t].re, sv[kb].re, re[t]);
+        im[t] = mfma(cv[t].re, sv[kb].im, im[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < TQ; ++t) {
+        re[t] = mfma(cv[t].im, nsi, re[t]);
+        im[t] = mfma(cv[t].im, sv[kb].re, im[t]);
       }
     }
     // output lane holds D[lk + 4r][li]: output column t*16 + lk + 4r, row rb*16 + li
@@ -380,7 +395,11 @@ int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, i
   const size_t nblk = (n + 15) / 16;
   const unsigned gx = (unsigned)std::max<size_t>(1, std::min<size_t>((nblk + 3) / 4, 4096 / std::max(nb, 1) + 1));
   dim3 grid(gx, nb);
-  const size_t shm = (size_t)p * q * sizeof(c64);
+  const size_t shm = (size_t)RR_NMAX * ((q + 15) / 16 * 16) * sizeof(c64);
+  if (p > RR_NMAX) {
+    set_error("update: too many input columns");
+    return KC_ERR_INVALID_ARG;
+  }
   if (q <= 16) {
     k_update<1><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, kskip);
   } else if (q <= 32) {
