@@ -23,17 +23,22 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // Gram matrices of the Rayleigh-Ritz step: GA_b = S_b^H AS_b and GB_b = S_b^H S_b (nc x nc,
 // Hermitian: only the 16x16 tiles on and above the diagonal are formed).  Complex products on
 // real MFMA: with a = ar + i ai, b = br + i bi,
-//   Re(conj(a) b) = ar br + ai bi,   Im(conj(a) b) = ar bi - ai br,
-// so a 16x16 tile over 4 rows is four real MFMAs whose A operands are the real and imaginary
-// parts of 4 rows of 16 S-columns and whose B operands are (br, bi) and (bi, -br).
-// A workgroup owns a chunk of rows of one k-point; it stages 16 rows of all 2 nc columns
-// (S and AS) in LDS with coalesced loads, so each column is read from HBM once, and its 4
-// waves share the tiles.  Partial tiles per chunk are summed in a fixed order afterwards.
+//   Re(conj(a) b) = ar br + ai bi,   Im(conj(a) b) = ar bi - ai br
+//                 = P1 + P2,                      = P3 - P1 + P2
+// with P1 = ar br, P2 = ai bi, P3 = (ar - ai)(br + bi) (Gauss): a 16x16 tile over 4 rows is
+// three real MFMAs.  A workgroup owns a chunk of rows of one k-point; it stages 16 rows of all
+// 2 nc columns (S and AS) in LDS with coalesced loads, so each column is read from HBM once,
+// and its 8 waves share the tiles (wave w and w + 4 run on one SIMD: 5 tiles per SIMD at
+// nc <= 64).  Partial tiles per chunk are summed in a fixed order
+// afterwards.
 // ------------------------------------------------------------------------------------
 constexpr int G2_ROWS = 16;
-constexpr int G2_PITCH = 2 * 64 + 1;  // LDS row pitch (complex), odd to spread banks
+constexpr int G2_COLS = 64;                       // S at [0, 64), AS at [64, 128) of a stage row
+constexpr int G2_ZERO = 2 * G2_COLS;              // 16 zero entries (tiles a wave does not own)
+constexpr int G2_PITCH = 2 * G2_COLS + 16 + 1;    // LDS row pitch (complex), odd to spread banks
+constexpr int G2_THREADS = 512;                   // 8 waves
 
-__global__ __launch_bounds__(256) void k_gram2(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
+__global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
                                                int nc, int kstride, int rows_per_chunk, int ntile,
                                                c64* __restrict__ part, const int* __restrict__ kskip) {
   __shared__ c64 st[G2_ROWS * G2_PITCH];
@@ -43,39 +48,47 @@ __global__ __launch_bounds__(256) void k_gram2(const c64* __restrict__ S, const 
   const int T = (nc + 15) / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  // this wave's tiles: t = wave, wave + 4, ...; t -> (mat, ti, tj), ti <= tj
-  constexpr int MAXT = 5;
+  // this wave's tiles: t = wave, wave + 8, ...; t -> (mat, ti, tj), ti <= tj
+  constexpr int MAXT = 3;
+  // tiles past nt read the zero entries of the stage rows
   int tmat[MAXT], tti[MAXT], ttj[MAXT];
+  for (int t = 0; t < MAXT; ++t) {
+    tmat[t] = 1;
+    tti[t] = ttj[t] = G2_ZERO / 16;
+  }
   int nt = 0;
   {
     int t = 0;
     for (int mat = 0; mat < 2; ++mat)
       for (int i = 0; i < T; ++i)
         for (int j = i; j < T; ++j, ++t)
-          if ((t & 3) == wave && nt < MAXT) {
+          if ((t & 7) == wave && nt < MAXT) {
             tmat[nt] = mat;
             tti[nt] = i;
             ttj[nt] = j;
             ++nt;
           }
   }
-  d4 re[MAXT], im[MAXT];
+  // three real products per complex one (Gauss): P1 = Ar Br, P2 = Ai Bi,
+  // P3 = (Ar - Ai)(Br + Bi); Re(A^H B) = P1 + P2, Im(A^H B) = P3 - P1 + P2
+  d4 p1[MAXT], p2[MAXT], p3[MAXT];
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) {
-    re[t] = d4{0, 0, 0, 0};
-    im[t] = d4{0, 0, 0, 0};
+    p1[t] = d4{0, 0, 0, 0};
+    p2[t] = d4{0, 0, 0, 0};
+    p3[t] = d4{0, 0, 0, 0};
   }
   const c64* Sb = S + (size_t)b * kstride * n;
   const c64* ASb = AS + (size_t)b * kstride * n;
   const size_t r_begin = (size_t)chunk * rows_per_chunk;
   const size_t r_end = std::min(n, r_begin + rows_per_chunk);
   const int ncol2 = 2 * nc;
-  constexpr int PER = (G2_ROWS * 2 * 64 + 255) / 256;  // staged entries per thread
+  constexpr int PER = (G2_ROWS * 2 * 64 + G2_THREADS - 1) / G2_THREADS;  // staged entries per thread
   c64 nxt[PER];
   auto fetch = [&](size_t r0) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * 256;
+      const int e = threadIdx.x + q * G2_THREADS;
       c64 v = mk(0.0, 0.0);
       if (e < G2_ROWS * ncol2) {
         const int c = e / G2_ROWS, r = e % G2_ROWS;
@@ -88,10 +101,16 @@ __global__ __launch_bounds__(256) void k_gram2(const c64* __restrict__ S, const 
   auto stash = [&]() {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * 256;
-      if (e < G2_ROWS * ncol2) st[(e % G2_ROWS) * G2_PITCH + e / G2_ROWS] = nxt[q];
+      const int e = threadIdx.x + q * G2_THREADS;
+      if (e < G2_ROWS * ncol2) {
+        const int c = e / G2_ROWS;
+        st[(e % G2_ROWS) * G2_PITCH + (c < nc ? c : G2_COLS + c - nc)] = nxt[q];
+      }
     }
   };
+  // padding columns (nc..63 of S and of AS) and the zero block stay zero for the whole chunk
+  for (int e = threadIdx.x; e < G2_ROWS * G2_PITCH; e += blockDim.x) st[e] = mk(0.0, 0.0);
+  __syncthreads();
   if (r_begin < r_end) {
     fetch(r_begin);
     stash();
@@ -103,32 +122,37 @@ __global__ __launch_bounds__(256) void k_gram2(const c64* __restrict__ S, const 
 #pragma unroll
     for (int kb = 0; kb < G2_ROWS; kb += 4) {
       const c64* srow = st + (kb + lk) * G2_PITCH;
+      asm volatile("" ::: "memory");  // one 4-row step's operands live at a time (occupancy)
+      c64 av[MAXT], bv[MAXT];
 #pragma unroll
       for (int t = 0; t < MAXT; ++t) {
-        if (t < nt) {
-          const int ca = tti[t] * 16 + li;
-          const int cb = ttj[t] * 16 + li;
-          const c64 av = (ca < nc) ? srow[ca] : mk(0.0, 0.0);
-          const c64 bv = (cb < nc) ? srow[(tmat[t] == 0 ? nc : 0) + cb] : mk(0.0, 0.0);
-          re[t] = mfma(av.re, bv.re, re[t]);
-          im[t] = mfma(av.re, bv.im, im[t]);
-          re[t] = mfma(av.im, bv.im, re[t]);
-          im[t] = mfma(av.im, -bv.re, im[t]);
-        }
+        // tiles past nt and columns past nc read zeros (the stage is zero-padded)
+        const int ca = tti[t] * 16 + li;
+        const int cb = ttj[t] * 16 + li;
+        av[t] = srow[ca];
+        bv[t] = srow[(tmat[t] == 0 ? G2_COLS : 0) + cb];
       }
+      // consecutive MFMAs go to different accumulators
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) p1[t] = mfma(av[t].re, bv[t].re, p1[t]);
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) p2[t] = mfma(av[t].im, bv[t].im, p2[t]);
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) p3[t] = mfma(av[t].re - av[t].im, bv[t].re + bv[t].im, p3[t]);
     }
     __syncthreads();
     if (more) stash();
     __syncthreads();
   }
-  // partial tiles: [b][chunk][tile][256], tile id = wave + 4 t
+  // partial tiles: [b][chunk][tile][256], tile id = wave + 8 t
   const int nchunk = gridDim.x;
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) {
     if (t < nt) {
-      c64* out = part + (((size_t)b * nchunk + chunk) * ntile + (wave + 4 * t)) * 256;
+      c64* out = part + (((size_t)b * nchunk + chunk) * ntile + (wave + 8 * t)) * 256;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) out[(lk + 4 * r) * 16 + li] = mk(re[t][r], im[t][r]);
+      for (int r = 0; r < 4; ++r)
+        out[(lk + 4 * r) * 16 + li] = mk(p1[t][r] + p2[t][r], p3[t][r] - p1[t][r] + p2[t][r]);
     }
   }
 }
@@ -174,9 +198,9 @@ __global__ void k_gram2_reduce(const c64* __restrict__ part, int nchunk, int nti
 // Update: Y_b[:, map(j)] = sum_c S_b[:, c] C_b[c][j], j < q, in place (Y may be S).
 // Computed transposed, D = C^T S^T: the B operand lanes read 16 consecutive rows of one
 // column (coalesced), the output lanes hold 16 consecutive rows of one output column.
-// Re(Y) = Cr Sr - Ci Si, Im(Y) = Cr Si + Ci Sr.  Output column j goes to column
-// (j < q1 ? ycol0 + j : ycol1 + j - q1).  Each wave owns 16 rows at a time, so all reads of
-// its rows happen before its writes and other waves never touch them.
+// Re(Y) = Cr Sr - Ci Si, Im(Y) = Cr Si + Ci Sr (three MFMAs per complex product).  Output
+// column j goes to column (j < q1 ? ycol0 + j : ycol1 + j - q1).  Each wave owns 16 rows at
+// a time, so all reads of its rows happen before its writes and other waves never touch them.
 // ------------------------------------------------------------------------------------
 template <int TQ>
 __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64* __restrict__ C, size_t n,
@@ -216,11 +240,14 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
     }
     // keep every load issued ahead of the MFMAs (each MFMA group then waits only for its own)
     asm volatile("" ::: "memory");
-    d4 re[TQ], im[TQ];
+    // three real products per complex one (Gauss): P1 = Cr Sr, P2 = Ci Si,
+    // P3 = (Cr + Ci)(Sr + Si); Re(Y) = P1 - P2, Im(Y) = P3 - P1 - P2
+    d4 p1[TQ], p2[TQ], p3[TQ];
 #pragma unroll
     for (int t = 0; t < TQ; ++t) {
-      re[t] = d4{0, 0, 0, 0};
-      im[t] = d4{0, 0, 0, 0};
+      p1[t] = d4{0, 0, 0, 0};
+      p2[t] = d4{0, 0, 0, 0};
+      p3[t] = d4{0, 0, 0, 0};
     }
 #pragma unroll
     for (int kb = 0; kb < PK; ++kb) {
@@ -230,18 +257,14 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
       c64 cv[TQ];
 #pragma unroll
       for (int t = 0; t < TQ; ++t) cv[t] = csh[ca * QP + t * 16 + li];
-      const double nsi = -sv[kb].im;
-      // the two products of each accumulator are TQ x 2 MFMAs apart
+      const double ssum = sv[kb].re + sv[kb].im;
+      // consecutive MFMAs go to different accumulators
 #pragma unroll
-      for (int t = 0; t < TQ; ++t) {
-        re[t] = mfma(cv[t].re, sv[kb].re, re[t]);
-        im[t] = mfma(cv[t].re, sv[kb].im, im[t]);
-      }
+      for (int t = 0; t < TQ; ++t) p1[t] = mfma(cv[t].re, sv[kb].re, p1[t]);
 #pragma unroll
-      for (int t = 0; t < TQ; ++t) {
-        re[t] = mfma(cv[t].im, nsi, re[t]);
-        im[t] = mfma(cv[t].im, sv[kb].re, im[t]);
-      }
+      for (int t = 0; t < TQ; ++t) p2[t] = mfma(cv[t].im, sv[kb].im, p2[t]);
+#pragma unroll
+      for (int t = 0; t < TQ; ++t) p3[t] = mfma(cv[t].re + cv[t].im, ssum, p3[t]);
     }
     // output lane holds D[lk + 4r][li]: output column t*16 + lk + 4r, row rb*16 + li
 #pragma unroll
@@ -251,7 +274,7 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
         const int j = t * 16 + lk + 4 * r;
         if (rok && j < q) {
           const int col = (j < q1) ? ycol0 + j : ycol1 + (j - q1);
-          Yb[(size_t)col * n + row] = mk(re[t][r], im[t][r]);
+          Yb[(size_t)col * n + row] = mk(p1[t][r] - p2[t][r], p3[t][r] - p1[t][r] - p2[t][r]);
         }
       }
   }
@@ -382,7 +405,7 @@ int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, De
   const int nchunk = (int)((n + rows - 1) / rows);
   KC_TRY(part.ensure((size_t)nb * nchunk * ntile * 256 * sizeof(c64)));
   dim3 grid(nchunk, nb);
-  k_gram2<<<grid, 256, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part.as<c64>(), kskip);
+  k_gram2<<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part.as<c64>(), kskip);
   KC_LAUNCHED();
   dim3 g2(1, ntile, nb);
   k_gram2_reduce<<<g2, 256, 0, s>>>(part.as<c64>(), nchunk, ntile, nc, GA, GB, kskip);
