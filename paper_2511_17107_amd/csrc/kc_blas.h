@@ -16,11 +16,12 @@ int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, i
            int ycol1, const c64* C, size_t n, int nb, const int* kskip, hipStream_t s);
 
 // W_j = K_P^{-1} (AX_j - theta_j X_j), res_j = |AX_j - theta_j X_j| / |X_j|; optionally the
-// residuals themselves (Rout, contiguous [nb*mb][3N^3]) and |r_j|^2 (rnorm2).
+// residuals themselves (Rout, contiguous [nb*mb][3N^3]) and |r_j|^2 (rnorm2); W is left
+// untouched for the k-points b with wskip[b] != 0.
 int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
                   const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
                   double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout = nullptr,
-                  double* rnorm2 = nullptr);
+                  double* rnorm2 = nullptr, const int* wskip = nullptr);
 
 int random_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, uint64_t seed, const int* kglobal,
                  hipStream_t s);

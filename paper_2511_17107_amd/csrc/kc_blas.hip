@@ -283,7 +283,8 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
 // ------------------------------------------------------------------------------------
 // Residual + preconditioner: r_j = AX_j - theta_j X_j, W_j = K_P^{-1} r_j (closed form of
 // the diagonal-block preconditioner, eqs (2.31)-(2.32)), per-block partial sums of |r_j|^2
-// and |x_j|^2; optionally a contiguous copy of r (Rout, [b*mb + j][3N^3]).
+// and |x_j|^2; optionally a contiguous copy of r (Rout, [b*mb + j][3N^3]); W is not written
+// for the k-points whose wskip is set (their new directions come from another preconditioner).
 // Grid: x = blocks per vector, y = column j, z = k-point b.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S, const c64* __restrict__ AS,
@@ -291,9 +292,11 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
                                                        const c64* __restrict__ ktab64,
                                                        const double* __restrict__ gamma, int N, int kstride,
                                                        int xcol0, int wcol0, int mb, double* __restrict__ part,
-                                                       const int* __restrict__ kskip, c64* __restrict__ Rout) {
+                                                       const int* __restrict__ kskip, c64* __restrict__ Rout,
+                                                       const int* __restrict__ wskip) {
   const int b = blockIdx.z, j = blockIdx.y;
   if (kskip && kskip[b]) return;
+  const bool ww = !(wskip && wskip[b]);
   const size_t N3 = (size_t)N * N * N, n = 3 * N3;
   const c64* x = S + ((size_t)b * kstride + xcol0 + j) * n;
   const c64* ax = AS + ((size_t)b * kstride + xcol0 + j) * n;
@@ -319,9 +322,11 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
       w2 = is * r2 + cmulc(K2, u);
       w3 = is * r3 + cmulc(K3, u);
     }
-    w[p] = w1;
-    w[N3 + p] = w2;
-    w[2 * N3 + p] = w3;
+    if (ww) {
+      w[p] = w1;
+      w[N3 + p] = w2;
+      w[2 * N3 + p] = w3;
+    }
     if (rc) {
       rc[p] = r1;
       rc[N3 + p] = r2;
@@ -439,13 +444,14 @@ int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, i
 
 int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
                   const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
-                  double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout, double* rnorm2) {
+                  double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout, double* rnorm2,
+                  const int* wskip) {
   const size_t N3 = (size_t)N * N * N;
   const int nblk = (int)std::max<size_t>(1, std::min<size_t>((N3 + 255) / 256, 256));
   KC_TRY(part.ensure((size_t)nb * mb * nblk * 2 * sizeof(double)));
   dim3 grid(nblk, mb, nb);
   k_resid_precond<<<grid, 256, 0, s>>>(S, AS, W, theta, ktab64, gamma, N, kstride, xcol0, wcol0, mb,
-                                       part.as<double>(), kskip, Rout);
+                                       part.as<double>(), kskip, Rout, wskip);
   KC_LAUNCHED();
   const int nv = nb * mb;
   k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2, rnorm2);

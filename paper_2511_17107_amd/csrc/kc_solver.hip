@@ -33,7 +33,7 @@ struct SolverWork {
   DevBuf GA, GB, Cu, Lsave;
   DevBuf theta, res, xn2;
   DevBuf R, tmask;  // residuals (input of T_E) and the columns that get T_E R
-  DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal [nb each]
+  DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal, wskip [nb each]
   hipStream_t gstream = nullptr;  // private stream of graph-captured solves (default priority)
   ~SolverWork() {
     if (gstream) (void)hipStreamDestroy(gstream);
@@ -53,7 +53,7 @@ struct Batch {
   int ik0, nb, m, mb, nc, N;
   size_t n;
   hipStream_t s;
-  int *xmask, *wmask, *pmask, *pvalid, *kskip, *flags, *kglobal;
+  int *xmask, *wmask, *pmask, *pvalid, *kskip, *flags, *kglobal, *wskip;
   c64 *S, *AS;
   int pc = KC_PRECOND_DIAG;
   const float* field = nullptr;  // E of T_E: one per k-point (fks = 1) or shared (fks = 0)
@@ -88,12 +88,14 @@ int rayleigh_ritz(Batch& B) {
   return KC_OK;
 }
 
-// Res and W = K_P^{-1} R; with copy_r also a contiguous copy of R for T_E
+// Res and W = K_P^{-1} R; with copy_r also a contiguous copy of R for T_E, and W = K_P^{-1} R
+// only for the k-points that do not use T_E (wskip)
 int residuals(Batch& B, bool copy_r) {
   c64* R = copy_r ? B.w->R.as<c64>() : nullptr;
   KC_TRY(resid_precond(B.S, B.AS, B.S, B.w->theta.as<double>(), B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N,
                        B.op->gamma_d.as<double>() + B.ik0, B.N, B.nc, 0, B.mb, B.mb, B.nb, B.w->part_res,
-                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, R));
+                       B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, R, nullptr,
+                       copy_r ? B.wskip : nullptr));
   return KC_OK;
 }
 
@@ -156,7 +158,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
     KC_TRY(w->R.ensure((size_t)nb * mb * colbytes));
     KC_TRY(w->tmask.ensure((size_t)nb * mb * sizeof(int)));
   }
-  KC_TRY(w->ints.ensure((size_t)(4 * nb * mb + 3 * nb) * sizeof(int)));
+  KC_TRY(w->ints.ensure((size_t)(4 * nb * mb + 4 * nb) * sizeof(int)));
   // operator work buffers at their largest (FP64) size up front: captured iterations keep
   // their pointers, so no buffer may move after a capture
   KC_TRY(op->work_a.ensure((size_t)nb * mb * n * sizeof(c64)));
@@ -171,6 +173,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   B.kskip = ib + 4 * nb * mb;
   B.flags = B.kskip + nb;
   B.kglobal = B.flags + nb;
+  B.wskip = B.kglobal + nb;
 
   std::vector<int> hx(nb * mb, 0), hw(nb * mb, 1), hp(nb * mb, 0), hpv(nb * mb, 0), hskip(nb, 0), hflags(nb, 0),
       hkg(nb);
@@ -196,6 +199,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   std::vector<double> lbest(nb, 1e300);
   std::vector<int> lstall(nb, 0);
   double napp = 0;
+  KC_TRY(upload_ints(B.wskip, lon, s));
   KC_TRY(upload_ints(B.xmask, hx, s));
   KC_TRY(upload_ints(B.wmask, hw, s));
   KC_TRY(upload_ints(B.pmask, hp, s));
@@ -315,6 +319,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
         ++ncand;
       }
     }
+    bool lchanged = false;
     if (B.pc == KC_PRECOND_LEARNED) {
       for (int b = 0; b < nb; ++b) {
         if (done[b] || !lon[b]) continue;
@@ -326,8 +331,13 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
           lstall[b] = 0;
         } else if (++lstall[b] >= 8 || gm > 100.0 * lbest[b]) {
           lon[b] = 0;  // fall back to the diagonal-block preconditioner
+          lchanged = true;
           if (o.verbose) fprintf(stderr, "[kc_solve] k %d: learned preconditioner off\n", ik0 + b);
         }
+      }
+      if (lchanged) {  // this iteration's W of those k-points must be K_P^{-1} R
+        KC_TRY(upload_ints(B.wskip, lon, s));
+        KC_TRY(residuals(B, tp));
       }
     }
     if (verify_pending) {
