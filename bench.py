@@ -5,8 +5,8 @@ eps = [[12, 0.5i, 0], [-0.5i, 12, 0], [0, 0, 10]] at N = 128 (3 x 128^3 = 6.3M u
 CrossDoF inverse permittivity, 16 bands, 60 k-points on Gamma-X-M-Gamma-R, FP32 operator
 applications with FP64 orthogonalisation / Rayleigh-Ritz / residual checks.
 
-One step = one kc_solve of a batch of k-points (default 4, interleaved along the 60-point
-path so that consecutive steps walk the whole path).  Inputs (geometry, tables, k-points)
+One step = one kc_solve of a batch of k-points (default 10, interleaved along the 60-point
+path so that consecutive steps walk the whole path; ~180 GB of HBM for the batch's blocks).  Inputs (geometry, tables, k-points)
 are resident before the timed region; the solve allocates its block workspace once and
 reuses it.  Prints one JSON line (see the keys below).
 
@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--kpb", type=int, default=4, help="k-points per step (one batched solve)")
+    ap.add_argument("--kpb", type=int, default=10, help="k-points per step (one batched solve)")
     ap.add_argument("--nk", type=int, default=60)
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--m", type=int, default=16)

@@ -157,3 +157,32 @@ def test_graph_replay_matches_eager(prec, pc):
         assert res[graph][3] == 0 and res[graph][1].max() <= TOL
     assert np.array_equal(res[True][2], res[False][2])
     assert np.max(np.abs(res[True][0] - res[False][0]) / res[False][0]) <= 1e-12
+
+
+def test_solve_n128_woodpile_properties():
+    """The benchmark's workload (128^3 woodpile, gyrotropic eps, CrossDoF, 16 bands + 4 guard,
+    FP32 operator then FP64, transverse preconditioner, batched, graph-replayed) on two k-points
+    of the path, checked through properties that hold at any size with the FP64 operator (itself
+    checked at N = 128 against the oracle): Res_j <= 1e-8 from a fresh application, eigenvalues
+    ascending and equal to the Rayleigh quotients, eigenvectors orthonormal."""
+    import torch
+
+    wl = W.woodpile_gyrotropic(N=128, nk=60, m=16)
+    op = kc.Op(128, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(wl.kpoints[[7, 41]])
+    X = torch.zeros((2 * 16, 3, 128 ** 3), dtype=torch.complex128, device="cuda")
+    note("solve n128 woodpile")
+    eig, res, its, st = op.solve(16, tol=TOL, guard=4, batch_k=2, prec=kc.KC_PREC_FP32, switch_tol=3e-4,
+                                 precond=kc.KC_PRECOND_TRANSVERSE, X_out=X)
+    assert st == 0 and res.max() <= TOL
+    AX = op.apply(X, vecs_per_k=16)
+    for b in range(2):
+        Xb = X[16 * b:16 * (b + 1)].reshape(16, -1)
+        Ab = AX[16 * b:16 * (b + 1)].reshape(16, -1)
+        G = (Xb.conj() @ Xb.T).cpu().numpy()
+        assert np.abs(G - np.eye(16)).max() < 1e-10
+        rq = (Xb.conj() * Ab).sum(dim=1).real.cpu().numpy()
+        assert np.max(np.abs(rq - eig[b]) / eig[b]) < 1e-12
+        r = torch.linalg.vector_norm(Ab - torch.from_numpy(eig[b]).to(Ab.device)[:, None] * Xb, dim=1)
+        assert float(r.max()) <= 1.5 * TOL
+        assert np.all(np.diff(eig[b]) >= -1e-12 * eig[b][-1])
