@@ -213,6 +213,8 @@ def main():
                      "frac": gbs[dom] / HBM_PEAK_GBS,
                      "traffic": MEASURED_TRAFFIC.get((names[dom], a.N, a.m, a.prec)),
                      "alg_bytes": pbytes[dom]},
+        "tile_widths": {"fp32": op.tile_widths(kc.KC_PREC_FP32).tolist(),
+                        "fp64": op.tile_widths(kc.KC_PREC_FP64).tolist()},
         "matvec": {"passes": names, "ms": [round(float(t), 4) for t in ms],
                    "alg_GBps": [round(g, 1) for g in gbs], "nvec": a.m,
                    "ms_per_band": mv_time / a.m,

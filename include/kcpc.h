@@ -207,6 +207,15 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
  * preconditioner to the end, preconditioner applications (vector count), 0, 0}. */
 int kc_last_solve_stats(const kc_op* op, double* stats_host);
 
+/*
+ * Tile widths (pencils per workgroup) chosen for the handle's passes in precision prec, int32
+ * [10] in the order X1, Y (inverse), Za, Zb, Z (Trivial/diagonal), Y (forward), X2, then the
+ * transverse preconditioner's X1, Z and X2; 0 while not yet chosen.  On a handle's first
+ * application in a precision (N >= 32) every valid width of every pass is timed on a block of
+ * up to 32 vectors and the fastest kept; smaller grids use a fixed rule.
+ */
+int kc_tile_widths(const kc_op* op, int prec, int* widths_host);
+
 /* Release the handle and every device buffer it owns.  NULL is allowed. */
 void kc_destroy(kc_op* op);
 

@@ -67,6 +67,7 @@ def lib():
         L.kc_solve_opts_default.restype = None
         L.kc_solve.argtypes = [vp, i32, i32, ctypes.POINTER(KcSolveOpts), vp, vp, vp, vp, vp]
         L.kc_last_solve_stats.argtypes = [vp, vp]
+        L.kc_tile_widths.argtypes = [vp, i32, vp]
         L.kc_destroy.argtypes = [vp]
         L.kc_destroy.restype = None
         L.kc_net_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
@@ -265,6 +266,11 @@ class Op:
         if check and st not in (KC_OK, KC_ERR_NO_CONVERGENCE):
             _check(st, "kc_solve")
         return eig, res, its, st
+
+    def tile_widths(self, prec: int = KC_PREC_FP32) -> np.ndarray:
+        w = np.zeros(10, dtype=np.int32)
+        _check(lib().kc_tile_widths(self._h, int(prec), w.ctypes.data_as(ctypes.c_void_p)), "kc_tile_widths")
+        return w
 
     def last_solve_stats(self) -> np.ndarray:
         s = np.zeros(8)

@@ -371,6 +371,14 @@ int kc_fft3d(int N, int nvec, int sign, int prec, const void* in, void* out, voi
   return fft3d(N, nvec, sign, prec, in, out, tw, (hipStream_t)stream);
 }
 
+int kc_tile_widths(const kc_op* op, int prec, int* widths_host) {
+  KC_ARG(op != nullptr && widths_host != nullptr, "NULL argument");
+  KC_ARG(prec == KC_PREC_FP64 || prec == KC_PREC_FP32, "prec");
+  const int pi = prec == KC_PREC_FP64 ? 1 : 0;
+  for (int i = 0; i < TP_NPASS; ++i) widths_host[i] = op->tuned[pi] ? op->tiles[pi][i] : 0;
+  return KC_OK;
+}
+
 int kc_last_solve_stats(const kc_op* op, double* stats_host) {
   KC_ARG(op != nullptr && stats_host != nullptr, "NULL argument");
   for (int i = 0; i < 8; ++i) stats_host[i] = op->stats[i];

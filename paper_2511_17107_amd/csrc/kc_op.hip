@@ -29,6 +29,8 @@
 // singular, and equals K_P^{-1} for E = 1.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
+#include <vector>
 
 #include "kc_fft.h"
 #include "kc_state.h"
@@ -55,11 +57,10 @@ __device__ __forceinline__ void load_eps_table(EpsEntry<T>* lt, const EpsEntry<T
 // ------------------------------------------------------------------------------------
 // X1: curl prologue + inverse DFT along x.  Tile: P rows (y) of one (vec, z), 3 comps.
 // ------------------------------------------------------------------------------------
-template <int N, typename T, bool PRE>
+template <int N, typename T, bool PRE, int P>
 __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, cpx<T>* __restrict__ E,
                                                     const cpx<T>* __restrict__ ktab, VecMap vm,
                                                     const cpx<T>* __restrict__ gtw) {
-  constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -103,14 +104,13 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
 // ------------------------------------------------------------------------------------
 // X2: forward DFT along x + outer curl + penalty epilogue.
 // ------------------------------------------------------------------------------------
-template <int N, typename T, bool PRE>
+template <int N, typename T, bool PRE, int P>
 __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict__ E,
                                                         const c64* __restrict__ x, c64* __restrict__ y,
                                                         const cpx<T>* __restrict__ ktab,
                                                         const c64* __restrict__ ktab64,
                                                         const double* __restrict__ gamma,
                                                         VecMap vm, VecMap vmy, const cpx<T>* __restrict__ gtw) {
-  constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -167,10 +167,9 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
 // ------------------------------------------------------------------------------------
 // Y: DFT along y, in place.  Tile: P consecutive x of one (vec*3+c, z).
 // ------------------------------------------------------------------------------------
-template <int N, int DIR, typename T>
+template <int N, int DIR, typename T, int P>
 __global__ __launch_bounds__(NT) void k_y(cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ gtw,
                                           const int* __restrict__ active) {
-  constexpr int P = TileP<N, 1, T>::P;
   using G = TileGeom<N, P, 1>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -198,9 +197,8 @@ __global__ __launch_bounds__(NT) void k_y(cpx<T>* __restrict__ buf, const cpx<T>
 // ------------------------------------------------------------------------------------
 // X (plain): DFT along x, in -> out (out may alias in).  Tile: P rows of one (vc, z).
 // ------------------------------------------------------------------------------------
-template <int N, int DIR, typename T>
+template <int N, int DIR, typename T, int P>
 __global__ __launch_bounds__(NT) void k_x_plain(const cpx<T>* in, cpx<T>* out, const cpx<T>* __restrict__ gtw) {
-  constexpr int P = TileP<N, 1, T>::P;
   using G = TileGeom<N, P, 1>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -227,10 +225,9 @@ __global__ __launch_bounds__(NT) void k_x_plain(const cpx<T>* in, cpx<T>* out, c
 // ------------------------------------------------------------------------------------
 // Z (plain): DFT along z, in -> out (may alias).  Tile: P consecutive x of one (vc, y).
 // ------------------------------------------------------------------------------------
-template <int N, int DIR, typename T>
+template <int N, int DIR, typename T, int P>
 __global__ __launch_bounds__(NT) void k_z_plain(const cpx<T>* in, cpx<T>* out, const cpx<T>* __restrict__ gtw,
                                                 const int* __restrict__ active, int ncomp) {
-  constexpr int P = TileP<N, 1, T>::P;
   using G = TileGeom<N, P, 1>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -260,11 +257,10 @@ __global__ __launch_bounds__(NT) void k_z_plain(const cpx<T>* in, cpx<T>* out, c
 // (diagonal from the edge points, off-diagonals from the volume point; eqs (3.3)-(3.4)),
 // forward DFT along z.  In place.  Tile: P consecutive x of one (vec, y), 3 comps.
 // ------------------------------------------------------------------------------------
-template <int N, typename T>
+template <int N, typename T, int P>
 __global__ __launch_bounds__(NT) void k_z_trivial(cpx<T>* __restrict__ buf, const uint32_t* __restrict__ ids,
                                                   const EpsEntry<T>* __restrict__ geps, int n_mat,
                                                   const cpx<T>* __restrict__ gtw, const int* __restrict__ active) {
-  constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -311,11 +307,10 @@ __global__ __launch_bounds__(NT) void k_z_trivial(cpx<T>* __restrict__ buf, cons
 // positive per-point field f (FP32 [3][N^3], one per k-point group or shared), forward DFT
 // along z.  In place.  Tile: P consecutive x of one (vec, y), 3 comps.
 // ------------------------------------------------------------------------------------
-template <int N, typename T>
+template <int N, typename T, int P>
 __global__ __launch_bounds__(NT) void k_z_field(cpx<T>* __restrict__ buf, const float* __restrict__ field,
                                                 int vpk, int fkstride, const cpx<T>* __restrict__ gtw,
                                                 const int* __restrict__ active) {
-  constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -358,92 +353,63 @@ __global__ __launch_bounds__(NT) void k_z_field(cpx<T>* __restrict__ buf, const 
 // and the lower blocks are the conjugate transposes.  Stencils (0-based, periodic):
 //   T12: (i,j),(i-1,j),(i,j+1),(i-1,j+1)   T13: (i,k),(i-1,k),(i,k+1),(i-1,k+1)
 //   T23: (j,k),(j-1,k),(j,k+1),(j-1,k+1)   and their transposes mirrored.
-// Tile: P consecutive x of one (vec, y), 3 comps; E is read around the tile through the cache.
+// Tile: P consecutive x of one (vec, y), 3 comps.  A thread walks a segment of z for one x: the
+// stencils need E1 at the columns (i,j), (i+1,j), (i,j-1), (i+1,j-1), E2 at (i,j), (i-1,j),
+// (i,j+1), (i-1,j+1), E3 at (i,j), (i-1,j), (i,j-1), and the ids at those seven columns, on the
+// planes k-1, k, k+1; the three planes live in registers and slide along z, so each plane is
+// read once per thread.  E and ids are read through the cache (neighbouring tiles share them).
 // ------------------------------------------------------------------------------------
 template <typename T>
-struct CrossCtx {
-  const cpx<T>* E1;
-  const cpx<T>* E2;
-  const cpx<T>* E3;
-  const uint32_t* ids;
-  const EpsEntry<T>* eps;
-  int N;
-  __device__ __forceinline__ size_t at(int i, int j, int k) const {
-    return ((size_t)k * N + j) * N + i;
-  }
+struct ZPlane {
+  cpx<T> e1[4];    // E1 at (i,j), (i+1,j), (i,j-1), (i+1,j-1)
+  cpx<T> e2[4];    // E2 at (i,j), (i-1,j), (i,j+1), (i-1,j+1)
+  cpx<T> e3[3];    // E3 at (i,j), (i-1,j), (i,j-1)
+  uint32_t id[7];  // ids at (i,j), (i+1,j), (i,j-1), (i+1,j-1), (i-1,j), (i,j+1), (i-1,j+1)
 };
 
 template <typename T>
-__device__ __forceinline__ void crossdof_point(const CrossCtx<T>& C, int i, int j, int k, cpx<T>& o1,
-                                               cpx<T>& o2, cpx<T>& o3) {
-  const int N = C.N;
-  const int ip = (i + 1 == N) ? 0 : i + 1, im = (i == 0) ? N - 1 : i - 1;
-  const int jp = (j + 1 == N) ? 0 : j + 1, jm = (j == 0) ? N - 1 : j - 1;
-  const int kp = (k + 1 == N) ? 0 : k + 1, km = (k == 0) ? N - 1 : k - 1;
-  const size_t c0 = C.at(i, j, k);
-  const uint32_t idc = C.ids[c0];
-  const EpsEntry<T>& ex = C.eps[idc & 255u];
-  const EpsEntry<T>& ey = C.eps[(idc >> 8) & 255u];
-  const EpsEntry<T>& ez = C.eps[(idc >> 16) & 255u];
-  const T e8 = static_cast<T>(0.125);
-  auto mx = [&](size_t a) -> const EpsEntry<T>& { return C.eps[C.ids[a] & 255u]; };
-  auto my = [&](size_t a) -> const EpsEntry<T>& { return C.eps[(C.ids[a] >> 8) & 255u]; };
-  auto mz = [&](size_t a) -> const EpsEntry<T>& { return C.eps[(C.ids[a] >> 16) & 255u]; };
-
-  // row 1: d1 E1 + block(1,2) E2 + block(1,3) E3
-  cpx<T> a1 = mk<T>(0, 0);
-  {
-    const size_t s[4] = {c0, C.at(im, j, k), C.at(i, jp, k), C.at(im, jp, k)};
+__device__ __forceinline__ void load_plane(ZPlane<T>& z, const cpx<T>* E1, const cpx<T>* E2, const cpx<T>* E3,
+                                           const uint32_t* ids, const size_t (&col)[7], size_t plane) {
+  // col: (i,j), (i+1,j), (i,j-1), (i+1,j-1), (i-1,j), (i,j+1), (i-1,j+1)
+  z.e1[0] = E1[plane + col[0]];
+  z.e1[1] = E1[plane + col[1]];
+  z.e1[2] = E1[plane + col[2]];
+  z.e1[3] = E1[plane + col[3]];
+  z.e2[0] = E2[plane + col[0]];
+  z.e2[1] = E2[plane + col[4]];
+  z.e2[2] = E2[plane + col[5]];
+  z.e2[3] = E2[plane + col[6]];
+  z.e3[0] = E3[plane + col[0]];
+  z.e3[1] = E3[plane + col[4]];
+  z.e3[2] = E3[plane + col[2]];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) a1 = a1 + (ex.o[0] + my(s[t]).o[0]) * C.E2[s[t]];
-  }
-  {
-    const size_t s[4] = {c0, C.at(im, j, k), C.at(i, j, kp), C.at(im, j, kp)};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) a1 = a1 + (ex.o[1] + mz(s[t]).o[1]) * C.E3[s[t]];
-  }
-  o1 = ex.d[0] * C.E1[c0] + e8 * a1;
-
-  // row 2: block(2,1) E1 + d2 E2 + block(2,3) E3
-  cpx<T> a2 = mk<T>(0, 0);
-  {
-    const size_t s[4] = {c0, C.at(ip, j, k), C.at(i, jm, k), C.at(ip, jm, k)};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) a2 = a2 + cmulc(mx(s[t]).o[0] + ey.o[0], C.E1[s[t]]);
-  }
-  {
-    const size_t s[4] = {c0, C.at(i, jm, k), C.at(i, j, kp), C.at(i, jm, kp)};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) a2 = a2 + (ey.o[2] + mz(s[t]).o[2]) * C.E3[s[t]];
-  }
-  o2 = ey.d[1] * C.E2[c0] + e8 * a2;
-
-  // row 3: block(3,1) E1 + block(3,2) E2 + d3 E3
-  cpx<T> a3 = mk<T>(0, 0);
-  {
-    const size_t s[4] = {c0, C.at(ip, j, k), C.at(i, j, km), C.at(ip, j, km)};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) a3 = a3 + cmulc(mx(s[t]).o[1] + ez.o[1], C.E1[s[t]]);
-  }
-  {
-    const size_t s[4] = {c0, C.at(i, jp, k), C.at(i, j, km), C.at(i, jp, km)};
-#pragma unroll
-    for (int t = 0; t < 4; ++t) a3 = a3 + cmulc(my(s[t]).o[2] + ez.o[2], C.E2[s[t]]);
-  }
-  o3 = ez.d[2] * C.E3[c0] + e8 * a3;
+  for (int c = 0; c < 7; ++c) z.id[c] = ids[plane + col[c]];
 }
 
-template <int N, typename T>
+template <int N, int P>
+struct ZbSeg {  // z-segments per x: the largest divisor of N with P * NSEG <= 256 threads
+  static constexpr int pick() {
+    int best = 1;
+    for (int d = 1; d <= N; ++d)
+      if (N % d == 0 && P * d <= 256) best = d;
+    return best;
+  }
+  static constexpr int NSEG = pick();
+  static constexpr int ZL = N / NSEG;
+};
+
+template <int N, typename T, int P>
 __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E, cpx<T>* __restrict__ out,
                                                     const uint32_t* __restrict__ ids,
                                                     const EpsEntry<T>* __restrict__ geps, int n_mat,
                                                     const cpx<T>* __restrict__ gtw, const int* __restrict__ active) {
-  constexpr int P = TileP<N, 3, T>::P;
   using G = TileGeom<N, P, 3>;
+  constexpr int NSEG = ZbSeg<N, P>::NSEG, ZL = ZbSeg<N, P>::ZL;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
   __shared__ EpsEntry<T> eps[KC_MAX_MAT];
   constexpr size_t N3 = (size_t)N * N * N;
+  constexpr size_t NN = (size_t)N * N;
   const unsigned nb = gridDim.x;
   unsigned b = xcd_swizzle(blockIdx.x, nb);
   const int xt = b % (N / P);
@@ -454,20 +420,63 @@ __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E
   load_twiddles<N>(tw, gtw);
   load_eps_table(eps, geps, n_mat);
   __syncthreads();
-  CrossCtx<T> C;
-  C.E1 = E + vec * 3 * N3;
-  C.E2 = C.E1 + N3;
-  C.E3 = C.E2 + N3;
-  C.ids = ids;
-  C.eps = eps;
-  C.N = N;
-  for (int w = threadIdx.x; w < N * P; w += NT) {
-    const int p = w % P, e = w / P;
-    cpx<T> o1, o2, o3;
-    crossdof_point(C, xt * P + p, yy, e, o1, o2, o3);
-    lds[G::addr3(0, e, p)] = o1;
-    lds[G::addr3(1, e, p)] = o2;
-    lds[G::addr3(2, e, p)] = o3;
+  const cpx<T>* E1 = E + vec * 3 * N3;
+  const cpx<T>* E2 = E1 + N3;
+  const cpx<T>* E3 = E2 + N3;
+  const T e8 = static_cast<T>(0.125);
+  for (int w = threadIdx.x; w < P * NSEG; w += NT) {
+    const int p = w % P, seg = w / P;
+    const int i = xt * P + p, j = yy;
+    const int ip = (i + 1 == N) ? 0 : i + 1, im = (i == 0) ? N - 1 : i - 1;
+    const int jp = (j + 1 == N) ? 0 : j + 1, jm = (j == 0) ? N - 1 : j - 1;
+    const size_t col[7] = {(size_t)j * N + i,   (size_t)j * N + ip, (size_t)jm * N + i, (size_t)jm * N + ip,
+                           (size_t)j * N + im, (size_t)jp * N + i, (size_t)jp * N + im};
+    const int kb = seg * ZL;
+    ZPlane<T> prev, cur, next;
+    load_plane(prev, E1, E2, E3, ids, col, (size_t)(kb == 0 ? N - 1 : kb - 1) * NN);
+    load_plane(cur, E1, E2, E3, ids, col, (size_t)kb * NN);
+    for (int k = kb; k < kb + ZL; ++k) {
+      load_plane(next, E1, E2, E3, ids, col, (size_t)(k + 1 == N ? 0 : k + 1) * NN);
+      const uint32_t idc = cur.id[0];
+      const EpsEntry<T>& ex = eps[idc & 255u];
+      const EpsEntry<T>& ey = eps[(idc >> 8) & 255u];
+      const EpsEntry<T>& ez = eps[(idc >> 16) & 255u];
+      auto mx = [&](uint32_t id) -> const EpsEntry<T>& { return eps[id & 255u]; };
+      auto my = [&](uint32_t id) -> const EpsEntry<T>& { return eps[(id >> 8) & 255u]; };
+      auto mz = [&](uint32_t id) -> const EpsEntry<T>& { return eps[(id >> 16) & 255u]; };
+      // row 1: d1 E1 + block(1,2) E2 [T12 on plane k] + block(1,3) E3 [T13 on planes k, k+1]
+      cpx<T> a1 = (ex.o[0] + my(cur.id[0]).o[0]) * cur.e2[0];
+      a1 = a1 + (ex.o[0] + my(cur.id[4]).o[0]) * cur.e2[1];
+      a1 = a1 + (ex.o[0] + my(cur.id[5]).o[0]) * cur.e2[2];
+      a1 = a1 + (ex.o[0] + my(cur.id[6]).o[0]) * cur.e2[3];
+      a1 = a1 + (ex.o[1] + mz(cur.id[0]).o[1]) * cur.e3[0];
+      a1 = a1 + (ex.o[1] + mz(cur.id[4]).o[1]) * cur.e3[1];
+      a1 = a1 + (ex.o[1] + mz(next.id[0]).o[1]) * next.e3[0];
+      a1 = a1 + (ex.o[1] + mz(next.id[4]).o[1]) * next.e3[1];
+      // row 2: block(2,1) E1 [T21 on plane k] + d2 E2 + block(2,3) E3 [T23 on planes k, k+1]
+      cpx<T> a2 = cmulc(mx(cur.id[0]).o[0] + ey.o[0], cur.e1[0]);
+      a2 = a2 + cmulc(mx(cur.id[1]).o[0] + ey.o[0], cur.e1[1]);
+      a2 = a2 + cmulc(mx(cur.id[2]).o[0] + ey.o[0], cur.e1[2]);
+      a2 = a2 + cmulc(mx(cur.id[3]).o[0] + ey.o[0], cur.e1[3]);
+      a2 = a2 + (ey.o[2] + mz(cur.id[0]).o[2]) * cur.e3[0];
+      a2 = a2 + (ey.o[2] + mz(cur.id[2]).o[2]) * cur.e3[2];
+      a2 = a2 + (ey.o[2] + mz(next.id[0]).o[2]) * next.e3[0];
+      a2 = a2 + (ey.o[2] + mz(next.id[2]).o[2]) * next.e3[2];
+      // row 3: block(3,1) E1 [T31 on planes k, k-1] + block(3,2) E2 [T32 on planes k, k-1] + d3 E3
+      cpx<T> a3 = cmulc(mx(cur.id[0]).o[1] + ez.o[1], cur.e1[0]);
+      a3 = a3 + cmulc(mx(cur.id[1]).o[1] + ez.o[1], cur.e1[1]);
+      a3 = a3 + cmulc(mx(prev.id[0]).o[1] + ez.o[1], prev.e1[0]);
+      a3 = a3 + cmulc(mx(prev.id[1]).o[1] + ez.o[1], prev.e1[1]);
+      a3 = a3 + cmulc(my(cur.id[0]).o[2] + ez.o[2], cur.e2[0]);
+      a3 = a3 + cmulc(my(cur.id[5]).o[2] + ez.o[2], cur.e2[2]);
+      a3 = a3 + cmulc(my(prev.id[0]).o[2] + ez.o[2], prev.e2[0]);
+      a3 = a3 + cmulc(my(prev.id[5]).o[2] + ez.o[2], prev.e2[2]);
+      lds[G::addr3(0, k, p)] = ex.d[0] * cur.e1[0] + e8 * a1;
+      lds[G::addr3(1, k, p)] = ey.d[1] * cur.e2[0] + e8 * a2;
+      lds[G::addr3(2, k, p)] = ez.d[2] * cur.e3[0] + e8 * a3;
+      prev = cur;
+      cur = next;
+    }
   }
   __syncthreads();
   fft_tile<N, P, 3, NT, -1, T>(lds, tw);
@@ -520,9 +529,151 @@ __global__ __launch_bounds__(NT) void k_precond(const c64* r, c64* z, const c64*
 // ------------------------------------------------------------------------------------
 static inline unsigned nblk(size_t n) { return (unsigned)n; }
 
+// ------------------------------------------------------------------------------------
+// Tile widths.  Every pass handles P pencils per workgroup; any P that divides N and whose
+// LDS tile (NC components x N x (P+1) complex, plus twiddles and the permittivity table) fits
+// the 64 KiB of static LDS is valid, and the data layout between passes does not depend on it.
+// The width of each pass is chosen per handle and precision by timing the candidates
+// (tune_tiles); until then, and for grids below 32, TileP's heuristic is used.
+// ------------------------------------------------------------------------------------
+template <int N, int NC, typename T, int P>
+constexpr bool tile_ok() {
+  return P >= 1 && N % P == 0 &&
+         (size_t)TileGeom<N, P, NC>::ELEMS * sizeof(cpx<T>) + N * sizeof(cpx<T>) + KC_MAX_MAT * sizeof(EpsEntry<T>) <=
+             65536;
+}
+
+// calls f(std::integral_constant<int, P>) with the requested width if valid, else the default
+template <int N, int NC, typename T, typename F>
+static void with_tile(int p, F&& f) {
+  constexpr int PD = TileP<N, NC, T>::P;
+  if (p == 4) {
+    if constexpr (tile_ok<N, NC, T, 4>()) return f(std::integral_constant<int, 4>{});
+  } else if (p == 8) {
+    if constexpr (tile_ok<N, NC, T, 8>()) return f(std::integral_constant<int, 8>{});
+  } else if (p == 16) {
+    if constexpr (tile_ok<N, NC, T, 16>()) return f(std::integral_constant<int, 16>{});
+  } else if (p == 32) {
+    if constexpr (tile_ok<N, NC, T, 32>()) return f(std::integral_constant<int, 32>{});
+  }
+  f(std::integral_constant<int, PD>{});
+}
+
+template <int N, int NC, typename T>
+static std::vector<int> tile_candidates() {
+  std::vector<int> c{TileP<N, NC, T>::P};
+  auto add = [&](int p, bool ok) {
+    if (ok && std::find(c.begin(), c.end(), p) == c.end()) c.push_back(p);
+  };
+  if (N >= 32) {
+    add(4, tile_ok<N, NC, T, 4>());
+    add(8, tile_ok<N, NC, T, 8>());
+    add(16, tile_ok<N, NC, T, 16>());
+    add(32, tile_ok<N, NC, T, 32>());
+  }
+  return c;
+}
+
+template <typename T>
+static int tile_of(const kc_op* op, int pass) {
+  return op->tiles[sizeof(T) == 8 ? 1 : 0][pass];
+}
+
+// The launchers below take the tile width of their pass from the handle.
+template <int N, typename T, bool PRE>
+static void launch_x1(kc_op* op, int pass, int nvec, const c64* x, cpx<T>* A, const cpx<T>* ktab, const VecMap& vm,
+                      const cpx<T>* tw, hipStream_t s) {
+  with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    k_x1_curl_inv<N, T, PRE, P><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw);
+  });
+}
+
+template <int N, typename T, bool PRE>
+static void launch_x2(kc_op* op, int pass, int nvec, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* ktab,
+                      const c64* ktab64, const double* gam, const VecMap& vm, const VecMap& vmy, const cpx<T>* tw,
+                      hipStream_t s) {
+  with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    k_x2_fwd_curl_pen<N, T, PRE, P>
+        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw);
+  });
+}
+
+template <int N, int DIR, typename T>
+static void launch_y(kc_op* op, int pass, int nvec, cpx<T>* A, const cpx<T>* tw, const int* act, hipStream_t s) {
+  with_tile<N, 1, T>(tile_of<T>(op, pass), [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    k_y<N, DIR, T, P><<<nblk((size_t)nvec * 3 * N * (N / P)), NT, 0, s>>>(A, tw, act);
+  });
+}
+
+template <int N, int DIR, typename T>
+static void launch_zplain(kc_op* op, int pass, int nvc, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw,
+                          const int* act, int ncomp, hipStream_t s) {
+  with_tile<N, 1, T>(tile_of<T>(op, pass), [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    k_z_plain<N, DIR, T, P><<<nblk((size_t)nvc * N * (N / P)), NT, 0, s>>>(in, out, tw, act, ncomp);
+  });
+}
+
+template <int N, typename T>
+static void launch_zb(kc_op* op, int nvec, const cpx<T>* B, cpx<T>* A, const EpsEntry<T>* eps, const cpx<T>* tw,
+                      const int* act, hipStream_t s) {
+  with_tile<N, 3, T>(tile_of<T>(op, TP_ZB), [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    k_zb_crossdof<N, T, P><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(B, A, op->ids.as<uint32_t>(), eps,
+                                                                           op->n_mat, tw, act);
+  });
+}
+
+template <int N, typename T>
+static void launch_zt(kc_op* op, int nvec, cpx<T>* A, const EpsEntry<T>* eps, const cpx<T>* tw, const int* act,
+                      hipStream_t s) {
+  with_tile<N, 3, T>(tile_of<T>(op, TP_ZT), [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    k_z_trivial<N, T, P><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, op->ids.as<uint32_t>(), eps, op->n_mat,
+                                                                         tw, act);
+  });
+}
+
+template <int N, typename T>
+static void launch_zf(kc_op* op, int nvec, cpx<T>* A, const float* field, int vpk, int fks, const cpx<T>* tw,
+                      const int* act, hipStream_t s) {
+  with_tile<N, 3, T>(tile_of<T>(op, TP_ZF), [&](auto pc) {
+    constexpr int P = decltype(pc)::value;
+    k_z_field<N, T, P><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, field, vpk, fks, tw, act);
+  });
+}
+
+template <typename T>
+struct PassArgs {
+  const cpx<T>* ktab;
+  const c64* ktab64;
+  const double* gam;
+  const cpx<T>* tw;
+  const EpsEntry<T>* eps;
+};
+
+template <int N, typename T>
+static PassArgs<T> pass_args(kc_op* op, int ik0) {
+  const bool f64 = sizeof(T) == 8;
+  PassArgs<T> a;
+  a.ktab = (f64 ? op->ktab64.as<cpx<T>>() : op->ktab32.as<cpx<T>>()) + (size_t)ik0 * 3 * N;
+  a.ktab64 = op->ktab64.as<c64>() + (size_t)ik0 * 3 * N;
+  a.gam = op->gamma_d.as<double>() + ik0;
+  a.tw = f64 ? op->tw64.as<cpx<T>>() : op->tw32.as<cpx<T>>();
+  a.eps = f64 ? op->eps64.as<EpsEntry<T>>() : op->eps32.as<EpsEntry<T>>();
+  return a;
+}
+
+template <int N, typename T>
+static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s);
+
 template <int N, typename T>
 static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x, c64* y, hipStream_t s,
                    hipEvent_t* ev) {
+  KC_TRY((tune_tiles_n<N, T>(op, nvec, s)));
   int nev = 0;
   auto mark = [&]() -> int {
     if (ev) KC_HIP(hipEventRecord(ev[nev++], s));
@@ -532,42 +683,32 @@ static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x,
   const size_t nbuf = (size_t)nvec * 3 * N3 * sizeof(cpx<T>);
   KC_TRY(op->work_a.ensure(nbuf));
   cpx<T>* A = op->work_a.as<cpx<T>>();
-  const bool f64 = sizeof(T) == 8;
-  const cpx<T>* ktab = (f64 ? op->ktab64.as<cpx<T>>() : op->ktab32.as<cpx<T>>()) + (size_t)ik0 * 3 * N;
-  const c64* ktab64 = op->ktab64.as<c64>() + (size_t)ik0 * 3 * N;
-  const double* gam = op->gamma_d.as<double>() + ik0;
-  const cpx<T>* tw = f64 ? op->tw64.as<cpx<T>>() : op->tw32.as<cpx<T>>();
-  const EpsEntry<T>* eps = f64 ? op->eps64.as<EpsEntry<T>>() : op->eps32.as<EpsEntry<T>>();
-  const uint32_t* ids = op->ids.as<uint32_t>();
-  constexpr int P3 = TileP<N, 3, T>::P;
-  constexpr int P1 = TileP<N, 1, T>::P;
-  const unsigned g3 = nblk((size_t)nvec * N * (N / P3));
-  const unsigned g1 = nblk((size_t)nvec * 3 * N * (N / P1));
+  const PassArgs<T> pa = pass_args<N, T>(op, ik0);
   const int* act = vm.active;
   if (op->scheme == KC_EPS_CROSSDOF) KC_TRY(op->work_b.ensure(nbuf));
   KC_TRY(mark());
-  k_x1_curl_inv<N, T, false><<<g3, NT, 0, s>>>(x, A, ktab, vm, tw);
+  launch_x1<N, T, false>(op, TP_X1, nvec, x, A, pa.ktab, vm, pa.tw, s);
   KC_LAUNCHED();
   KC_TRY(mark());
-  k_y<N, +1, T><<<g1, NT, 0, s>>>(A, tw, act);
+  launch_y<N, +1, T>(op, TP_Y1, nvec, A, pa.tw, act, s);
   KC_LAUNCHED();
   KC_TRY(mark());
   if (op->scheme == KC_EPS_CROSSDOF) {
     cpx<T>* B = op->work_b.as<cpx<T>>();
-    k_z_plain<N, +1, T><<<g1, NT, 0, s>>>(A, B, tw, act, 3);
+    launch_zplain<N, +1, T>(op, TP_ZA, 3 * nvec, A, B, pa.tw, act, 3, s);
     KC_LAUNCHED();
     KC_TRY(mark());
-    k_zb_crossdof<N, T><<<g3, NT, 0, s>>>(B, A, ids, eps, op->n_mat, tw, act);
+    launch_zb<N, T>(op, nvec, B, A, pa.eps, pa.tw, act, s);
     KC_LAUNCHED();
   } else {
-    k_z_trivial<N, T><<<g3, NT, 0, s>>>(A, ids, eps, op->n_mat, tw, act);
+    launch_zt<N, T>(op, nvec, A, pa.eps, pa.tw, act, s);
     KC_LAUNCHED();
   }
   KC_TRY(mark());
-  k_y<N, -1, T><<<g1, NT, 0, s>>>(A, tw, act);
+  launch_y<N, -1, T>(op, TP_Y2, nvec, A, pa.tw, act, s);
   KC_LAUNCHED();
   KC_TRY(mark());
-  k_x2_fwd_curl_pen<N, T, false><<<g3, NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vm, tw);
+  launch_x2<N, T, false>(op, TP_X2, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s);
   KC_LAUNCHED();
   KC_TRY(mark());
   return KC_OK;
@@ -578,31 +719,107 @@ static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x,
 template <int N, typename T>
 static int apply_tp_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecMap& vmy, const c64* x, c64* y,
                       const float* field, int fkstride, hipStream_t s) {
+  KC_TRY((tune_tiles_n<N, T>(op, nvec, s)));
   constexpr size_t N3 = (size_t)N * N * N;
   const size_t nbuf = (size_t)nvec * 3 * N3 * sizeof(cpx<T>);
   KC_TRY(op->work_a.ensure(nbuf));
   cpx<T>* A = op->work_a.as<cpx<T>>();
-  const bool f64 = sizeof(T) == 8;
-  const cpx<T>* ktab = (f64 ? op->ktab64.as<cpx<T>>() : op->ktab32.as<cpx<T>>()) + (size_t)ik0 * 3 * N;
-  const c64* ktab64 = op->ktab64.as<c64>() + (size_t)ik0 * 3 * N;
-  const double* gam = op->gamma_d.as<double>() + ik0;
-  const cpx<T>* tw = f64 ? op->tw64.as<cpx<T>>() : op->tw32.as<cpx<T>>();
-  constexpr int P3 = TileP<N, 3, T>::P;
-  constexpr int P1 = TileP<N, 1, T>::P;
-  const unsigned g3 = nblk((size_t)nvec * N * (N / P3));
-  const unsigned g1 = nblk((size_t)nvec * 3 * N * (N / P1));
+  const PassArgs<T> pa = pass_args<N, T>(op, ik0);
   const int* act = vm.active;
-  k_x1_curl_inv<N, T, true><<<g3, NT, 0, s>>>(x, A, ktab, vm, tw);
+  launch_x1<N, T, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s);
   KC_LAUNCHED();
-  k_y<N, +1, T><<<g1, NT, 0, s>>>(A, tw, act);
+  launch_y<N, +1, T>(op, TP_Y1, nvec, A, pa.tw, act, s);
   KC_LAUNCHED();
-  k_z_field<N, T><<<g3, NT, 0, s>>>(A, field, vm.vpk, fkstride, tw, act);
+  launch_zf<N, T>(op, nvec, A, field, vm.vpk, fkstride, pa.tw, act, s);
   KC_LAUNCHED();
-  k_y<N, -1, T><<<g1, NT, 0, s>>>(A, tw, act);
+  launch_y<N, -1, T>(op, TP_Y2, nvec, A, pa.tw, act, s);
   KC_LAUNCHED();
-  k_x2_fwd_curl_pen<N, T, true><<<g3, NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw);
+  launch_x2<N, T, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s);
   KC_LAUNCHED();
   return KC_OK;
+}
+
+// Times every candidate width of every pass on min(nvec, 32) vectors (inputs: the zero-filled
+// work buffers; only the durations matter) and keeps the fastest per pass.  Runs once per
+// handle and precision, never while the stream is being captured.
+template <int N, typename T>
+static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s) {
+  const int pi = sizeof(T) == 8 ? 1 : 0;
+  if (op->tuned[pi]) return KC_OK;
+  if (N < 32) {
+    op->tuned[pi] = true;
+    return KC_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  KC_HIP(hipStreamIsCapturing(s, &cs));
+  if (cs != hipStreamCaptureStatusNone) return KC_OK;
+  constexpr size_t N3 = (size_t)N * N * N;
+  const int nv = std::max(1, std::min(nvec, 32));
+  const size_t vb = (size_t)nv * 3 * N3;
+  KC_TRY(op->work_a.ensure(vb * sizeof(c64)));
+  KC_TRY(op->work_b.ensure(vb * sizeof(c64)));
+  KC_TRY(op->work_c.ensure(2 * vb * sizeof(c64)));
+  KC_TRY(build_efield(op));
+  cpx<T>* A = op->work_a.as<cpx<T>>();
+  cpx<T>* B = op->work_b.as<cpx<T>>();
+  c64* X = op->work_c.as<c64>();
+  c64* Y = X + vb;
+  const PassArgs<T> pa = pass_args<N, T>(op, 0);
+  VecMap vm;
+  vm.vpk = nv;
+  vm.kstride = nv;
+  const float* fld = op->efield.as<float>();
+  hipEvent_t e0, e1;
+  KC_HIP(hipEventCreate(&e0));
+  KC_HIP(hipEventCreate(&e1));
+  auto run_pass = [&](int pass) {
+    switch (pass) {
+      case TP_X1: launch_x1<N, T, false>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s); break;
+      case TP_X1P: launch_x1<N, T, true>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s); break;
+      case TP_Y1: launch_y<N, +1, T>(op, pass, nv, A, pa.tw, nullptr, s); break;
+      case TP_Y2: launch_y<N, -1, T>(op, pass, nv, A, pa.tw, nullptr, s); break;
+      case TP_ZA: launch_zplain<N, +1, T>(op, pass, 3 * nv, A, B, pa.tw, nullptr, 3, s); break;
+      case TP_ZB: launch_zb<N, T>(op, nv, B, A, pa.eps, pa.tw, nullptr, s); break;
+      case TP_ZT: launch_zt<N, T>(op, nv, A, pa.eps, pa.tw, nullptr, s); break;
+      case TP_ZF: launch_zf<N, T>(op, nv, A, fld, nv, 0, pa.tw, nullptr, s); break;
+      case TP_X2: launch_x2<N, T, false>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s); break;
+      case TP_X2P: launch_x2<N, T, true>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s); break;
+      default: break;
+    }
+  };
+  int st = KC_OK;
+  for (int pass = 0; pass < TP_NPASS && st == KC_OK; ++pass) {
+    const bool three = (pass == TP_X1 || pass == TP_X1P || pass == TP_X2 || pass == TP_X2P || pass == TP_ZB ||
+                        pass == TP_ZT || pass == TP_ZF);
+    const std::vector<int> cand = three ? tile_candidates<N, 3, T>() : tile_candidates<N, 1, T>();
+    float best = 1e30f;
+    int bestp = cand[0];
+    for (int p : cand) {
+      op->tiles[pi][pass] = (int8_t)p;
+      run_pass(pass);  // warm-up
+      hipError_t e = hipEventRecord(e0, s);
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) run_pass(pass);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        set_error(std::string("tile tuning: ") + hipGetErrorString(e));
+        st = KC_ERR_HIP;
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        bestp = p;
+      }
+    }
+    op->tiles[pi][pass] = (int8_t)bestp;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == KC_OK) op->tuned[pi] = true;
+  return st;
 }
 
 // g[b][c][p] += sum_j w[b vpk + j] Re(conj(Ge_j) Gr_j)_c(p) with G = F3 K_A^{+} (the real-space
@@ -635,23 +852,18 @@ static int tp_grad_n(kc_op* op, int ik0, int nvec, int vpk, const c64* r, const 
   KC_TRY(op->work_b.ensure(nbuf));
   KC_TRY(op->work_c.ensure(nbuf));
   c64* A = op->work_a.as<c64>();
-  const c64* ktab = op->ktab64.as<c64>() + (size_t)ik0 * 3 * N;
-  const c64* tw = op->tw64.as<c64>();
-  constexpr int P3 = TileP<N, 3, T>::P;
-  constexpr int P1 = TileP<N, 1, T>::P;
-  const unsigned g3 = nblk((size_t)nvec * N * (N / P3));
-  const unsigned g1 = nblk((size_t)nvec * 3 * N * (N / P1));
+  const PassArgs<T> pa = pass_args<N, T>(op, ik0);
   VecMap vm;
   vm.vpk = vpk;
   vm.kstride = vpk;
   c64* out[2] = {op->work_b.as<c64>(), op->work_c.as<c64>()};
   const c64* in[2] = {r, e};
   for (int i = 0; i < 2; ++i) {
-    k_x1_curl_inv<N, T, true><<<g3, NT, 0, s>>>(in[i], A, ktab, vm, tw);
+    launch_x1<N, T, true>(op, TP_X1P, nvec, in[i], A, pa.ktab, vm, pa.tw, s);
     KC_LAUNCHED();
-    k_y<N, +1, T><<<g1, NT, 0, s>>>(A, tw, nullptr);
+    launch_y<N, +1, T>(op, TP_Y1, nvec, A, pa.tw, nullptr, s);
     KC_LAUNCHED();
-    k_z_plain<N, +1, T><<<g1, NT, 0, s>>>(A, out[i], tw, nullptr, 3);
+    launch_zplain<N, +1, T>(op, TP_ZA, 3 * nvec, A, out[i], pa.tw, nullptr, 3, s);
     KC_LAUNCHED();
   }
   const int nk = nvec / vpk;
@@ -661,23 +873,24 @@ static int tp_grad_n(kc_op* op, int ik0, int nvec, int vpk, const c64* r, const 
   return KC_OK;
 }
 
+// standalone 3D DFT (no handle): the default widths
 template <int N, typename T>
 static int fft3d_n(int nvec, int sign, const cpx<T>* in, cpx<T>* out, const cpx<T>* tw, hipStream_t s) {
   constexpr int P1 = TileP<N, 1, T>::P;
   const unsigned g1 = nblk((size_t)nvec * N * (N / P1));
   if (sign > 0) {
-    k_x_plain<N, +1, T><<<g1, NT, 0, s>>>(in, out, tw);
+    k_x_plain<N, +1, T, P1><<<g1, NT, 0, s>>>(in, out, tw);
     KC_LAUNCHED();
-    k_y<N, +1, T><<<g1, NT, 0, s>>>(out, tw, nullptr);
+    k_y<N, +1, T, P1><<<g1, NT, 0, s>>>(out, tw, nullptr);
     KC_LAUNCHED();
-    k_z_plain<N, +1, T><<<g1, NT, 0, s>>>(out, out, tw, nullptr, 1);
+    k_z_plain<N, +1, T, P1><<<g1, NT, 0, s>>>(out, out, tw, nullptr, 1);
     KC_LAUNCHED();
   } else {
-    k_x_plain<N, -1, T><<<g1, NT, 0, s>>>(in, out, tw);
+    k_x_plain<N, -1, T, P1><<<g1, NT, 0, s>>>(in, out, tw);
     KC_LAUNCHED();
-    k_y<N, -1, T><<<g1, NT, 0, s>>>(out, tw, nullptr);
+    k_y<N, -1, T, P1><<<g1, NT, 0, s>>>(out, tw, nullptr);
     KC_LAUNCHED();
-    k_z_plain<N, -1, T><<<g1, NT, 0, s>>>(out, out, tw, nullptr, 1);
+    k_z_plain<N, -1, T, P1><<<g1, NT, 0, s>>>(out, out, tw, nullptr, 1);
     KC_LAUNCHED();
   }
   return KC_OK;

@@ -10,6 +10,9 @@ namespace kc {
 // Largest number of materials (entries of the inverse-permittivity table).
 constexpr int KC_MAX_MAT = 64;
 
+// Operator and preconditioner passes whose tile width is tuned per handle.
+enum TilePass { TP_X1 = 0, TP_Y1, TP_ZA, TP_ZB, TP_ZT, TP_Y2, TP_X2, TP_X1P, TP_ZF, TP_X2P, TP_NPASS };
+
 // Inverse-permittivity entry of one material in compute precision T: the real diagonal
 // (eps^-1)_cc and the upper off-diagonals (eps^-1)_12, _13, _23, all pre-multiplied by 1/N^3
 // (the normalisation of the two unnormalised 3D DFTs around the permittivity step).
@@ -68,6 +71,8 @@ struct kc_op {
   kc::DevBuf efield_k;        // f32 [nb][3][N^3] learned fields of the k-points being solved
   kc::DevBuf kdev;            // double [nk][3] wave vectors
   double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int8_t tiles[2][16] = {};     // tile width per pass (kc::TilePass), [FP32, FP64]; 0 = default
+  bool tuned[2] = {false, false};
 };
 
 namespace kc {
