@@ -204,7 +204,9 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
 
 /* Statistics of the last kc_solve: float64 [8] = {matvecs FP64 (vector count), matvecs FP32,
  * seconds total, iterations (sum over k-points), k-points that kept the transverse or learned
- * preconditioner to the end, preconditioner applications (vector count), 0, 0}. */
+ * preconditioner to the end, preconditioner applications (vector count), iterations whose Gram
+ * step formed only the new directions' columns (the X/P blocks taken from the previous
+ * Rayleigh-Ritz step), 0}. */
 int kc_last_solve_stats(const kc_op* op, double* stats_host);
 
 /*

@@ -10,6 +10,14 @@ namespace kc {
 int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
           const int* kskip, hipStream_t s);
 
+// The W columns of the Gram matrices of S = [X W P] (kstride-spaced blocks of 3mb columns):
+// GB(:, W) = S^H W, GA(:, W) = S^H AW, with the X/P blocks filled from the previous
+// Rayleigh-Ritz step: GB_XX = GB_PP = I, GB_XP = 0, GA_XX = diag(theta), GA_XP = 0,
+// GA_PP = gapp ([nb][mb][mb]).  Valid while X and P are the last Rayleigh-Ritz output and AX, AP
+// their updated images.
+int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
+          const double* theta, const c64* gapp, const int* kskip, hipStream_t s);
+
 // Y_b[:, map(j)] = S_b[:, scol0 .. scol0+p) C_b, C: [nb][p][q]; output column j < q goes to
 // ycol0 + j (j < q1) or ycol1 + j - q1; Y may alias S.
 int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, int q, int q1, int ycol0,
@@ -33,7 +41,9 @@ constexpr int RR_NMAX = 64;  // 3 * block size
 // smallest Ritz values theta and Cu = [C1 | Cp] (3mb x 2mb) with X_new = S C1, P_new = S Cp
 // (P_new orthonormal and orthogonal to X_new in the GB inner product).  The columns of S need
 // not be normalised or orthogonal: the pencil is scaled to unit diagonal first.
+// Also writes gapp_out[b] = P_new^H A P_new = Cp^H GA Cp (mb x mb) for the next step's gramw.
 int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,
-             double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, hipStream_t s);
+             double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, c64* gapp_out,
+             hipStream_t s);
 
 }  // namespace kc

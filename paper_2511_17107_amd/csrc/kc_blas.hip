@@ -195,6 +195,174 @@ __global__ void k_gram2_reduce(const c64* __restrict__ part, int nchunk, int nti
 }
 
 // ------------------------------------------------------------------------------------
+// Gram blocks of the new directions only: [GB | GA](:, W) = S^H [W | AW] (nc x 2mb) in one pass
+// over S (nc columns) and AW (mb columns); the blocks between X and P follow from the previous
+// Rayleigh-Ritz step (X^H X = I, X^H AX = Theta, X^H P = X^H AP = 0, P^H P = I, P^H AP stored by
+// it) and are filled by k_gramw_reduce.  Stage row: S at [0, 64), [W | AW] at [64, 64 + 2mb),
+// zeros after; the 16x16 tiles (ti < ceil(nc/16), tj < ceil(2mb/16)) are dealt to the 8 waves.
+// ------------------------------------------------------------------------------------
+constexpr int GW_R = G2_COLS;                      // start of [W | AW] in a stage row
+constexpr int GW_ZERO = G2_COLS + 48;              // 16 zero entries
+constexpr int GW_PITCH = G2_COLS + 48 + 16 + 1;
+
+__global__ __launch_bounds__(G2_THREADS) void k_gramw(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
+                                                      int mb, int kstride, int rows_per_chunk, int ntile,
+                                                      c64* __restrict__ part, const int* __restrict__ kskip) {
+  __shared__ c64 st[G2_ROWS * GW_PITCH];
+  const int b = blockIdx.y;
+  if (kskip && kskip[b]) return;
+  const int nc = 3 * mb;
+  const int chunk = blockIdx.x;
+  const int TR = (2 * mb + 15) / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int MAXT = 2;
+  int tti[MAXT], ttj[MAXT];
+  int nt = 0;
+  for (int t = 0; t < MAXT; ++t) {
+    const int id = wave + 8 * t;
+    if (id < ntile) {
+      tti[t] = id / TR;
+      ttj[t] = id % TR;
+      ++nt;
+    } else {  // reads the zero entries
+      tti[t] = GW_ZERO / 16;
+      ttj[t] = (GW_ZERO - GW_R) / 16;
+    }
+  }
+  d4 p1[MAXT], p2[MAXT], p3[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    p1[t] = d4{0, 0, 0, 0};
+    p2[t] = d4{0, 0, 0, 0};
+    p3[t] = d4{0, 0, 0, 0};
+  }
+  const c64* Sb = S + (size_t)b * kstride * n;
+  const c64* AWb = AS + ((size_t)b * kstride + mb) * n;
+  const size_t r_begin = (size_t)chunk * rows_per_chunk;
+  const size_t r_end = std::min(n, r_begin + rows_per_chunk);
+  const int ncl = nc + mb;  // loaded columns: S, then AW
+  constexpr int PER = (G2_ROWS * 80 + G2_THREADS - 1) / G2_THREADS;
+  c64 nxt[PER];
+  auto fetch = [&](size_t r0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * G2_THREADS;
+      c64 v = mk(0.0, 0.0);
+      if (e < G2_ROWS * ncl) {
+        const int c = e / G2_ROWS, r = e % G2_ROWS;
+        const size_t row = r0 + r;
+        if (row < r_end) v = (c < nc) ? Sb[(size_t)c * n + row] : AWb[(size_t)(c - nc) * n + row];
+      }
+      nxt[q] = v;
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * G2_THREADS;
+      if (e < G2_ROWS * ncl) {
+        const int c = e / G2_ROWS;
+        c64* row = st + (e % G2_ROWS) * GW_PITCH;
+        if (c < nc) {
+          row[c] = nxt[q];
+          if (c >= mb && c < 2 * mb) row[GW_R + c - mb] = nxt[q];  // W, again on the right
+        } else {
+          row[GW_R + mb + c - nc] = nxt[q];  // AW
+        }
+      }
+    }
+  };
+  for (int e = threadIdx.x; e < G2_ROWS * GW_PITCH; e += blockDim.x) st[e] = mk(0.0, 0.0);
+  __syncthreads();
+  if (r_begin < r_end) {
+    fetch(r_begin);
+    stash();
+  }
+  __syncthreads();
+  for (size_t r0 = r_begin; r0 < r_end; r0 += G2_ROWS) {
+    const bool more = r0 + G2_ROWS < r_end;
+    if (more) fetch(r0 + G2_ROWS);
+#pragma unroll
+    for (int kb = 0; kb < G2_ROWS; kb += 4) {
+      const c64* srow = st + (kb + lk) * GW_PITCH;
+      asm volatile("" ::: "memory");
+      c64 av[MAXT], bv[MAXT];
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) {
+        av[t] = srow[tti[t] * 16 + li];
+        bv[t] = srow[GW_R + ttj[t] * 16 + li];
+      }
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) p1[t] = mfma(av[t].re, bv[t].re, p1[t]);
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) p2[t] = mfma(av[t].im, bv[t].im, p2[t]);
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) p3[t] = mfma(av[t].re - av[t].im, bv[t].re + bv[t].im, p3[t]);
+    }
+    __syncthreads();
+    if (more) stash();
+    __syncthreads();
+  }
+  const int nchunk = gridDim.x;
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) {
+    if (t < nt) {
+      c64* out = part + (((size_t)b * nchunk + chunk) * ntile + (wave + 8 * t)) * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out[(lk + 4 * r) * 16 + li] = mk(p1[t][r] + p2[t][r], p3[t][r] - p1[t][r] + p2[t][r]);
+    }
+  }
+}
+
+// Sum the partial tiles and scatter S^H W into GB(:, W), S^H AW into GA(:, W) (and the
+// conjugates into the W rows); blockIdx.y == ntile fills the known X/P blocks instead.
+__global__ void k_gramw_reduce(const c64* __restrict__ part, int nchunk, int ntile, int mb, c64* __restrict__ GA,
+                               c64* __restrict__ GB, const double* __restrict__ theta,
+                               const c64* __restrict__ gapp, const int* __restrict__ kskip) {
+  const int b = blockIdx.z;
+  if (kskip && kskip[b]) return;
+  const int nc = 3 * mb;
+  c64* ga = GA + (size_t)b * nc * nc;
+  c64* gb = GB + (size_t)b * nc * nc;
+  const int t = blockIdx.y;
+  if (t == ntile) {
+    // X rows/cols are [0, mb), P rows/cols [2mb, 3mb)
+    for (int e = threadIdx.x; e < 4 * mb * mb; e += blockDim.x) {
+      const int i0 = e / (2 * mb), j0 = e % (2 * mb);
+      const int i = i0 < mb ? i0 : i0 + mb, j = j0 < mb ? j0 : j0 + mb;
+      const bool xi = i < mb, xj = j < mb;
+      c64 vb = mk((i == j) ? 1.0 : 0.0, 0.0), va = mk(0.0, 0.0);
+      if (xi && xj) {
+        if (i == j) va = mk(theta[b * mb + i], 0.0);
+      } else if (!xi && !xj) {
+        va = gapp[((size_t)b * mb + (i - 2 * mb)) * mb + (j - 2 * mb)];
+      }
+      gb[(size_t)i * nc + j] = vb;
+      ga[(size_t)i * nc + j] = va;
+    }
+    return;
+  }
+  const int e = threadIdx.x;
+  const int TR = (2 * mb + 15) / 16;
+  const int ti = t / TR, tj = t % TR;
+  const c64* src = part + ((size_t)b * nchunk * ntile + t) * 256 + e;
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < nchunk; ++k) {
+    const c64 v = src[(size_t)k * ntile * 256];
+    sr += v.re;
+    si += v.im;
+  }
+  const int i = ti * 16 + e / 16, jj = tj * 16 + e % 16;
+  if (i >= nc || jj >= 2 * mb) return;
+  c64* G = (jj < mb) ? gb : ga;
+  const int j = mb + (jj < mb ? jj : jj - mb);
+  G[(size_t)i * nc + j] = mk(sr, si);
+  if (i < mb || i >= 2 * mb) G[(size_t)j * nc + i] = mk(sr, -si);
+}
+
+// ------------------------------------------------------------------------------------
 // Update: Y_b[:, map(j)] = sum_c S_b[:, c] C_b[c][j], j < q, in place (Y may be S).
 // Computed transposed, D = C^T S^T: the B operand lanes read 16 consecutive rows of one
 // column (coalesced), the output lanes hold 16 consecutive rows of one output column.
@@ -414,6 +582,31 @@ int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, De
   KC_LAUNCHED();
   dim3 g2(1, ntile, nb);
   k_gram2_reduce<<<g2, 256, 0, s>>>(part.as<c64>(), nchunk, ntile, nc, GA, GB, kskip);
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
+          const double* theta, const c64* gapp, const int* kskip, hipStream_t s) {
+  const int nc = 3 * mb;
+  const int T = (nc + 15) / 16, TR = (2 * mb + 15) / 16;
+  const int ntile = T * TR;
+  if (nc > 64 || 2 * mb > 48 || ntile > 16) {
+    set_error("gramw: too many columns");
+    return KC_ERR_INVALID_ARG;
+  }
+  const size_t target_wg = 2048;
+  const size_t per_k = std::max<size_t>(1, target_wg / (size_t)nb);
+  size_t rows = (n + per_k - 1) / per_k;
+  rows = std::max<size_t>(rows, 64);
+  rows = (rows + G2_ROWS - 1) / G2_ROWS * G2_ROWS;
+  const int nchunk = (int)((n + rows - 1) / rows);
+  KC_TRY(part.ensure((size_t)nb * nchunk * ntile * 256 * sizeof(c64)));
+  dim3 grid(nchunk, nb);
+  k_gramw<<<grid, G2_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, part.as<c64>(), kskip);
+  KC_LAUNCHED();
+  dim3 g2(1, ntile + 1, nb);
+  k_gramw_reduce<<<g2, 256, 0, s>>>(part.as<c64>(), nchunk, ntile, mb, GA, GB, theta, gapp, kskip);
   KC_LAUNCHED();
   return KC_OK;
 }

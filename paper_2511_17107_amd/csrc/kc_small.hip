@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
                                                   const int* __restrict__ pmask, double* __restrict__ theta,
                                                   c64* __restrict__ Cu, int* __restrict__ pvalid,
                                                   c64* __restrict__ Lsave, int* __restrict__ flags,
-                                                  const int* __restrict__ kskip) {
+                                                  const int* __restrict__ kskip, c64* __restrict__ gapp_out) {
   const int b = blockIdx.x;
   if (kskip && kskip[b]) return;
   extern __shared__ c64 sm[];
@@ -436,10 +436,36 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
   }
   for (int j = threadIdx.x; j < mb; j += blockDim.x) pvalid[b * mb + j] = pact[j];
   if (threadIdx.x == 0 && brk) atomicOr(&flags[b], 1);
+  if (gapp_out) {
+    // P_new^H A P_new = Cp^H GA Cp over the active columns, for the next step's Gram blocks
+    __syncthreads();
+    c64* T1 = Bm;  // n x mb (LDC)
+    auto cup = [&](int i, int a) -> c64 { return pact[a] ? sc[i] * conj(YH[a * LD + i]) : mk(0.0, 0.0); };
+    for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {
+      const int i = e / mb, a = e % mb;
+      c64 acc = mk(0.0, 0.0);
+      if (act[i])
+        for (int j = 0; j < n; ++j)
+          if (act[j]) {
+            const c64 x = ga[(size_t)i * n + j], y = ga[(size_t)j * n + i];
+            acc = acc + mk(0.5 * (x.re + y.re), 0.5 * (x.im - y.im)) * cup(j, a);
+          }
+      T1[i * LDC + a] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) {
+      const int a = e / mb, c = e % mb;
+      c64 acc = mk(0.0, 0.0);
+      for (int i = 0; i < n; ++i)
+        if (act[i]) acc = acc + cmulc(cup(i, a), T1[i * LDC + c]);
+      gapp_out[((size_t)b * mb + a) * mb + c] = acc;
+    }
+  }
 }
 
 int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,
-             double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, hipStream_t s) {
+             double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, c64* gapp_out,
+             hipStream_t s) {
   if (3 * mb > RR_NMAX || mb > 21) {
     set_error("block size too large");
     return KC_ERR_INVALID_ARG;
@@ -450,7 +476,8 @@ int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, con
     KC_HIP(hipFuncSetAttribute((const void*)k_small_rr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     attr = true;
   }
-  k_small_rr<<<nb, 256, shm, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave, flags, kskip);
+  k_small_rr<<<nb, 256, shm, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave, flags, kskip,
+                                  gapp_out);
   KC_LAUNCHED();
   return KC_OK;
 }

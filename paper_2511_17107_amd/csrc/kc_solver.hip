@@ -30,7 +30,7 @@ namespace kc {
 struct SolverWork {
   DevBuf S, AS;
   DevBuf part_gram, part_res;
-  DevBuf GA, GB, Cu, Lsave;
+  DevBuf GA, GB, Cu, Lsave, GApp;
   DevBuf theta, res, xn2;
   DevBuf R, tmask;  // residuals (input of T_E) and the columns that get T_E R
   DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal, wskip [nb each]
@@ -74,12 +74,19 @@ int apply_cols(Batch& B, int col0, const int* active, int prec) {
   return apply_op(B.op, B.ik0, B.nb * B.mb, vm, B.S + (size_t)col0 * B.n, B.AS + (size_t)col0 * B.n, prec, B.s);
 }
 
-int rayleigh_ritz(Batch& B) {
-  KC_TRY(gram2(B.S, B.AS, B.nc, B.nc, B.n, B.nb, B.w->part_gram, B.w->GA.as<c64>(), B.w->GB.as<c64>(), B.kskip,
-               B.s));
+// Gram matrices (all blocks, or with `implicit` only the W columns, the X/P blocks coming from
+// the previous step), small Rayleigh-Ritz, update
+int rayleigh_ritz(Batch& B, bool implicit = false) {
+  if (implicit) {
+    KC_TRY(gramw(B.S, B.AS, B.nc, B.mb, B.n, B.nb, B.w->part_gram, B.w->GA.as<c64>(), B.w->GB.as<c64>(),
+                 B.w->theta.as<double>(), B.w->GApp.as<c64>(), B.kskip, B.s));
+  } else {
+    KC_TRY(gram2(B.S, B.AS, B.nc, B.nc, B.n, B.nb, B.w->part_gram, B.w->GA.as<c64>(), B.w->GB.as<c64>(),
+                 B.kskip, B.s));
+  }
   KC_TRY(small_rr(B.w->GA.as<c64>(), B.w->GB.as<c64>(), B.mb, B.nb, B.xmask, B.wmask, B.pmask,
                   B.w->theta.as<double>(), B.w->Cu.as<c64>(), B.pvalid, B.w->Lsave.as<c64>(), B.flags, B.kskip,
-                  B.s));
+                  B.w->GApp.as<c64>(), B.s));
   // [X | P] <- S Cu, [AX | AP] <- AS Cu
   KC_TRY(update(B.S, B.nc, 0, B.nc, B.S, B.nc, 2 * B.mb, B.mb, 0, 2 * B.mb, B.w->Cu.as<c64>(), B.n, B.nb,
                 B.kskip, B.s));
@@ -134,6 +141,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(w->GB.ensure((size_t)nb * nc * nc * sizeof(c64)));
   KC_TRY(w->Cu.ensure((size_t)nb * nc * 2 * mb * sizeof(c64)));
   KC_TRY(w->Lsave.ensure((size_t)nb * RR_NMAX * RR_NMAX * sizeof(c64)));
+  KC_TRY(w->GApp.ensure((size_t)nb * mb * mb * sizeof(c64)));
   KC_TRY(w->theta.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->res.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->xn2.ensure((size_t)nb * mb * sizeof(double)));
@@ -217,26 +225,31 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   // captured once per precision into a hipGraph and replayed; every launch has a fixed grid
   // (masked columns exit early), reads its masks from device memory and writes to buffers
   // sized before the first capture.
-  auto body = [&](int pr) -> int {
+  // With `implicit` the Gram step forms only the W columns (the X/P blocks are known from the
+  // previous Rayleigh-Ritz step); that is valid while X, P, AX and AP are the last step's output,
+  // so after a fresh application of Op to X or P (precision switch, verification) or a
+  // breakdown the next step forms all blocks, and near convergence (Res within 1e4 tol) every
+  // step does, where rounding in the assumed blocks would show.
+  auto body = [&](int pr, bool implicit) -> int {
     if (tp) KC_TRY(precond_tp(B));
     KC_TRY(apply_cols(B, mb, B.wmask, pr));
-    KC_TRY(rayleigh_ritz(B));
+    KC_TRY(rayleigh_ritz(B, implicit));
     return residuals(B, tp);
   };
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
   struct GraphGuard {
     hipGraphExec_t* g;
     ~GraphGuard() {
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i)
         if (g[i]) (void)hipGraphExecDestroy(g[i]);
     }
   } gguard{gexec};
-  auto run_body = [&](int pr) -> int {
-    if (!o.graph) return body(pr);
-    const int slot = (pr == KC_PREC_FP64) ? 1 : 0;
+  auto run_body = [&](int pr, bool implicit) -> int {
+    if (!o.graph) return body(pr, implicit);
+    const int slot = ((pr == KC_PREC_FP64) ? 1 : 0) + (implicit ? 2 : 0);
     if (!gexec[slot]) {
       KC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      const int st = body(pr);
+      const int st = body(pr, implicit);
       hipGraph_t g = nullptr;
       const hipError_t e = hipStreamEndCapture(s, &g);
       if (st != KC_OK) {
@@ -257,6 +270,8 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   int stall = 0;
   bool verify_pending = false;
   bool need_resid = true;
+  bool full_gram = true;  // the next Gram step forms all blocks
+  double ngram_w = 0;
   while (true) {
     if (need_resid) KC_TRY(residuals(B, tp));
     need_resid = true;
@@ -272,6 +287,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       if (hflags[b] & 1) {
         reset_flags = true;
         drop_p[b] = 1;
+        full_gram = true;
         if (++brk_count[b] > 5) {
           set_error("LOBPCG breakdown (loss of positive definiteness or non-finite values) at k-point " +
                     std::to_string(ik0 + b));
@@ -365,6 +381,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       KC_TRY(apply_cols(B, 0, B.wmask, KC_PREC_FP64));
       nmv64 += ncand * mb;
       verify_pending = true;
+      full_gram = true;
       continue;
     }
     if (it >= o.maxit) break;
@@ -378,6 +395,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       }
       if (mxres <= o.switch_tol || stall >= 4 || ncand > 0) {
         prec = KC_PREC_FP64;
+        full_gram = true;
         std::vector<int> act(nb * mb, 0);
         for (int b = 0; b < nb; ++b)
           if (!done[b])
@@ -422,7 +440,10 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       KC_TRY(upload_ints(B.w->tmask.as<int>(), ht, s));
       napp += nt;
     }
-    KC_TRY(run_body(prec));
+    const bool implicit = !full_gram && mxres > 1e4 * o.tol;
+    KC_TRY(run_body(prec, implicit));
+    ngram_w += implicit;
+    full_gram = false;
     need_resid = false;
     (prec == KC_PREC_FP64 ? nmv64 : nmv32) += nact;
     ++it;
@@ -451,6 +472,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   op->stats[3] += (double)it * nb;
   for (int b = 0; b < nb; ++b) op->stats[4] += lon[b];  // k-points that kept T_E to the end
   op->stats[5] += napp;
+  op->stats[6] += ngram_w;  // iterations whose Gram step formed only the W columns
   *all_conv = allc;
   return KC_OK;
 }

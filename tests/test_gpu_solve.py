@@ -116,6 +116,7 @@ def test_mixed_precision_matches_fp64():
     assert st == 0 and res.max() <= TOL
     stats = op.last_solve_stats()
     assert stats[1] > 0  # FP32 applications happened
+    assert stats[6] > 0  # some Gram steps formed only the W columns (X/P blocks from the last step)
     for i, c in enumerate(cases):
         ref = np.array(c["eigenvalues"])
         assert np.max(np.abs(eig[i] - ref) / ref) <= REL
