@@ -35,7 +35,8 @@ int random_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, uint
                  hipStream_t s);
 
 // Small dense steps (one workgroup per k-point), see kc_small.hip.
-constexpr int RR_NMAX = 64;  // 3 * block size
+constexpr int RR_NMAX = 64;      // 3 * block size
+constexpr int RR_THREADS = 1024;  // one workgroup per k-point: 16 waves hide the LDS latency
 
 // Rayleigh-Ritz on S = [X W P]: from GA = S^H AS, GB = S^H S (3mb x 3mb) compute the mb
 // smallest Ritz values theta and Cu = [C1 | Cp] (3mb x 2mb) with X_new = S C1, P_new = S Cp

@@ -1,4 +1,4 @@
-// Small dense steps of the LOBPCG iteration, one workgroup (256 threads) per k-point, all in
+// Small dense steps of the LOBPCG iteration, one workgroup (1024 threads) per k-point, all in
 // LDS and FP64: masked Cholesky, triangular solves, cyclic Jacobi for complex Hermitian
 // matrices with a parallel (round-robin) pair ordering, Ritz-vector selection and the
 // construction of the next search direction P orthogonal to the new Ritz vectors.
@@ -25,6 +25,7 @@ __device__ void chol_masked(c64* A, int n, int* act, const double* diag0, double
                             int* breakdown) {
   __shared__ double piv;
   __shared__ int fail;
+  __shared__ c64 colj[LD];
   for (int j = 0; j < n; ++j) {
     if (threadIdx.x == 0) {
       const double d = A[j * LD + j].re;
@@ -47,13 +48,17 @@ __device__ void chol_masked(c64* A, int n, int* act, const double* diag0, double
       continue;
     }
     const double ip = 1.0 / piv;
-    for (int t = j + 1 + threadIdx.x; t < n; t += blockDim.x) A[t * LD + j] = ip * A[t * LD + j];
+    for (int t = j + 1 + threadIdx.x; t < n; t += blockDim.x) {
+      const c64 v = ip * A[t * LD + j];
+      A[t * LD + j] = v;
+      colj[t] = v;  // contiguous copy: the update below reads it along k without bank conflicts
+    }
     if (threadIdx.x == 0) A[j * LD + j] = mk(piv, 0.0);
     __syncthreads();
     const int m = n - j - 1;
     for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
       const int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) A[i * LD + k] = A[i * LD + k] - A[i * LD + j] * conj(A[k * LD + j]);
+      if (k <= i) A[i * LD + k] = A[i * LD + k] - colj[i] * conj(colj[k]);
     }
     __syncthreads();
   }
@@ -106,7 +111,10 @@ __device__ void conj_transpose(c64* A, int n) {
 // the round-robin schedule (na-1 rounds of na/2 disjoint pairs per sweep over the na active
 // indices); one round updates every 2x2 block A[{p_k,q_k},{p_l,q_l}] <- J_k^H A J_l at once.
 // Rotations with |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) are skipped; sweeps stop when none is applied.
-__device__ void jacobi(c64* A, c64* V, int n, const int* act) {
+// A pair is rotated while |a_pq| > 1e-15 sqrt(|a_pp a_qq|) (relative accuracy) and |a_pq| is
+// above the rounding floor 4e-16 ||A||_F that the 2x2 updates themselves leave behind; without
+// the second test, pairs of a small and a large diagonal entry would keep rotating on noise.
+__device__ void jacobi(c64* A, c64* V, int n, const int* act, double fro) {
   __shared__ int idx[LD];
   __shared__ int na;
   __shared__ int pp[LD / 2], qq[LD / 2];
@@ -145,7 +153,7 @@ __device__ void jacobi(c64* A, c64* V, int n, const int* act) {
           const c64 apq = A[p * LD + q];
           const double g = sqrt(abs2(apq));
           const double app = A[p * LD + p].re, aqq = A[q * LD + q].re;
-          if (g > 1e-300 && g > 1e-15 * sqrt(fabs(app * aqq))) {
+          if (g > 1e-300 && g > 1e-15 * sqrt(fabs(app * aqq)) && g > 4e-16 * fro) {
             const double tau = (aqq - app) / (2.0 * g);
             const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
@@ -188,9 +196,10 @@ __device__ void jacobi(c64* A, c64* V, int n, const int* act) {
         if (qk >= 0) A[qk * LD + pl] = d10;
         if (qk >= 0 && ql >= 0) A[qk * LD + ql] = d11;
       }
-      // eigenvectors: V <- V J (all rows)
+      // eigenvectors: V <- V J (all rows); consecutive lanes take different pairs of one row, so
+      // their LDS addresses fall in different banks (a column walk would hit one bank)
       for (int e = threadIdx.x; e < half * n; e += blockDim.x) {
-        const int l = e / n, i = e % n;
+        const int i = e / half, l = e % half;
         const int p = pp[l], q = qq[l];
         if (q < 0) continue;
         const double c = cc[l], s = ss[l];
@@ -209,7 +218,7 @@ __device__ void jacobi(c64* A, c64* V, int n, const int* act) {
 // ------------------------------------------------------------------------------------
 // Rayleigh-Ritz.  Dynamic LDS: Am (LD x LD), Bm (LD x LD), C1 (LD x mb).
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, const c64* __restrict__ GB, int mb,
+__global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__ GA, const c64* __restrict__ GB, int mb,
                                                   const int* __restrict__ xmask, const int* __restrict__ wmask,
                                                   const int* __restrict__ pmask, double* __restrict__ theta,
                                                   c64* __restrict__ Cu, int* __restrict__ pvalid,
@@ -290,18 +299,24 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  {  // ||A||_F over the active part: per-thread sums, wave sums by shuffles, then the waves
     double f = 0.0;
-    int na = 0;
-    for (int i = 0; i < n; ++i) {
-      if (!act[i]) continue;
-      ++na;
-      for (int j = 0; j < n; ++j)
-        if (act[j]) f += abs2(Am[i * LD + j]);
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      if (act[i] && act[j]) f += abs2(Am[i * LD + j]);
     }
-    fro = sqrt(f);
-    nact = na;
-    if (!std::isfinite(f) || na < mb) brk = 1;
+    for (int o = 32; o > 0; o >>= 1) f += __shfl_down(f, o, 64);
+    if ((threadIdx.x & 63) == 0) ev[threadIdx.x >> 6] = f;  // ev is free until the Jacobi ends
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < RR_THREADS / 64; ++w) t += ev[w];
+      int na = 0;
+      for (int i = 0; i < n; ++i) na += act[i] ? 1 : 0;
+      fro = sqrt(t);
+      nact = na;
+      if (!std::isfinite(t) || na < mb) brk = 1;
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -314,7 +329,7 @@ __global__ __launch_bounds__(256) void k_small_rr(const c64* __restrict__ GA, co
     Bm[i * LD + j] = (i == j) ? mk(1.0, 0.0) : mk(0.0, 0.0);
   }
   __syncthreads();
-  jacobi(Am, Bm, n, act);
+  jacobi(Am, Bm, n, act, fro);
   // ascending order by rank (ties by index)
   for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = Am[i * LD + i].re;
   __syncthreads();
@@ -476,7 +491,7 @@ int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, con
     KC_HIP(hipFuncSetAttribute((const void*)k_small_rr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     attr = true;
   }
-  k_small_rr<<<nb, 256, shm, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave, flags, kskip,
+  k_small_rr<<<nb, RR_THREADS, shm, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave, flags, kskip,
                                   gapp_out);
   KC_LAUNCHED();
   return KC_OK;
