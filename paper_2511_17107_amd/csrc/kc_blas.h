@@ -23,6 +23,18 @@ int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, De
 int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, int q, int q1, int ycol0,
            int ycol1, const c64* C, size_t n, int nb, const int* kskip, hipStream_t s);
 
+// Workgroups per k-point of update and update_res (update_res's partial sums take
+// nb * mb * update_grid_x(n, nb) * 2 doubles).
+unsigned update_grid_x(size_t n, int nb);
+
+// Both updates of a Rayleigh-Ritz step and the next residuals in one pass (S, AS: kstride-spaced
+// groups of 3mb columns [X W P], C: [nb][3mb][2mb]): [X P] <- S C, [AX AP] <- AS C in place,
+// R_j = AX_j - theta_j X_j into R ([nb*mb][n]), res_j = |r_j| / |x_j| and xnorm2_j = |x_j|^2.
+int update_res(c64* S, c64* AS, int kstride, int mb, const c64* C, size_t n, int nb, const double* theta, c64* R,
+               double* part, double* res, double* xnorm2, const int* kskip, hipStream_t s);
+// Sets the LDS limit of update_res's kernels (call once before update_res is captured in a graph).
+int update_res_prepare();
+
 // W_j = K_P^{-1} (AX_j - theta_j X_j), res_j = |AX_j - theta_j X_j| / |X_j|; optionally the
 // residuals themselves (Rout, contiguous [nb*mb][3N^3]) and |r_j|^2 (rnorm2); W is left
 // untouched for the k-points b with wskip[b] != 0.

@@ -370,81 +370,216 @@ __global__ void k_gramw_reduce(const c64* __restrict__ part, int nchunk, int nti
 // column j goes to column (j < q1 ? ycol0 + j : ycol1 + j - q1).  Each wave owns 16 rows at
 // a time, so all reads of its rows happen before its writes and other waves never touch them.
 // ------------------------------------------------------------------------------------
-template <int TQ>
-__global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64* __restrict__ C, size_t n,
-                                                int p, int q, int skstride, int scol0, int ykstride, int q1,
-                                                int ycol0, int ycol1, const int* __restrict__ kskip) {
-  constexpr int PK = RR_NMAX / 4;  // input columns in groups of 4 (p <= 64)
-  constexpr int QP = TQ * 16;      // output columns padded to whole tiles
-  extern __shared__ c64 csh[];     // C_b zero-padded to (4 PK) x QP
-  const int b = blockIdx.y;
-  if (kskip && kskip[b]) return;
-  const c64* Cb = C + (size_t)b * p * q;
-  for (int t = threadIdx.x; t < 4 * PK * QP; t += blockDim.x) {
-    const int r = t / QP, c = t % QP;
-    csh[t] = (r < p && c < q) ? Cb[r * q + c] : mk(0.0, 0.0);
-  }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int li = lane & 15, lk = lane >> 4;
-  const c64* Sb = S + ((size_t)b * skstride + scol0) * n;
-  c64* Yb = Y + (size_t)b * ykstride * n;
-  const size_t nblk = (n + 15) / 16;
-  for (size_t rb = (size_t)blockIdx.x * 4 + wave; rb < nblk; rb += (size_t)gridDim.x * 4) {
-    const size_t row = rb * 16 + li;
-    const bool rok = row < n;
-    // all inputs of this wave's 16 rows first (many loads in flight), then the MFMAs.  Loads
-    // are unconditional (row and column clamped into range): columns past p meet zero rows of
-    // the padded C, rows past n are not stored.
-    const size_t rowc = rok ? row : n - 1;
-    // C is re-read from LDS for every row block: kept in registers across the loop it would
-    // take 3/4 of the register file and halve the occupancy
-    asm volatile("" ::: "memory");
-    c64 sv[PK];
+// One wave's 16 rows of S_b C_b: the products of all output tiles accumulate in p1, p2, p3
+// (Gauss: Re = P1 - P2, Im = P3 - P1 - P2); output lane (lk, li) of tile t holds output column
+// t*16 + lk + 4r, r < 4, of row rb*16 + li.  C_b sits zero-padded in LDS (re-read per row
+// block so that it does not occupy registers: kept in registers across the loop it would take
+// 3/4 of the register file and halve the occupancy).  All 4*PK input loads are issued before
+// the MFMAs and are unconditional: the column is clamped below p (those columns meet zero rows
+// of the padded C) and the row below n (rows past n are never stored).
+// With U (p a multiple of 4) the clamp moves whole groups of 4 columns, so every column offset
+// is uniform (scalar registers) and a lane adds only its 32-bit byte offset `boff` (lk*n + row);
+// otherwise each lane clamps its own column.
+template <int TQ, bool U>
+__device__ __forceinline__ void rows_times_c(const c64* Sb, const c64* csh, int p, size_t n, size_t rowc,
+                                             uint32_t boff, int lk, int li, d4 (&p1)[TQ], d4 (&p2)[TQ],
+                                             d4 (&p3)[TQ]) {
+  constexpr int PK = RR_NMAX / 4;
+  constexpr int QP = TQ * 16;
+  asm volatile("" ::: "memory");
+  c64 sv[PK];
+  if constexpr (U) {
+#pragma unroll
+    for (int kb = 0; kb < PK; ++kb) {
+      const char* cb = reinterpret_cast<const char*>(Sb + (size_t)min(kb * 4, p - 4) * n);
+      sv[kb] = *reinterpret_cast<const c64*>(cb + boff);
+    }
+  } else {
 #pragma unroll
     for (int kb = 0; kb < PK; ++kb) {
       const int c = min(kb * 4 + lk, p - 1);
       sv[kb] = Sb[(size_t)c * n + rowc];
     }
-    // keep every load issued ahead of the MFMAs (each MFMA group then waits only for its own)
-    asm volatile("" ::: "memory");
-    // three real products per complex one (Gauss): P1 = Cr Sr, P2 = Ci Si,
-    // P3 = (Cr + Ci)(Sr + Si); Re(Y) = P1 - P2, Im(Y) = P3 - P1 - P2
+  }
+  // keep every load issued ahead of the MFMAs (each MFMA group then waits only for its own)
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int t = 0; t < TQ; ++t) {
+    p1[t] = d4{0, 0, 0, 0};
+    p2[t] = d4{0, 0, 0, 0};
+    p3[t] = d4{0, 0, 0, 0};
+  }
+#pragma unroll
+  for (int kb = 0; kb < PK; ++kb) {
+    const int ca = kb * 4 + lk;
+    // A operand lane (i = li -> output column, k = lk -> input column): C[k][i];
+    // B operand lane (k = lk -> input column, j = li -> row): S[row][k]
+    c64 cv[TQ];
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) cv[t] = csh[ca * QP + t * 16 + li];
+    const double ssum = sv[kb].re + sv[kb].im;
+    // consecutive MFMAs go to different accumulators
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) p1[t] = mfma(cv[t].re, sv[kb].re, p1[t]);
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) p2[t] = mfma(cv[t].im, sv[kb].im, p2[t]);
+#pragma unroll
+    for (int t = 0; t < TQ; ++t) p3[t] = mfma(cv[t].re + cv[t].im, ssum, p3[t]);
+  }
+}
+
+// Element (column col, lane offset) of a column block: with U the column part is uniform and
+// the lane part is the 32-bit byte offset boff, else plain indexing with the lane's row.
+template <bool U>
+__device__ __forceinline__ c64& elem(c64* base, int col, size_t n, uint32_t boff, size_t row) {
+  if constexpr (U)
+    return *reinterpret_cast<c64*>(reinterpret_cast<char*>(base + (size_t)col * n) + boff);
+  else
+    return base[(size_t)col * n + row];
+}
+
+// C_b (p x q) into LDS, zero-padded to RR_NMAX x TQ*16
+template <int TQ>
+__device__ __forceinline__ void stage_c(const c64* Cb, c64* csh, int p, int q) {
+  constexpr int QP = TQ * 16;
+  for (int t = threadIdx.x; t < RR_NMAX * QP; t += blockDim.x) {
+    const int r = t / QP, c = t % QP;
+    csh[t] = (r < p && c < q) ? Cb[r * q + c] : mk(0.0, 0.0);
+  }
+}
+
+template <int TQ, bool U>
+__global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64* __restrict__ C, size_t n,
+                                                int p, int q, int skstride, int scol0, int ykstride, int q1,
+                                                int ycol0, int ycol1, const int* __restrict__ kskip) {
+  extern __shared__ c64 csh[];  // C_b zero-padded to RR_NMAX x TQ*16
+  const int b = blockIdx.y;
+  if (kskip && kskip[b]) return;
+  stage_c<TQ>(C + (size_t)b * p * q, csh, p, q);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const c64* Sb = S + ((size_t)b * skstride + scol0) * n;
+  c64* Yb = Y + (size_t)b * ykstride * n;
+  const int ucol = U ? 0 : 1;  // with U (p, q, q1 multiples of 4) the lane's lk is in boff
+  const size_t nblk = (n + 15) / 16;
+  for (size_t rb = (size_t)blockIdx.x * 4 + wave; rb < nblk; rb += (size_t)gridDim.x * 4) {
+    const size_t row = rb * 16 + li;
+    const bool rok = row < n;
+    const size_t rowc = rok ? row : n - 1;
+    const uint32_t boff = (uint32_t)(((size_t)lk * n + rowc) * sizeof(c64));
     d4 p1[TQ], p2[TQ], p3[TQ];
-#pragma unroll
-    for (int t = 0; t < TQ; ++t) {
-      p1[t] = d4{0, 0, 0, 0};
-      p2[t] = d4{0, 0, 0, 0};
-      p3[t] = d4{0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int kb = 0; kb < PK; ++kb) {
-      const int ca = kb * 4 + lk;
-      // A operand lane (i = li -> output column, k = lk -> input column): C[k][i];
-      // B operand lane (k = lk -> input column, j = li -> row): S[row][k]
-      c64 cv[TQ];
-#pragma unroll
-      for (int t = 0; t < TQ; ++t) cv[t] = csh[ca * QP + t * 16 + li];
-      const double ssum = sv[kb].re + sv[kb].im;
-      // consecutive MFMAs go to different accumulators
-#pragma unroll
-      for (int t = 0; t < TQ; ++t) p1[t] = mfma(cv[t].re, sv[kb].re, p1[t]);
-#pragma unroll
-      for (int t = 0; t < TQ; ++t) p2[t] = mfma(cv[t].im, sv[kb].im, p2[t]);
-#pragma unroll
-      for (int t = 0; t < TQ; ++t) p3[t] = mfma(cv[t].re + cv[t].im, ssum, p3[t]);
-    }
-    // output lane holds D[lk + 4r][li]: output column t*16 + lk + 4r, row rb*16 + li
+    rows_times_c<TQ, U>(Sb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
 #pragma unroll
     for (int t = 0; t < TQ; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int j = t * 16 + lk + 4 * r;
-        if (rok && j < q) {
-          const int col = (j < q1) ? ycol0 + j : ycol1 + (j - q1);
-          Yb[(size_t)col * n + row] = mk(p1[t][r] - p2[t][r], p3[t][r] - p1[t][r] - p2[t][r]);
-        }
+        const int j = t * 16 + lk + 4 * r, ju = t * 16 + 4 * r + lk * ucol;
+        if (rok && j < q)
+          elem<U>(Yb, (ju < q1) ? ycol0 + ju : ycol1 + (ju - q1), n, boff, row) =
+              mk(p1[t][r] - p2[t][r], p3[t][r] - p1[t][r] - p2[t][r]);
       }
+  }
+}
+
+// The two block updates of a Rayleigh-Ritz step in one pass, with the next residuals:
+// [X P] <- S [C1 Cp] and [AX AP] <- AS [C1 Cp] in place (S = [X W P] and AS as kstride-spaced
+// groups of 3mb columns; X to columns 0..mb-1, P to 2mb..3mb-1), then from the new X and AX of
+// the same 16 rows, still in registers, R_j = AX_j - theta_j X_j (eq (4.3)) into the contiguous
+// R ([b*mb + j][n]) and per-workgroup partial sums of |r_j|^2 and |x_j|^2 (part, the layout of
+// k_resid_reduce).  X column j = 4s + lk is slot s < XS of lane (lk, li): tile s/4, entry s%4;
+// between the two products each lane parks its new X values in a private LDS slot (in registers
+// they would push the kernel to one wave per SIMD).
+template <int XS, bool U>
+__global__ __launch_bounds__(256) void k_update_res(c64* S, c64* AS, const c64* __restrict__ C, size_t n, int mb,
+                                                    int kstride, const double* __restrict__ theta,
+                                                    c64* __restrict__ R, double* __restrict__ part,
+                                                    const int* __restrict__ kskip) {
+  constexpr int TQ = (XS + 1) / 2;  // 2mb output columns in tiles of 16
+  extern __shared__ c64 csh[];  // C_b (RR_NMAX x TQ*16), then the parked X values [4][XS][64]
+  __shared__ double th[RR_NMAX];
+  __shared__ double red[4][XS][4][2];
+  c64* xpark = csh + RR_NMAX * TQ * 16;
+  const int b = blockIdx.y;
+  if (kskip && kskip[b]) return;
+  const int p = 3 * mb, q = 2 * mb;
+  stage_c<TQ>(C + (size_t)b * p * q, csh, p, q);
+  for (int j = threadIdx.x; j < mb; j += blockDim.x) th[j] = theta[b * mb + j];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  c64* Sb = S + (size_t)b * kstride * n;
+  c64* ASb = AS + (size_t)b * kstride * n;
+  c64* Rb = R + (size_t)b * mb * n;
+  // with U, output column t*16 + lk + 4r is column t*16 + 4r of the lane's base (lk*n + row),
+  // and which of X / P it belongs to does not depend on lk (mb is a multiple of 4)
+  const int ucol = U ? 0 : 1;
+  double rr[XS], xx[XS];
+#pragma unroll
+  for (int s = 0; s < XS; ++s) rr[s] = xx[s] = 0.0;
+  const size_t nblk = (n + 15) / 16;
+  for (size_t rb = (size_t)blockIdx.x * 4 + wave; rb < nblk; rb += (size_t)gridDim.x * 4) {
+    const size_t row = rb * 16 + li;
+    const bool rok = row < n;
+    const size_t rowc = rok ? row : n - 1;
+    const uint32_t boff = (uint32_t)(((size_t)lk * n + rowc) * sizeof(c64));
+    c64* xk = xpark + (size_t)wave * XS * 64 + lane;  // slot s at xk[s * 64]
+    {
+      d4 p1[TQ], p2[TQ], p3[TQ];
+      rows_times_c<TQ, U>(Sb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
+#pragma unroll
+      for (int t = 0; t < TQ; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = t * 16 + lk + 4 * r, ju = t * 16 + 4 * r + lk * ucol;
+          const c64 v = mk(p1[t][r] - p2[t][r], p3[t][r] - p1[t][r] - p2[t][r]);
+          if (t * 4 + r < XS) xk[(t * 4 + r) * 64] = v;
+          if (rok && j < q) elem<U>(Sb, ju < mb ? ju : mb + ju, n, boff, row) = v;
+        }
+    }
+    {
+      d4 p1[TQ], p2[TQ], p3[TQ];
+      rows_times_c<TQ, U>(ASb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
+#pragma unroll
+      for (int t = 0; t < TQ; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = t * 16 + lk + 4 * r, ju = t * 16 + 4 * r + lk * ucol;
+          const c64 v = mk(p1[t][r] - p2[t][r], p3[t][r] - p1[t][r] - p2[t][r]);
+          if (rok && j < q) elem<U>(ASb, ju < mb ? ju : mb + ju, n, boff, row) = v;
+          if (t * 4 + r < XS) {
+            const int s = t * 4 + r;
+            if (rok && j < mb) {
+              const c64 x = xk[s * 64];
+              const c64 rv = v - th[j] * x;
+              elem<U>(Rb, ju, n, boff, row) = rv;
+              rr[s] += abs2(rv);
+              xx[s] += abs2(x);
+            }
+          }
+        }
+    }
+  }
+  // sums over the 16 rows of a lane group (li), then over the waves, in a fixed order
+#pragma unroll
+  for (int s = 0; s < XS; ++s)
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      rr[s] += __shfl_xor(rr[s], o, 16);
+      xx[s] += __shfl_xor(xx[s], o, 16);
+    }
+  if (li == 0)
+#pragma unroll
+    for (int s = 0; s < XS; ++s) {
+      red[wave][s][lk][0] = rr[s];
+      red[wave][s][lk][1] = xx[s];
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < 2 * mb) {
+    const int j = threadIdx.x >> 1, c = threadIdx.x & 1;
+    const double v = red[0][j >> 2][j & 3][c] + red[1][j >> 2][j & 3][c] + red[2][j >> 2][j & 3][c] +
+                     red[3][j >> 2][j & 3][c];
+    part[(((size_t)b * mb + j) * gridDim.x + blockIdx.x) * 2 + c] = v;
   }
 }
 
@@ -613,24 +748,91 @@ int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, De
 
 int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, int q, int q1, int ycol0,
            int ycol1, const c64* C, size_t n, int nb, const int* kskip, hipStream_t s) {
-  const size_t nblk = (n + 15) / 16;
-  const unsigned gx = (unsigned)std::max<size_t>(1, std::min<size_t>((nblk + 3) / 4, 4096 / std::max(nb, 1) + 1));
-  dim3 grid(gx, nb);
+  dim3 grid(update_grid_x(n, nb), nb);
   const size_t shm = (size_t)RR_NMAX * ((q + 15) / 16 * 16) * sizeof(c64);
   if (p > RR_NMAX) {
     set_error("update: too many input columns");
     return KC_ERR_INVALID_ARG;
   }
+  const bool u = p % 4 == 0 && q % 4 == 0 && q1 % 4 == 0 && 4 * n * sizeof(c64) < (size_t(1) << 32);
+#define KC_UPD(T)                                                                                       \
+  if (u)                                                                                                \
+    k_update<T, true><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, \
+                                             kskip);                                                    \
+  else                                                                                                  \
+    k_update<T, false><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, \
+                                              kskip)
   if (q <= 16) {
-    k_update<1><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, kskip);
+    KC_UPD(1);
   } else if (q <= 32) {
-    k_update<2><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, kskip);
+    KC_UPD(2);
   } else if (q <= 48) {
-    k_update<3><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, kskip);
+    KC_UPD(3);
   } else {
     set_error("update: too many output columns");
     return KC_ERR_INVALID_ARG;
   }
+#undef KC_UPD
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+unsigned update_grid_x(size_t n, int nb) {
+  const size_t nblk = (n + 15) / 16;
+  return (unsigned)std::max<size_t>(1, std::min<size_t>((nblk + 3) / 4, 4096 / std::max(nb, 1) + 1));
+}
+
+// dynamic LDS of k_update_res: C_b and the parked X values
+static size_t update_res_lds(int mb) {
+  const int xs = (mb + 3) / 4;
+  return ((size_t)RR_NMAX * (((xs + 1) / 2) * 16) + (size_t)4 * xs * 64) * sizeof(c64);
+}
+
+int update_res_prepare() {
+  static bool done = false;
+  if (done) return KC_OK;
+  const void* k[12] = {(const void*)k_update_res<1, false>, (const void*)k_update_res<2, false>,
+                       (const void*)k_update_res<3, false>, (const void*)k_update_res<4, false>,
+                       (const void*)k_update_res<5, false>, (const void*)k_update_res<6, false>,
+                       (const void*)k_update_res<1, true>,  (const void*)k_update_res<2, true>,
+                       (const void*)k_update_res<3, true>,  (const void*)k_update_res<4, true>,
+                       (const void*)k_update_res<5, true>,  (const void*)k_update_res<6, true>};
+  for (int i = 0; i < 12; ++i)
+    KC_HIP(hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)update_res_lds(4 * (i % 6 + 1))));
+  done = true;
+  return KC_OK;
+}
+
+int update_res(c64* S, c64* AS, int kstride, int mb, const c64* C, size_t n, int nb, const double* theta, c64* R,
+               double* part, double* res, double* xnorm2, const int* kskip, hipStream_t s) {
+  if (mb < 1 || 3 * mb > RR_NMAX) {
+    set_error("update_res: block size out of range");
+    return KC_ERR_INVALID_ARG;
+  }
+  const unsigned gx = update_grid_x(n, nb);
+  dim3 grid(gx, nb);
+  const int xs = (mb + 3) / 4;
+  const size_t shm = update_res_lds(mb);
+  // uniform column offsets need whole groups of 4 columns and 32-bit lane byte offsets
+  const bool u = (mb % 4 == 0) && 4 * n * sizeof(c64) < (size_t(1) << 32);
+#define KC_UPDRES(X)                                                                          \
+  if (u)                                                                                      \
+    k_update_res<X, true><<<grid, 256, shm, s>>>(S, AS, C, n, mb, kstride, theta, R, part, kskip); \
+  else                                                                                        \
+    k_update_res<X, false><<<grid, 256, shm, s>>>(S, AS, C, n, mb, kstride, theta, R, part, kskip)
+  switch (xs) {
+    case 1: KC_UPDRES(1); break;
+    case 2: KC_UPDRES(2); break;
+    case 3: KC_UPDRES(3); break;
+    case 4: KC_UPDRES(4); break;
+    case 5: KC_UPDRES(5); break;
+    default: KC_UPDRES(6); break;
+  }
+#undef KC_UPDRES
+  KC_LAUNCHED();
+  const int nv = nb * mb;
+  k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part, (int)gx, nv, res, xnorm2, nullptr);
   KC_LAUNCHED();
   return KC_OK;
 }

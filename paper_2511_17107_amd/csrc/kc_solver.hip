@@ -29,7 +29,7 @@ namespace kc {
 
 struct SolverWork {
   DevBuf S, AS;
-  DevBuf part_gram, part_res;
+  DevBuf part_gram, part_res, part_upd;
   DevBuf GA, GB, Cu, Lsave, GApp;
   DevBuf theta, res, xn2;
   DevBuf R, tmask;  // residuals (input of T_E) and the columns that get T_E R
@@ -75,8 +75,9 @@ int apply_cols(Batch& B, int col0, const int* active, int prec) {
 }
 
 // Gram matrices (all blocks, or with `implicit` only the W columns, the X/P blocks coming from
-// the previous step), small Rayleigh-Ritz, update
-int rayleigh_ritz(Batch& B, bool implicit = false) {
+// the previous step), small Rayleigh-Ritz, update; with `fused` the update pass also forms the
+// next residuals R (for T_E) and their norms
+int rayleigh_ritz(Batch& B, bool implicit = false, bool fused = false) {
   if (implicit) {
     KC_TRY(gramw(B.S, B.AS, B.nc, B.mb, B.n, B.nb, B.w->part_gram, B.w->GA.as<c64>(), B.w->GB.as<c64>(),
                  B.w->theta.as<double>(), B.w->GApp.as<c64>(), B.kskip, B.s));
@@ -88,6 +89,10 @@ int rayleigh_ritz(Batch& B, bool implicit = false) {
                   B.w->theta.as<double>(), B.w->Cu.as<c64>(), B.pvalid, B.w->Lsave.as<c64>(), B.flags, B.kskip,
                   B.w->GApp.as<c64>(), B.s));
   // [X | P] <- S Cu, [AX | AP] <- AS Cu
+  if (fused)
+    return update_res(B.S, B.AS, B.nc, B.mb, B.w->Cu.as<c64>(), B.n, B.nb, B.w->theta.as<double>(),
+                      B.w->R.as<c64>(), B.w->part_upd.as<double>(), B.w->res.as<double>(), B.w->xn2.as<double>(),
+                      B.kskip, B.s);
   KC_TRY(update(B.S, B.nc, 0, B.nc, B.S, B.nc, 2 * B.mb, B.mb, 0, 2 * B.mb, B.w->Cu.as<c64>(), B.n, B.nb,
                 B.kskip, B.s));
   KC_TRY(update(B.AS, B.nc, 0, B.nc, B.AS, B.nc, 2 * B.mb, B.mb, 0, 2 * B.mb, B.w->Cu.as<c64>(), B.n, B.nb,
@@ -166,6 +171,13 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
     KC_TRY(w->R.ensure((size_t)nb * mb * colbytes));
     KC_TRY(w->tmask.ensure((size_t)nb * mb * sizeof(int)));
   }
+  // with T_E on every k-point the update pass forms the next residuals itself (the learned
+  // field falls back to K_P^{-1} per k-point, which needs the separate residual pass)
+  const bool fused = B.pc == KC_PRECOND_TRANSVERSE;
+  if (fused) {
+    KC_TRY(w->part_upd.ensure((size_t)nb * mb * update_grid_x(n, nb) * 2 * sizeof(double)));
+    KC_TRY(update_res_prepare());
+  }
   KC_TRY(w->ints.ensure((size_t)(4 * nb * mb + 4 * nb) * sizeof(int)));
   // operator work buffers at their largest (FP64) size up front: captured iterations keep
   // their pointers, so no buffer may move after a capture
@@ -233,8 +245,8 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   auto body = [&](int pr, bool implicit) -> int {
     if (tp) KC_TRY(precond_tp(B));
     KC_TRY(apply_cols(B, mb, B.wmask, pr));
-    KC_TRY(rayleigh_ritz(B, implicit));
-    return residuals(B, tp);
+    KC_TRY(rayleigh_ritz(B, implicit, fused));
+    return fused ? KC_OK : residuals(B, tp);
   };
   hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
   struct GraphGuard {

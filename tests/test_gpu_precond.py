@@ -125,3 +125,24 @@ def test_solve_sphere32_mixed_transverse():
     for i, c in enumerate(g["cases"]):
         ref = np.array(c["eigenvalues"])
         assert np.max(np.abs(eig[i] - ref) / ref) <= 1e-6, (c["k"], eig[i], ref)
+
+
+@pytest.mark.parametrize("m,guard", [(2, 1), (3, 1), (4, 1), (8, 0), (10, 3), (10, 6), (10, 11)])
+@pytest.mark.parametrize("pc", [kc.KC_PRECOND_TRANSVERSE, kc.KC_PRECOND_DIAG])
+def test_solve_block_sizes(m, guard, pc):
+    """Block sizes mb = m + guard from 3 to 21: the update passes take whole groups of four
+    columns when mb is a multiple of 4 and clamp per lane otherwise, and the fused update +
+    residual pass (T_E) keeps 1 to 6 new X values per lane; every variant against the oracle's
+    eigenvalues."""
+    g = _golden("sphere16_aniso")
+    wl = W.sphere_anisotropic(N=16, nk=9, m=10)
+    cases = [c for c in g["cases"] if c["scheme"] == "crossdof"][:3]
+    kpts = np.array([c["k"] for c in cases])
+    op = kc.Op(16, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(kpts)
+    note("solve m", m, "guard", guard, "precond", pc)
+    eig, res, its, st = op.solve(m, tol=1e-8, batch_k=len(kpts), guard=guard, precond=pc)
+    assert st == 0 and res.max() <= 1e-8
+    for i, c in enumerate(cases):
+        ref = np.array(c["eigenvalues"][:m])
+        assert np.max(np.abs(eig[i] - ref) / ref) <= 1e-6, (m, guard, c["k"], eig[i], ref)
