@@ -25,10 +25,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of a pass, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0),
-# the factors read off a plain 1 GiB device copy in the same run
-# (profiles/matvec_woodpile128_fp32_16vec.md); keyed by pass, N, vectors, precision.
-MEASURED_TRAFFIC = {("X2", 128, 16, "fp32"): 4.030e9}
+# HBM bytes per launch, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the factors
+# read off a plain 1 GiB device copy in the same run: operator passes keyed by pass, N, vectors,
+# precision (profiles/matvec_woodpile128_fp32_16vec.md), the fused update by N, k-points and
+# block width.
+MEASURED_TRAFFIC = {("X2", 128, 16, "fp32"): 4.030e9,
+                    # fused update + residuals at 128^3, 10 k-points, 20-column blocks
+                    # (profiles/update_woodpile128_10k_20col.md)
+                    ("update", 128, 10, 20): 221.51e9}
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -51,6 +56,9 @@ def parse():
     ap.add_argument("--matvec-only", action="store_true",
                     help="only the operator application on one block (and a plain device copy of known "
                          "size, the reference for hardware byte counters); for profiling")
+    ap.add_argument("--update-only", action="store_true",
+                    help="only the fused block update (kc_block_update) at the solve's batch shape, three "
+                         "launches, and the 1 GiB device copy; for profiling")
     ap.add_argument("--verbose", type=int, default=0)
     return ap.parse_args()
 
@@ -116,6 +124,74 @@ def matvec_only(a, op, prec, dev):
                       "checksum": float(y.abs().sum()) + float(dst[0])}), flush=True)
 
 
+def update_block(a, dev):
+    """Seeded inputs of the fused update at the solve's shape: blocks S, AS of kpb k-points x 3mb
+    columns x 3N^3 rows, coefficients scaled so that repeated in-place updates keep the
+    magnitudes, Ritz values in the woodpile's range."""
+    import torch
+
+    import workloads as W
+
+    mb, nb, n = a.m + a.guard, a.kpb, 3 * a.N ** 3
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    S = torch.randn((nb, 3 * mb, n), dtype=torch.complex128, device=dev, generator=g)
+    AS = torch.randn((nb, 3 * mb, n), dtype=torch.complex128, device=dev, generator=g)
+    C = torch.from_numpy(W.random_complex(8, (nb, 3 * mb, 2 * mb)) / np.sqrt(6 * mb)).to(dev)
+    theta = torch.from_numpy(np.random.default_rng(9).uniform(0.05, 0.5, (nb, mb))).to(dev)
+    return S, AS, C, theta
+
+
+def update_roofline(a, dev, reps=5):
+    """The fused update + residual pass (the largest share of a solve step) timed live with HIP
+    events on the stream it runs on, at the solve's batch shape."""
+    import torch
+
+    import paper_2511_17107_amd as kc
+
+    mb, nb, n = a.m + a.guard, a.kpb, 3 * a.N ** 3
+    S, AS, C, theta = update_block(a, dev)
+    R = torch.empty((nb, mb, n), dtype=torch.complex128, device=dev)
+    res = torch.empty((nb, mb), dtype=torch.float64, device=dev)
+    xn2 = torch.empty_like(res)
+    work = torch.empty(kc.block_work_bytes(nb, n, 3 * mb), dtype=torch.uint8, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * (reps + 1))]
+    for r in range(reps + 1):
+        ev[2 * r].record()
+        kc.block_update(S, AS, C, theta, R, res, xn2, work)
+        ev[2 * r + 1].record()
+    torch.cuda.synchronize()
+    ms = sum(ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(1, reps + 1)) / reps
+    alg_bytes = nb * n * 11 * mb * 16          # read S, AS (3mb each); write X, P, AX, AP, R
+    alg_flops = nb * n * 2 * (3 * mb) * (2 * mb) * 8  # two 3mb x 2mb complex products per row
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    del S, AS, R, work
+    torch.cuda.empty_cache()
+    return {"bound": "hbm", "kernel": "fused block update + residuals (k_update_res)",
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "traffic": MEASURED_TRAFFIC.get(("update", a.N, nb, mb)), "alg_bytes": alg_bytes,
+            "ms_per_launch": ms, "alg_tflops": alg_flops / (ms * 1e-3) / 1e12,
+            "mfma_frac": alg_flops / (ms * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS}
+
+
+def update_only(a, dev):
+    """Three fused updates at the solve's shape, then three copies of a 1 GiB buffer."""
+    import torch
+
+    import paper_2511_17107_amd as kc
+
+    S, AS, C, theta = update_block(a, dev)
+    for r in range(3):
+        R, res, xn2 = kc.block_update(S, AS, C, theta)
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for r in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"update_kpoints": a.kpb, "mb": a.m + a.guard, "N": a.N,
+                      "copy_bytes_each_way": src.numel() * 8, "res0": float(res[0, 0])}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -144,6 +220,9 @@ def main():
 
     if a.matvec_only:
         matvec_only(a, op, prec, dev)
+        return
+    if a.update_only:
+        update_only(a, dev)
         return
 
     def run_step(step):
@@ -184,7 +263,13 @@ def main():
     dom = int(np.argmax(ms))
     mv_time = float(ms.sum())
     alg_mv = (16 * 3 * a.N ** 3 * 2 + 4 * a.N ** 3) * a.m  # read x, write y, read ids
+    tiles = {"fp32": op.tile_widths(kc.KC_PREC_FP32).tolist(), "fp64": op.tile_widths(kc.KC_PREC_FP64).tolist()}
     del x
+    # the solver's block workspace (~180 GB at the default batch) goes with the handle, which
+    # makes room for the update measurement's own blocks
+    del op
+    torch.cuda.empty_cache()
+    upd = update_roofline(a, dev)
 
     out = {
         "metric": "k-points/s to rel. residual 1e-8 at n=128, 16 bands; matvec GB/s vs HBM peak",
@@ -208,17 +293,17 @@ def main():
         "iterations": iters,
         "matvecs_fp64": mv64,
         "matvecs_fp32": mv32,
-        "roofline": {"bound": "hbm", "kernel": "matvec pass " + names[dom],
-                     "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs[dom] / HBM_PEAK_GBS,
-                     "traffic": MEASURED_TRAFFIC.get((names[dom], a.N, a.m, a.prec)),
-                     "alg_bytes": pbytes[dom]},
-        "tile_widths": {"fp32": op.tile_widths(kc.KC_PREC_FP32).tolist(),
-                        "fp64": op.tile_widths(kc.KC_PREC_FP64).tolist()},
+        "roofline": upd,
+        "tile_widths": tiles,
         "matvec": {"passes": names, "ms": [round(float(t), 4) for t in ms],
                    "alg_GBps": [round(g, 1) for g in gbs], "nvec": a.m,
                    "ms_per_band": mv_time / a.m,
-                   "effective_GBps": alg_mv / (mv_time * 1e-3) / 1e9},
+                   "effective_GBps": alg_mv / (mv_time * 1e-3) / 1e9,
+                   "roofline": {"bound": "hbm", "kernel": "matvec pass " + names[dom],
+                                "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": gbs[dom] / HBM_PEAK_GBS,
+                                "traffic": MEASURED_TRAFFIC.get((names[dom], a.N, a.m, a.prec)),
+                                "alg_bytes": pbytes[dom]}},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.kpoints)

@@ -127,6 +127,41 @@ int kc_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void
                void* stream);
 
 /*
+ * Block kernels of the LOBPCG iteration (Section 4, the custom block solver; run by kc_solve,
+ * exposed for testing and measurement).  A block holds, for each of nb k-points b, nc columns
+ * of n complex128 entries, column j of k-point b at offset (b * nc + j) * n (entries).
+ *
+ * kc_block_work_bytes: device workspace (bytes) that kc_block_gram and kc_block_update need
+ * for nb k-points, n rows and at most nc columns (0 for arguments out of range).
+ */
+size_t kc_block_work_bytes(int nb, size_t n, int nc);
+
+/*
+ * Gram matrices of the search space: GA_b = S_b^H AS_b and GB_b = S_b^H S_b, each nc x nc,
+ * row-major, G_b[i][j] = sum_r conj(S_b[r][i]) AS_b[r][j] (resp. S_b[r][j]).  Both are taken
+ * to be Hermitian: AS_b must be the image A S_b of S_b under a Hermitian A (as in LOBPCG);
+ * the 16 x 16 tiles on and above the diagonal are summed, the others are their conjugates.
+ *   S, AS : device complex128, nb blocks of nc columns (1 <= nc <= 64)
+ *   GA, GB: device complex128 [nb][nc][nc]
+ *   work  : device scratch of at least kc_block_work_bytes(nb, n, nc) bytes
+ * The partial sums over row chunks are added in a fixed order (results are reproducible).
+ */
+int kc_block_gram(int nb, size_t n, int nc, const void* S, const void* AS, void* GA, void* GB, void* work,
+                  size_t work_bytes, void* stream);
+
+/*
+ * One Rayleigh-Ritz update with the next residuals (eq (4.3)), in place.  Per k-point b the
+ * block holds 3mb columns S_b = [X W P] and AS_b = [AX AW AP] (1 <= mb <= 21), and
+ * C_b = [C1 | Cp] is 3mb x 2mb (row-major, complex128 [nb][3mb][2mb]):
+ *   X <- S_b C1, P <- S_b Cp, AX <- AS_b C1, AP <- AS_b Cp   (W and AW are left as they are)
+ *   R_j = AX_j - theta_j X_j          (new X, AX; R device complex128 [nb * mb][n])
+ *   res_j = |R_j| / |X_j| (0 where X_j = 0), xnorm2_j = |X_j|^2    (device double [nb * mb])
+ * theta: device double [nb * mb].  S, AS and R must not overlap.  work as for kc_block_gram.
+ */
+int kc_block_update(int nb, size_t n, int mb, void* S, void* AS, const void* C, const double* theta, void* R,
+                    double* res, double* xnorm2, void* work, size_t work_bytes, void* stream);
+
+/*
  * Unnormalised 3D DFT of nvec scalar grids along x, y and z:
  *   out[q] = sum_j in[j] exp(sign 2 pi i (j . q) / N), sign = +1 or -1.
  * prec KC_PREC_FP64: in/out complex128 [nvec][N^3]; KC_PREC_FP32: complex64.  in == out is

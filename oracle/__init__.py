@@ -25,6 +25,9 @@ eigs      smallest strictly positive eigenvalues of the compensated operator
           k = 0 constant-field null space removed (Prop 2.5).
 nn        direct-summation 3D convolution with circular padding and its
           gradients (learned preconditioner), in FP64.
+block     the dense block steps of the LOBPCG iteration (Section 4): Gram matrices of
+          the search space and the Rayleigh-Ritz update with the residuals of
+          eq (4.3), from their definitions.
 
 Parity unpinned: none of the functions above is unpinned; the pins are listed
 in the test modules tests/test_oracle_*.py.

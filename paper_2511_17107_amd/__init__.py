@@ -17,6 +17,9 @@ from ._binding import (  # noqa: F401
     KC_PRECOND_TRANSVERSE,
     KcError,
     Net,
+    block_gram,
+    block_update,
+    block_work_bytes,
     Op,
     kc_create,
     kc_fft3d,

@@ -85,6 +85,10 @@ def lib():
         L.kc_net_features.argtypes = [vp, i32, i32, vp, vp]
         L.kc_net_efield.argtypes = [vp, i32, i32, vp, vp]
         L.kc_precond_learned.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
+        L.kc_block_work_bytes.argtypes = [i32, ctypes.c_size_t, i32]
+        L.kc_block_work_bytes.restype = ctypes.c_size_t
+        L.kc_block_gram.argtypes = [i32, ctypes.c_size_t, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.kc_block_update.argtypes = [i32, ctypes.c_size_t, i32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.kc_status_string.argtypes = [i32]
         L.kc_status_string.restype = ctypes.c_char_p
         L.kc_last_error.argtypes = []
@@ -142,6 +146,74 @@ def kc_fft3d(x, sign: int, prec: int = KC_PREC_FP64, out=None, stream=None):
     _check(lib().kc_fft3d(N, nvec, int(sign), int(prec), _dev_ptr(x, dt, "x"), _dev_ptr(out, dt, "out"),
                           _stream(stream)), "kc_fft3d")
     return out
+
+
+def block_work_bytes(nb: int, n: int, nc: int) -> int:
+    """Device workspace bytes of kc_block_gram / kc_block_update."""
+    return int(lib().kc_block_work_bytes(int(nb), int(n), int(nc)))
+
+
+def _block_shape(S, what: str):
+    if S.dim() != 3:
+        raise ValueError("%s must have shape (nb, nc, n)" % what)
+    return int(S.shape[0]), int(S.shape[1]), int(S.shape[2])
+
+
+def _work(nb, n, nc, work):
+    import torch
+
+    need = block_work_bytes(nb, n, nc)
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+    elif work.numel() < need:
+        raise ValueError("work holds %d bytes, %d needed" % (work.numel(), need))
+    return work
+
+
+def block_gram(S, AS, GA=None, GB=None, work=None, stream=None):
+    """GA_b = S_b^H AS_b, GB_b = S_b^H S_b for blocks of shape (nb, nc, n), complex128."""
+    import torch
+
+    nb, nc, n = _block_shape(S, "S")
+    if tuple(AS.shape) != (nb, nc, n):
+        raise ValueError("AS must have the shape of S")
+    if GA is None:
+        GA = torch.empty((nb, nc, nc), dtype=torch.complex128, device=S.device)
+    if GB is None:
+        GB = torch.empty((nb, nc, nc), dtype=torch.complex128, device=S.device)
+    work = _work(nb, n, nc, work)
+    _check(lib().kc_block_gram(nb, n, nc, _dev_ptr(S, "torch.complex128", "S"),
+                               _dev_ptr(AS, "torch.complex128", "AS"), _dev_ptr(GA, "torch.complex128", "GA"),
+                               _dev_ptr(GB, "torch.complex128", "GB"), ctypes.c_void_p(work.data_ptr()),
+                               work.numel(), _stream(stream)), "kc_block_gram")
+    return GA, GB
+
+
+def block_update(S, AS, C, theta, R=None, res=None, xnorm2=None, work=None, stream=None):
+    """In place: [X P] <- S [C1 Cp], [AX AP] <- AS [C1 Cp] for blocks (nb, 3mb, n) and C (nb, 3mb,
+    2mb); returns R (nb, mb, n) = AX - theta X, res = |R_j|/|X_j| and |X_j|^2 (nb, mb)."""
+    import torch
+
+    nb, nc, n = _block_shape(S, "S")
+    if nc % 3 != 0:
+        raise ValueError("S must hold 3mb columns per k-point")
+    mb = nc // 3
+    if tuple(AS.shape) != (nb, nc, n) or tuple(C.shape) != (nb, nc, 2 * mb) or tuple(theta.shape) != (nb, mb):
+        raise ValueError("shapes: AS (nb, 3mb, n), C (nb, 3mb, 2mb), theta (nb, mb)")
+    if R is None:
+        R = torch.empty((nb, mb, n), dtype=torch.complex128, device=S.device)
+    if res is None:
+        res = torch.empty((nb, mb), dtype=torch.float64, device=S.device)
+    if xnorm2 is None:
+        xnorm2 = torch.empty((nb, mb), dtype=torch.float64, device=S.device)
+    work = _work(nb, n, nc, work)
+    _check(lib().kc_block_update(nb, n, mb, _dev_ptr(S, "torch.complex128", "S"),
+                                 _dev_ptr(AS, "torch.complex128", "AS"), _dev_ptr(C, "torch.complex128", "C"),
+                                 _dev_ptr(theta, "torch.float64", "theta"), _dev_ptr(R, "torch.complex128", "R"),
+                                 _dev_ptr(res, "torch.float64", "res"), _dev_ptr(xnorm2, "torch.float64", "xnorm2"),
+                                 ctypes.c_void_p(work.data_ptr()), work.numel(), _stream(stream)),
+           "kc_block_update")
+    return R, res, xnorm2
 
 
 class Op:

@@ -9,6 +9,10 @@ namespace kc {
 // k-point b start at (b * kstride) * n.  `part` is scratch.
 int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
           const int* kskip, hipStream_t s);
+// The same with caller-provided partial sums (gram2_part_bytes(nc, n, nb) bytes).
+int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, c64* part, c64* GA, c64* GB,
+          const int* kskip, hipStream_t s);
+size_t gram2_part_bytes(int nc, size_t n, int nb);
 
 // The W columns of the Gram matrices of S = [X W P] (kstride-spaced blocks of 3mb columns):
 // GB(:, W) = S^H W, GA(:, W) = S^H AW, with the X/P blocks filled from the previous

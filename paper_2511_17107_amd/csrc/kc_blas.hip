@@ -697,7 +697,22 @@ __global__ void k_random_block(c64* S, size_t n, int kstride, int col0, int ncol
 // ------------------------------------------------------------------------------------
 // host launchers
 // ------------------------------------------------------------------------------------
-int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
+// rows per workgroup of the Gram kernels (a multiple of G2_ROWS, about 2048 workgroups in all)
+static size_t gram_rows(size_t n, int nb) {
+  const size_t target_wg = 2048;
+  const size_t per_k = std::max<size_t>(1, target_wg / (size_t)nb);
+  size_t rows = (n + per_k - 1) / per_k;
+  rows = std::max<size_t>(rows, 64);
+  return (rows + G2_ROWS - 1) / G2_ROWS * G2_ROWS;
+}
+
+size_t gram2_part_bytes(int nc, size_t n, int nb) {
+  const int T = (nc + 15) / 16;
+  const size_t rows = gram_rows(n, nb);
+  return (size_t)nb * ((n + rows - 1) / rows) * (T * (T + 1)) * 256 * sizeof(c64);
+}
+
+int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, c64* part, c64* GA, c64* GB,
           const int* kskip, hipStream_t s) {
   const int T = (nc + 15) / 16;
   const int ntile = T * (T + 1);
@@ -705,20 +720,21 @@ int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, De
     set_error("gram2: too many columns");
     return KC_ERR_INVALID_ARG;
   }
-  const size_t target_wg = 2048;
-  const size_t per_k = std::max<size_t>(1, target_wg / (size_t)nb);
-  size_t rows = (n + per_k - 1) / per_k;
-  rows = std::max<size_t>(rows, 64);
-  rows = (rows + G2_ROWS - 1) / G2_ROWS * G2_ROWS;
+  const size_t rows = gram_rows(n, nb);
   const int nchunk = (int)((n + rows - 1) / rows);
-  KC_TRY(part.ensure((size_t)nb * nchunk * ntile * 256 * sizeof(c64)));
   dim3 grid(nchunk, nb);
-  k_gram2<<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part.as<c64>(), kskip);
+  k_gram2<<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip);
   KC_LAUNCHED();
   dim3 g2(1, ntile, nb);
-  k_gram2_reduce<<<g2, 256, 0, s>>>(part.as<c64>(), nchunk, ntile, nc, GA, GB, kskip);
+  k_gram2_reduce<<<g2, 256, 0, s>>>(part, nchunk, ntile, nc, GA, GB, kskip);
   KC_LAUNCHED();
   return KC_OK;
+}
+
+int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
+          const int* kskip, hipStream_t s) {
+  KC_TRY(part.ensure(gram2_part_bytes(nc, n, nb)));
+  return gram2(S, AS, kstride, nc, n, nb, part.as<c64>(), GA, GB, kskip, s);
 }
 
 int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, DevBuf& part, c64* GA, c64* GB,
@@ -730,11 +746,7 @@ int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, De
     set_error("gramw: too many columns");
     return KC_ERR_INVALID_ARG;
   }
-  const size_t target_wg = 2048;
-  const size_t per_k = std::max<size_t>(1, target_wg / (size_t)nb);
-  size_t rows = (n + per_k - 1) / per_k;
-  rows = std::max<size_t>(rows, 64);
-  rows = (rows + G2_ROWS - 1) / G2_ROWS * G2_ROWS;
+  const size_t rows = gram_rows(n, nb);
   const int nchunk = (int)((n + rows - 1) / rows);
   KC_TRY(part.ensure((size_t)nb * nchunk * ntile * 256 * sizeof(c64)));
   dim3 grid(nchunk, nb);

@@ -1,5 +1,6 @@
 // C ABI entry points (include/kcpc.h): argument checking, set-up of the per-k symbol tables,
 // the inverse-permittivity table and the twiddles, and dispatch to the kernels.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -7,6 +8,7 @@
 #include <mutex>
 #include <string>
 
+#include "kc_blas.h"
 #include "kc_nn.h"
 
 namespace kc {
@@ -516,6 +518,43 @@ int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void*
   vm.vpk = vecs_per_k;
   vm.kstride = vecs_per_k;
   return apply_tp(op, ik0, nvec, vm, vm, (const c64*)r, (c64*)z, op->efield_k.as<float>(), 1, prec, s);
+}
+
+size_t kc_block_work_bytes(int nb, size_t n, int nc) {
+  if (nb < 1 || n < 1 || nc < 1 || nc > RR_NMAX) return 0;
+  const size_t upd = (size_t)nb * (RR_NMAX / 3) * update_grid_x(n, nb) * 2 * sizeof(double);
+  return std::max(gram2_part_bytes(nc, n, nb), upd);
+}
+
+static bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
+  return (const char*)a + na <= (const char*)b || (const char*)b + nb <= (const char*)a;
+}
+
+int kc_block_gram(int nb, size_t n, int nc, const void* S, const void* AS, void* GA, void* GB, void* work,
+                  size_t work_bytes, void* stream) {
+  KC_ARG(nb >= 0 && n >= 1 && nc >= 1 && nc <= RR_NMAX, "nb >= 0, n >= 1, 1 <= nc <= 64");
+  if (nb == 0) return KC_OK;
+  KC_ARG(S != nullptr && AS != nullptr && GA != nullptr && GB != nullptr && work != nullptr, "NULL buffer");
+  KC_ARG(work_bytes >= gram2_part_bytes(nc, n, nb), "work_bytes below kc_block_work_bytes");
+  return gram2((const c64*)S, (const c64*)AS, nc, nc, n, nb, (c64*)work, (c64*)GA, (c64*)GB, nullptr,
+               (hipStream_t)stream);
+}
+
+int kc_block_update(int nb, size_t n, int mb, void* S, void* AS, const void* C, const double* theta, void* R,
+                    double* res, double* xnorm2, void* work, size_t work_bytes, void* stream) {
+  KC_ARG(nb >= 0 && n >= 1 && mb >= 1 && 3 * mb <= RR_NMAX, "nb >= 0, n >= 1, 1 <= mb <= 21");
+  if (nb == 0) return KC_OK;
+  KC_ARG(S != nullptr && AS != nullptr && C != nullptr && theta != nullptr && R != nullptr && res != nullptr &&
+             xnorm2 != nullptr && work != nullptr,
+         "NULL buffer");
+  const size_t sb = (size_t)nb * 3 * mb * n * sizeof(c64), rb = (size_t)nb * mb * n * sizeof(c64);
+  KC_ARG(disjoint(S, sb, AS, sb) && disjoint(R, rb, S, sb) && disjoint(R, rb, AS, sb),
+         "S, AS and R must not overlap");
+  KC_ARG(work_bytes >= (size_t)nb * mb * update_grid_x(n, nb) * 2 * sizeof(double),
+         "work_bytes below kc_block_work_bytes");
+  KC_TRY(update_res_prepare());
+  return update_res((c64*)S, (c64*)AS, 3 * mb, mb, (const c64*)C, n, nb, theta, (c64*)R, (double*)work, res,
+                    xnorm2, nullptr, (hipStream_t)stream);
 }
 
 }  // extern "C"

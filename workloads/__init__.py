@@ -185,6 +185,12 @@ def random_block(seed: int, nvec: int, N: int) -> np.ndarray:
     return (re + 1j * im).reshape(nvec, 3, N ** 3)
 
 
+def random_complex(seed: int, shape) -> np.ndarray:
+    """Seeded complex Gaussian array of any shape, complex128."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
 @dataclasses.dataclass
 class Workload:
     name: str
