@@ -36,8 +36,15 @@ constexpr int G2_ROWS = 16;
 constexpr int G2_COLS = 64;                       // S at [0, 64), AS at [64, 128) of a stage row
 constexpr int G2_ZERO = 2 * G2_COLS;              // 16 zero entries (tiles a wave does not own)
 constexpr int G2_PITCH = 2 * G2_COLS + 16 + 1;    // LDS row pitch (complex), odd to spread banks
-constexpr int G2_THREADS = 512;                   // 8 waves
+constexpr int G2_WAVES = 8;                       // waves per workgroup of k_gram2
+constexpr int G2_THREADS = 64 * G2_WAVES;
+constexpr int GW_WAVES = 4;                       // waves per workgroup of k_gramw
+constexpr int GW_THREADS = 64 * GW_WAVES;
 
+// MAXT tiles per wave: ceil(ntile / G2_WAVES).  (At nc = 60, 20 tiles over 8 waves leave four
+// slots that multiply zeros; 4 waves x 5 tiles would waste none, but at one wave per SIMD it
+// measured 45.7 instead of 33 ms per launch.)
+template <int MAXT>
 __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
                                                int nc, int kstride, int rows_per_chunk, int ntile,
                                                c64* __restrict__ part, const int* __restrict__ kskip) {
@@ -48,8 +55,7 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
   const int T = (nc + 15) / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  // this wave's tiles: t = wave, wave + 8, ...; t -> (mat, ti, tj), ti <= tj
-  constexpr int MAXT = 3;
+  // this wave's tiles: t = wave, wave + G2_WAVES, ...; t -> (mat, ti, tj), ti <= tj
   // tiles past nt read the zero entries of the stage rows
   int tmat[MAXT], tti[MAXT], ttj[MAXT];
   for (int t = 0; t < MAXT; ++t) {
@@ -62,7 +68,7 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
     for (int mat = 0; mat < 2; ++mat)
       for (int i = 0; i < T; ++i)
         for (int j = i; j < T; ++j, ++t)
-          if ((t & 7) == wave && nt < MAXT) {
+          if (t % G2_WAVES == wave && nt < MAXT) {
             tmat[nt] = mat;
             tti[nt] = i;
             ttj[nt] = j;
@@ -144,12 +150,12 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
     if (more) stash();
     __syncthreads();
   }
-  // partial tiles: [b][chunk][tile][256], tile id = wave + 8 t
+  // partial tiles: [b][chunk][tile][256], tile id = wave + G2_WAVES t
   const int nchunk = gridDim.x;
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) {
     if (t < nt) {
-      c64* out = part + (((size_t)b * nchunk + chunk) * ntile + (wave + 8 * t)) * 256;
+      c64* out = part + (((size_t)b * nchunk + chunk) * ntile + (wave + G2_WAVES * t)) * 256;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         out[(lk + 4 * r) * 16 + li] = mk(p1[t][r] + p2[t][r], p3[t][r] - p1[t][r] + p2[t][r]);
@@ -199,13 +205,15 @@ __global__ void k_gram2_reduce(const c64* __restrict__ part, int nchunk, int nti
 // over S (nc columns) and AW (mb columns); the blocks between X and P follow from the previous
 // Rayleigh-Ritz step (X^H X = I, X^H AX = Theta, X^H P = X^H AP = 0, P^H P = I, P^H AP stored by
 // it) and are filled by k_gramw_reduce.  Stage row: S at [0, 64), [W | AW] at [64, 64 + 2mb),
-// zeros after; the 16x16 tiles (ti < ceil(nc/16), tj < ceil(2mb/16)) are dealt to the 8 waves.
+// zeros after; the 16x16 tiles (ti < ceil(nc/16), tj < ceil(2mb/16)) are dealt to the waves,
+// MAXT = ceil(ntile / GW_WAVES) each (12 tiles at mb = 20: three per wave, none idle).
 // ------------------------------------------------------------------------------------
 constexpr int GW_R = G2_COLS;                      // start of [W | AW] in a stage row
 constexpr int GW_ZERO = G2_COLS + 48;              // 16 zero entries
 constexpr int GW_PITCH = G2_COLS + 48 + 16 + 1;
 
-__global__ __launch_bounds__(G2_THREADS) void k_gramw(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
+template <int MAXT>
+__global__ __launch_bounds__(GW_THREADS) void k_gramw(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
                                                       int mb, int kstride, int rows_per_chunk, int ntile,
                                                       c64* __restrict__ part, const int* __restrict__ kskip) {
   __shared__ c64 st[G2_ROWS * GW_PITCH];
@@ -216,11 +224,10 @@ __global__ __launch_bounds__(G2_THREADS) void k_gramw(const c64* __restrict__ S,
   const int TR = (2 * mb + 15) / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  constexpr int MAXT = 2;
   int tti[MAXT], ttj[MAXT];
   int nt = 0;
   for (int t = 0; t < MAXT; ++t) {
-    const int id = wave + 8 * t;
+    const int id = wave + GW_WAVES * t;
     if (id < ntile) {
       tti[t] = id / TR;
       ttj[t] = id % TR;
@@ -241,13 +248,13 @@ __global__ __launch_bounds__(G2_THREADS) void k_gramw(const c64* __restrict__ S,
   const c64* AWb = AS + ((size_t)b * kstride + mb) * n;
   const size_t r_begin = (size_t)chunk * rows_per_chunk;
   const size_t r_end = std::min(n, r_begin + rows_per_chunk);
-  const int ncl = nc + mb;  // loaded columns: S, then AW
-  constexpr int PER = (G2_ROWS * 80 + G2_THREADS - 1) / G2_THREADS;
+  const int ncl = nc + mb;  // loaded columns: S, then AW (at most 4 * RR_NMAX / 3)
+  constexpr int PER = (G2_ROWS * (4 * (RR_NMAX / 3)) + GW_THREADS - 1) / GW_THREADS;
   c64 nxt[PER];
   auto fetch = [&](size_t r0) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * G2_THREADS;
+      const int e = threadIdx.x + q * GW_THREADS;
       c64 v = mk(0.0, 0.0);
       if (e < G2_ROWS * ncl) {
         const int c = e / G2_ROWS, r = e % G2_ROWS;
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(G2_THREADS) void k_gramw(const c64* __restrict__ S,
   auto stash = [&]() {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * G2_THREADS;
+      const int e = threadIdx.x + q * GW_THREADS;
       if (e < G2_ROWS * ncl) {
         const int c = e / G2_ROWS;
         c64* row = st + (e % G2_ROWS) * GW_PITCH;
@@ -308,7 +315,7 @@ __global__ __launch_bounds__(G2_THREADS) void k_gramw(const c64* __restrict__ S,
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) {
     if (t < nt) {
-      c64* out = part + (((size_t)b * nchunk + chunk) * ntile + (wave + 8 * t)) * 256;
+      c64* out = part + (((size_t)b * nchunk + chunk) * ntile + (wave + GW_WAVES * t)) * 256;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         out[(lk + 4 * r) * 16 + li] = mk(p1[t][r] + p2[t][r], p3[t][r] - p1[t][r] + p2[t][r]);
@@ -723,7 +730,11 @@ int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, c6
   const size_t rows = gram_rows(n, nb);
   const int nchunk = (int)((n + rows - 1) / rows);
   dim3 grid(nchunk, nb);
-  k_gram2<<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip);
+  switch ((ntile + G2_WAVES - 1) / G2_WAVES) {
+    case 1: k_gram2<1><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
+    case 2: k_gram2<2><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
+    default: k_gram2<3><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
+  }
   KC_LAUNCHED();
   dim3 g2(1, ntile, nb);
   k_gram2_reduce<<<g2, 256, 0, s>>>(part, nchunk, ntile, nc, GA, GB, kskip);
@@ -750,7 +761,11 @@ int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, De
   const int nchunk = (int)((n + rows - 1) / rows);
   KC_TRY(part.ensure((size_t)nb * nchunk * ntile * 256 * sizeof(c64)));
   dim3 grid(nchunk, nb);
-  k_gramw<<<grid, G2_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, part.as<c64>(), kskip);
+  switch ((ntile + GW_WAVES - 1) / GW_WAVES) {
+    case 1: k_gramw<1><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, part.as<c64>(), kskip); break;
+    case 2: k_gramw<2><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, part.as<c64>(), kskip); break;
+    default: k_gramw<3><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, part.as<c64>(), kskip); break;
+  }
   KC_LAUNCHED();
   dim3 g2(1, ntile + 1, nb);
   k_gramw_reduce<<<g2, 256, 0, s>>>(part.as<c64>(), nchunk, ntile, mb, GA, GB, theta, gapp, kskip);
