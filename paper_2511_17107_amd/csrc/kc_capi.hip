@@ -194,6 +194,7 @@ int kc_create(int N, int eps_scheme, const uint8_t* mat_ids_host, int n_mat, con
   make_twiddles(N, twd, twf);
   if (st == KC_OK) st = upload(op->tw64, twd);
   if (st == KC_OK) st = upload(op->tw32, twf);
+  if (st == KC_OK) st = prepare_kernels(N);
   if (st != KC_OK) {
     delete op;
     return st;

@@ -164,4 +164,58 @@ __device__ __forceinline__ void fft_tile(cpx<T>* lds, const cpx<T>* tw) {
   }
 }
 
+// The same stages on a 2D tile: NPEN pencils of N elements at lds[pen * PS + e * ES] (one of
+// PS, ES is 1, the other the row pitch).  Lanes run pencil-fastest: along a column (PS == 1)
+// the accesses are consecutive words, along a row (ES == 1) they are one pitch apart, which an
+// odd pitch spreads over the banks.
+template <int N, int NPEN, int ES, int PS, int NTH, int R, int NS, int DIR, typename T>
+__device__ __forceinline__ void fft_stage_2d(cpx<T>* lds, const cpx<T>* tw) {
+  constexpr int NB = N / R;
+  constexpr int TOT = NPEN * NB;
+  constexpr int IT = (TOT + NTH - 1) / NTH;
+  const int tid = threadIdx.x;
+  cpx<T> v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int w = tid + it * NTH;
+    if ((TOT % NTH) == 0 || w < TOT) {
+      const int pen = w % NPEN, j = w / NPEN;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[it][r] = lds[pen * PS + (j + r * NB) * ES];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int w = tid + it * NTH;
+    if ((TOT % NTH) == 0 || w < TOT) {
+      const int pen = w % NPEN, j = w / NPEN;
+      const int k = j % NS;
+      if constexpr (NS > 1) {
+        constexpr int STEP = N / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> t = tw[r * k * STEP];
+          if (DIR < 0) t.im = -t.im;
+          v[it][r] = v[it][r] * t;
+        }
+      }
+      dft_small<R, DIR, T>(v[it]);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[pen * PS + (base + r * NS) * ES] = v[it][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int NPEN, int ES, int PS, int NTH, int DIR, typename T, int S = 0, int NS = 1>
+__device__ __forceinline__ void fft_2d(cpx<T>* lds, const cpx<T>* tw) {
+  if constexpr (S < Plan<N>::S) {
+    constexpr int R = Plan<N>::R[S];
+    fft_stage_2d<N, NPEN, ES, PS, NTH, R, NS, DIR, T>(lds, tw);
+    fft_2d<N, NPEN, ES, PS, NTH, DIR, T, S + 1, NS * R>(lds, tw);
+  }
+}
+
 }  // namespace kc

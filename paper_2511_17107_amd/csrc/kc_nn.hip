@@ -553,6 +553,14 @@ int build_efield(kc_op* op) {
       const int m = (ids[p] >> (8 * c)) & 255;
       f[c * N3 + p] = (float)(1.0 / t[((m * 3 + c) * 3 + c) * 2]);
     }
+  std::vector<float> ft(3 * N3);  // x-major copy: [c][x][z][y]
+  for (int c = 0; c < 3; ++c)
+    for (int z = 0; z < N; ++z)
+      for (int y = 0; y < N; ++y)
+        for (int x = 0; x < N; ++x)
+          ft[c * N3 + ((size_t)x * N + z) * N + y] = f[c * N3 + ((size_t)z * N + y) * N + x];
+  KC_TRY(op->efield_t.ensure(ft.size() * sizeof(float)));
+  KC_HIP(hipMemcpy(op->efield_t.p, ft.data(), ft.size() * sizeof(float), hipMemcpyHostToDevice));
   KC_TRY(op->efield.ensure(f.size() * sizeof(float)));
   KC_HIP(hipMemcpy(op->efield.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
   return KC_OK;

@@ -26,7 +26,9 @@
 // K_B / (gamma s^2).  Hence T_E r = (1/s) [K_A F3^H E F3 K_A^H (r/s) + (1/gamma) K_B (r/s)]:
 // the operator's passes with a 1/s prologue and epilogue, the diagonal field E in the Z pass
 // and 1/gamma for gamma.  T_E is Hermitian positive semi-definite, zero exactly where K_P is
-// singular, and equals K_P^{-1} for E = 1.
+// singular, and equals K_P^{-1} for E = 1.  The field scales each component separately, so in
+// FP32 with the field shared by all k-points the y and z work of T_E is one pass over whole
+// yz-planes in LDS (k_yz_field), between x-passes that write and read an x-major layout.
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
@@ -55,9 +57,11 @@ __device__ __forceinline__ void load_eps_table(EpsEntry<T>* lt, const EpsEntry<T
 }
 
 // ------------------------------------------------------------------------------------
-// X1: curl prologue + inverse DFT along x.  Tile: P rows (y) of one (vec, z), 3 comps.
+// X1: curl prologue + inverse DFT along x.  Tile: P rows (y) of one (vec, z), 3 comps.  With XT
+// the output is written x-major, [vec][c][x][z][y], for the yz-plane pass (P consecutive y of
+// one (x, z) are contiguous there).
 // ------------------------------------------------------------------------------------
-template <int N, typename T, bool PRE, int P>
+template <int N, typename T, bool PRE, int P, bool XT = false>
 __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, cpx<T>* __restrict__ E,
                                                     const cpx<T>* __restrict__ ktab, VecMap vm,
                                                     const cpx<T>* __restrict__ gtw) {
@@ -95,16 +99,23 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
   __syncthreads();
   fft_tile<N, P, 3, NT, +1, T>(lds, tw);
   cpx<T>* Ev = E + (size_t)vec * 3 * N3;
-  for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
-    const int e = w % N, p = (w / N) % P, c = w / (N * P), y = yt * P + p;
-    Ev[c * N3 + (size_t)z * N * N + (size_t)y * N + e] = lds[G::addr3(c, e, p)];
+  if constexpr (XT) {
+    for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
+      const int p = w % P, e = (w / P) % N, c = w / (N * P);
+      Ev[c * N3 + (size_t)e * N * N + (size_t)z * N + yt * P + p] = lds[G::addr3(c, e, p)];
+    }
+  } else {
+    for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
+      const int e = w % N, p = (w / N) % P, c = w / (N * P), y = yt * P + p;
+      Ev[c * N3 + (size_t)z * N * N + (size_t)y * N + e] = lds[G::addr3(c, e, p)];
+    }
   }
 }
 
 // ------------------------------------------------------------------------------------
-// X2: forward DFT along x + outer curl + penalty epilogue.
+// X2: forward DFT along x + outer curl + penalty epilogue (XT: input x-major, as X1 writes it).
 // ------------------------------------------------------------------------------------
-template <int N, typename T, bool PRE, int P>
+template <int N, typename T, bool PRE, int P, bool XT = false>
 __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict__ E,
                                                         const c64* __restrict__ x, c64* __restrict__ y,
                                                         const cpx<T>* __restrict__ ktab,
@@ -127,9 +138,16 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
   const double g = PRE ? 1.0 / gamma[ik] : gamma[ik];
   load_twiddles<N>(tw, gtw);
   const cpx<T>* Ev = E + (size_t)vec * 3 * N3;
-  for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
-    const int e = w % N, p = (w / N) % P, c = w / (N * P), yy = yt * P + p;
-    lds[G::addr3(c, e, p)] = Ev[c * N3 + (size_t)z * N * N + (size_t)yy * N + e];
+  if constexpr (XT) {
+    for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
+      const int p = w % P, e = (w / P) % N, c = w / (N * P);
+      lds[G::addr3(c, e, p)] = Ev[c * N3 + (size_t)e * N * N + (size_t)z * N + yt * P + p];
+    }
+  } else {
+    for (int w = threadIdx.x; w < 3 * N * P; w += NT) {
+      const int e = w % N, p = (w / N) % P, c = w / (N * P), yy = yt * P + p;
+      lds[G::addr3(c, e, p)] = Ev[c * N3 + (size_t)z * N * N + (size_t)yy * N + e];
+    }
   }
   __syncthreads();
   fft_tile<N, P, 3, NT, -1, T>(lds, tw);
@@ -342,6 +360,57 @@ __global__ __launch_bounds__(NT) void k_z_field(cpx<T>* __restrict__ buf, const 
     const int p = w % P, e = (w / P) % N, c = w / (N * P);
     base[c * N3 + (size_t)e * N * N + p] = lds[G::addr3(c, e, p)];
   }
+}
+
+// ------------------------------------------------------------------------------------
+// YZ (transverse-projection preconditioner, FP32, shared field): on the x-major layout one
+// workgroup holds the whole yz-plane of one (vec, component, x) in LDS (N x (N+1) complex, the
+// odd pitch spreads the row-wise stages over the banks) and does what the Y1, Z(field) and Y2
+// passes do in three round trips: inverse DFTs along y and z, E_c' = f_c E_c / N^3 with the
+// x-major field, forward DFTs along z and y.  In place.
+// ------------------------------------------------------------------------------------
+constexpr int NT_PLANE = 1024;
+
+template <int N, typename T>
+constexpr size_t plane_lds_bytes() {
+  return ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
+}
+
+// the plane pass is used where its tile fits the 160 KiB of LDS (FP32 up to N = 128)
+template <int N, typename T>
+constexpr bool plane_ok() {
+  return sizeof(T) == 4 && plane_lds_bytes<N, T>() <= 160 * 1024;
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(NT_PLANE) void k_yz_field(cpx<T>* __restrict__ buf, const float* __restrict__ fieldt,
+                                                       const cpx<T>* __restrict__ gtw,
+                                                       const int* __restrict__ active) {
+  constexpr int PL = N + 1;
+  constexpr size_t N3 = (size_t)N * N * N;
+  constexpr T inv = T(1) / T(N3);
+  extern __shared__ __align__(16) unsigned char plane_smem[];
+  cpx<T>* lds = reinterpret_cast<cpx<T>*>(plane_smem);
+  cpx<T>* tw = lds + N * PL;
+  const unsigned b = blockIdx.x;
+  const int x = b % N, c = (b / N) % 3;
+  const size_t vec = b / (3 * N);
+  if (active && !active[vec]) return;
+  load_twiddles<N>(tw, gtw);
+  cpx<T>* pl = buf + vec * 3 * N3 + (size_t)c * N3 + (size_t)x * N * N;  // [z][y]
+  const float* f = fieldt + (size_t)c * N3 + (size_t)x * N * N;
+  for (int t = threadIdx.x; t < N * N; t += NT_PLANE) lds[(t / N) * PL + t % N] = pl[t];
+  __syncthreads();
+  fft_2d<N, N, 1, PL, NT_PLANE, +1, T>(lds, tw);  // along y: pencils = rows z
+  fft_2d<N, N, PL, 1, NT_PLANE, +1, T>(lds, tw);  // along z: pencils = columns y
+  for (int t = threadIdx.x; t < N * N; t += NT_PLANE) {
+    const int a = (t / N) * PL + t % N;
+    lds[a] = ((T)f[t] * inv) * lds[a];
+  }
+  __syncthreads();
+  fft_2d<N, N, PL, 1, NT_PLANE, -1, T>(lds, tw);
+  fft_2d<N, N, 1, PL, NT_PLANE, -1, T>(lds, tw);
+  for (int t = threadIdx.x; t < N * N; t += NT_PLANE) pl[t] = lds[(t / N) * PL + t % N];
 }
 
 // ------------------------------------------------------------------------------------
@@ -580,24 +649,30 @@ static int tile_of(const kc_op* op, int pass) {
 }
 
 // The launchers below take the tile width of their pass from the handle.
-template <int N, typename T, bool PRE>
+template <int N, typename T, bool PRE, bool XT = false>
 static void launch_x1(kc_op* op, int pass, int nvec, const c64* x, cpx<T>* A, const cpx<T>* ktab, const VecMap& vm,
                       const cpx<T>* tw, hipStream_t s) {
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    k_x1_curl_inv<N, T, PRE, P><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw);
+    k_x1_curl_inv<N, T, PRE, P, XT><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw);
   });
 }
 
-template <int N, typename T, bool PRE>
+template <int N, typename T, bool PRE, bool XT = false>
 static void launch_x2(kc_op* op, int pass, int nvec, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* ktab,
                       const c64* ktab64, const double* gam, const VecMap& vm, const VecMap& vmy, const cpx<T>* tw,
                       hipStream_t s) {
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    k_x2_fwd_curl_pen<N, T, PRE, P>
+    k_x2_fwd_curl_pen<N, T, PRE, P, XT>
         <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw);
   });
+}
+
+template <int N, typename T>
+static void launch_yz(int nvec, cpx<T>* A, const float* fieldt, const cpx<T>* tw, const int* act, hipStream_t s) {
+  if constexpr (plane_ok<N, T>())
+    k_yz_field<N, T><<<nblk((size_t)nvec * 3 * N), NT_PLANE, plane_lds_bytes<N, T>(), s>>>(A, fieldt, tw, act);
 }
 
 template <int N, int DIR, typename T>
@@ -726,6 +801,19 @@ static int apply_tp_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecM
   cpx<T>* A = op->work_a.as<cpx<T>>();
   const PassArgs<T> pa = pass_args<N, T>(op, ik0);
   const int* act = vm.active;
+  if constexpr (plane_ok<N, T>()) {
+    // the classical field shared by all k-points: x-passes in the x-major layout around one
+    // yz-plane pass
+    if (fkstride == 0 && field == op->efield.as<float>() && op->efield_t.p != nullptr) {
+      launch_x1<N, T, true, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s);
+      KC_LAUNCHED();
+      launch_yz<N, T>(nvec, A, op->efield_t.as<float>(), pa.tw, act, s);
+      KC_LAUNCHED();
+      launch_x2<N, T, true, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s);
+      KC_LAUNCHED();
+      return KC_OK;
+    }
+  }
   launch_x1<N, T, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s);
   KC_LAUNCHED();
   launch_y<N, +1, T>(op, TP_Y1, nvec, A, pa.tw, act, s);
@@ -775,7 +863,7 @@ static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s) {
   auto run_pass = [&](int pass) {
     switch (pass) {
       case TP_X1: launch_x1<N, T, false>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s); break;
-      case TP_X1P: launch_x1<N, T, true>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s); break;
+      case TP_X1P: launch_x1<N, T, true, plane_ok<N, T>()>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s); break;
       case TP_Y1: launch_y<N, +1, T>(op, pass, nv, A, pa.tw, nullptr, s); break;
       case TP_Y2: launch_y<N, -1, T>(op, pass, nv, A, pa.tw, nullptr, s); break;
       case TP_ZA: launch_zplain<N, +1, T>(op, pass, 3 * nv, A, B, pa.tw, nullptr, 3, s); break;
@@ -783,7 +871,9 @@ static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s) {
       case TP_ZT: launch_zt<N, T>(op, nv, A, pa.eps, pa.tw, nullptr, s); break;
       case TP_ZF: launch_zf<N, T>(op, nv, A, fld, nv, 0, pa.tw, nullptr, s); break;
       case TP_X2: launch_x2<N, T, false>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s); break;
-      case TP_X2P: launch_x2<N, T, true>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s); break;
+      case TP_X2P:
+        launch_x2<N, T, true, plane_ok<N, T>()>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s);
+        break;
       default: break;
     }
   };
@@ -911,6 +1001,20 @@ static int fft3d_n(int nvec, int sign, const cpx<T>* in, cpx<T>* out, const cpx<
     case 128: { constexpr int NN = 128; return CALL; } \
     default: break;                                   \
   }
+
+template <int N>
+static int prepare_n() {
+  if constexpr (plane_ok<N, float>())
+    KC_HIP(hipFuncSetAttribute((const void*)k_yz_field<N, float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)plane_lds_bytes<N, float>()));
+  return KC_OK;
+}
+
+int prepare_kernels(int N) {
+  KC_DISPATCH_N(N, (prepare_n<NN>()))
+  set_error("unsupported N");
+  return KC_ERR_UNSUPPORTED;
+}
 
 int apply_op(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x, c64* y, int prec, hipStream_t s,
              hipEvent_t* ev) {

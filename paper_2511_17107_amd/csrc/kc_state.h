@@ -68,6 +68,7 @@ struct kc_op {
   kc::Net* net = nullptr;     // attached learned preconditioner (not owned)
   kc::DevBuf epsfeat;         // f32 [N^3][9] inverse-permittivity features for the network
   kc::DevBuf efield;          // f32 [3][N^3] E_c = 1/(eps^-1)_cc at the c-edge points
+  kc::DevBuf efield_t;        // the same, x-major ([3][x][z][y]) for the yz-plane pass
   kc::DevBuf efield_k;        // f32 [nb][3][N^3] learned fields of the k-points being solved
   kc::DevBuf kdev;            // double [nk][3] wave vectors
   double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -89,6 +90,8 @@ int apply_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* r, c6
 // through vm, y through vmy (same grouping and active mask); x and y must not overlap.
 int apply_tp(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecMap& vmy, const c64* x, c64* y,
              const float* field, int fkstride, int prec, hipStream_t s);
+// per-grid kernel attributes (the LDS limit of the yz-plane pass); called by kc_create
+int prepare_kernels(int N);
 // E_c = 1/(eps^-1)_cc at the c-edge points (built on first use)
 int build_efield(kc_op* op);
 // g[b][3][N^3] += gradient with respect to E of sum_j w_j Re<e_j, T_E r_j> (w device, nvec

@@ -41,6 +41,25 @@ def test_transverse_matches_oracle(N, prec, tol):
         assert rel_err(z[2 * b:2 * b + 2], ref) < tol, (N, ik)
 
 
+@pytest.mark.parametrize("N,tol", [(64, 3e-6), (128, 5e-6)])
+def test_transverse_plane_pass_large(N, tol):
+    """FP32 with the classical field: the x-passes in the x-major layout around the yz-plane
+    pass (a whole 128 x 128 plane in LDS at N = 128), one k-point off the symmetry lines and
+    Gamma, two vectors each, against the oracle's pseudo-inverse definition."""
+    wl = W.woodpile_gyrotropic(N=N, nk=60, m=16)
+    op = kc.Op(N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    kp = np.array([wl.kpoints[0], wl.kpoints[23]])
+    op.set_kpoints(kp)
+    r = W.random_block(70 + N, 4, N)
+    note("tp plane pass N=%d" % N)
+    z = to_host(op.precond_transverse(to_dev(r), ik0=0, vecs_per_k=2, prec=kc.KC_PREC_FP32))
+    E0 = kspace.edge_permittivity(wl.ids, wl.table).astype(np.float32).astype(np.float64)
+    g = op.gamma()
+    for b in range(2):
+        ref = kspace.transverse_precond_apply(N, kp[b], g[b], E0, r[2 * b:2 * b + 2])
+        assert rel_err(z[2 * b:2 * b + 2], ref) < tol, (N, b)
+
+
 def test_transverse_field_per_kpoint():
     """A different positive field per k-point (device float32 [nk][3][N^3])."""
     N = 16
