@@ -1,7 +1,7 @@
 // LDS-resident pencil FFTs for gfx950.
 //
 // A workgroup holds a tile of NPEN pencils of length N in LDS and transforms all of them
-// along their length with a Stockham autosort sequence of radix-R stages (R in {2,3,4,8}):
+// along their length with a Stockham autosort sequence of radix-R stages (R in {2,3,4,8,16}):
 // at a stage with radix R after a sub-transform length NS, butterfly j of a pencil reads
 // elements j + r N/R (r < R), multiplies them by exp(DIR 2 pi i r (j mod NS) / (NS R)),
 // applies the length-R DFT and writes them to (j div NS) NS R + (j mod NS) + r NS.  After
@@ -87,6 +87,32 @@ __device__ __forceinline__ void dft_small(cpx<T>* v) {
     v[6] = e[2] - o2;
     v[3] = e[3] + o3;
     v[7] = e[3] - o3;
+  } else if constexpr (R == 16) {
+    // n = 4 n1 + n2, q = q1 + 4 q2: length-4 DFTs over n1, twiddles w16^(n2 q1), length-4 DFTs
+    // over n2 (w16 = exp(DIR i pi/8))
+    const T c1 = static_cast<T>(0.92387953251128675613), s1 = static_cast<T>(0.38268343236508977173);
+    const T r2 = static_cast<T>(0.70710678118654752440);
+    const T d = static_cast<T>(DIR);
+    const cpx<T> w[10] = {mk(T(1), T(0)),  mk(c1, d * s1),   mk(r2, d * r2),   mk(s1, d * c1),
+                          mk(T(0), d),     mk(-s1, d * c1),  mk(-r2, d * r2),  mk(-c1, d * s1),
+                          mk(T(-1), T(0)), mk(-c1, -d * s1)};
+    cpx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+      dft_small<4, DIR, T>(a[n2]);  // a[n2][q1]
+#pragma unroll
+      for (int q1 = 1; q1 < 4; ++q1)
+        if (n2 > 0) a[n2][q1] = a[n2][q1] * w[n2 * q1];
+    }
+#pragma unroll
+    for (int q1 = 0; q1 < 4; ++q1) {
+      cpx<T> b[4] = {a[0][q1], a[1][q1], a[2][q1], a[3][q1]};
+      dft_small<4, DIR, T>(b);
+#pragma unroll
+      for (int q2 = 0; q2 < 4; ++q2) v[q1 + 4 * q2] = b[q2];
+    }
   }
 }
 
@@ -209,10 +235,20 @@ __device__ __forceinline__ void fft_stage_2d(cpx<T>* lds, const cpx<T>* tw) {
   __syncthreads();
 }
 
+// radix plans of the 2D tiles (one butterfly per thread at N = 128 and 1024 threads, so the
+// larger radix costs no extra registers and saves a stage per direction)
+template <int N>
+struct Plan2D : Plan<N> {};
+template <>
+struct Plan2D<128> {
+  static constexpr int S = 2;
+  static constexpr int R[3] = {16, 8, 1};
+};
+
 template <int N, int NPEN, int ES, int PS, int NTH, int DIR, typename T, int S = 0, int NS = 1>
 __device__ __forceinline__ void fft_2d(cpx<T>* lds, const cpx<T>* tw) {
-  if constexpr (S < Plan<N>::S) {
-    constexpr int R = Plan<N>::R[S];
+  if constexpr (S < Plan2D<N>::S) {
+    constexpr int R = Plan2D<N>::R[S];
     fft_stage_2d<N, NPEN, ES, PS, NTH, R, NS, DIR, T>(lds, tw);
     fft_2d<N, NPEN, ES, PS, NTH, DIR, T, S + 1, NS * R>(lds, tw);
   }
