@@ -10,7 +10,13 @@ path so that consecutive steps walk the whole path; ~180 GB of HBM for the batch
 are resident before the timed region; the solve allocates its block workspace once and
 reuses it.  Prints one JSON line (see the keys below).
 
-    python bench.py [--steps K] [--warmup W] [--kpb 4] [--prec fp32|fp64] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--kpb 10] [--guard 4] [--prec fp32|fp64]
+                    [--precond transverse|diag] [--no-cpu-baseline]
+    python bench.py --matvec-only | --update-only     (single kernels, for rocprofv3)
+
+`roofline` is the fused block update + residual pass (the largest kernel of a step), timed live
+at the solve's batch shape after the solve; `matvec` lists the operator passes with their own
+`roofline` entry for the longest one.
 """
 import argparse
 import json
