@@ -122,17 +122,17 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
     stash();
   }
   __syncthreads();
-  for (size_t r0 = r_begin; r0 < r_end; r0 += G2_ROWS) {
-    const bool more = r0 + G2_ROWS < r_end;
-    if (more) fetch(r0 + G2_ROWS);  // next stage in flight while this one is multiplied
+  // the products of one staged slice for the first K tiles of this wave
+  auto multiply = [&](auto kc_) {
+    constexpr int K = decltype(kc_)::value;
 #pragma unroll
     for (int kb = 0; kb < G2_ROWS; kb += 4) {
       const c64* srow = st + (kb + lk) * G2_PITCH;
       asm volatile("" ::: "memory");  // one 4-row step's operands live at a time (occupancy)
-      c64 av[MAXT], bv[MAXT];
+      c64 av[K], bv[K];
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t) {
-        // tiles past nt and columns past nc read zeros (the stage is zero-padded)
+      for (int t = 0; t < K; ++t) {
+        // columns past nc read zeros (the stage is zero-padded)
         const int ca = tti[t] * 16 + li;
         const int cb = ttj[t] * 16 + li;
         av[t] = srow[ca];
@@ -140,11 +140,25 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
       }
       // consecutive MFMAs go to different accumulators
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t) p1[t] = mfma(av[t].re, bv[t].re, p1[t]);
+      for (int t = 0; t < K; ++t) p1[t] = mfma(av[t].re, bv[t].re, p1[t]);
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t) p2[t] = mfma(av[t].im, bv[t].im, p2[t]);
+      for (int t = 0; t < K; ++t) p2[t] = mfma(av[t].im, bv[t].im, p2[t]);
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t) p3[t] = mfma(av[t].re - av[t].im, bv[t].re + bv[t].im, p3[t]);
+      for (int t = 0; t < K; ++t) p3[t] = mfma(av[t].re - av[t].im, bv[t].re + bv[t].im, p3[t]);
+    }
+  };
+  for (size_t r0 = r_begin; r0 < r_end; r0 += G2_ROWS) {
+    const bool more = r0 + G2_ROWS < r_end;
+    if (more) fetch(r0 + G2_ROWS);  // next stage in flight while this one is multiplied
+    // a wave with a slot to spare skips it (waves w and w + 4 share a SIMD, so at 20 tiles each
+    // SIMD multiplies five)
+    if constexpr (MAXT > 1) {
+      if (nt == MAXT)
+        multiply(std::integral_constant<int, MAXT>{});
+      else
+        multiply(std::integral_constant<int, MAXT - 1>{});
+    } else {
+      multiply(std::integral_constant<int, MAXT>{});
     }
     __syncthreads();
     if (more) stash();
