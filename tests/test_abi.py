@@ -17,14 +17,15 @@ HEADER = os.path.join(ROOT, "include", "kcpc.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char)\s*\*?\s*(kc_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char|size_t)\s*\*?\s*(kc_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["kc_create", "kc_set_kpoints", "kc_apply", "kc_precond", "kc_solve", "kc_destroy",
-              "kc_fft3d", "kc_last_error", "kc_status_string"]:
+              "kc_fft3d", "kc_last_error", "kc_status_string", "kc_block_work_bytes", "kc_block_gram",
+              "kc_block_update", "kc_net_param_count"]:
         assert n in names
 
 
@@ -99,3 +100,28 @@ def test_solve_opts_defaults():
     assert (o.m, o.guard, o.maxit, o.prec, o.batch_k, o.precond, o.graph) == (10, 0, 500, B.KC_PREC_FP64, 1,
                                                                               B.KC_PRECOND_DIAG, 1)
     assert o.tol == 1e-8 and o.seed == 1234
+
+
+def test_block_calls_check_arguments():
+    """kc_block_work_bytes is 0 out of range; kc_block_gram / kc_block_update reject bad sizes,
+    NULL buffers, overlapping blocks and a short workspace before any device work."""
+    L = kc.lib()
+    assert L.kc_block_work_bytes(0, 100, 60) == 0 and L.kc_block_work_bytes(2, 100, 65) == 0
+    need = L.kc_block_work_bytes(2, 1000, 60)
+    assert need > 0
+    fake = ctypes.c_void_p(1 << 40)  # never dereferenced: every call below fails its checks first
+    other = ctypes.c_void_p(1 << 41)
+    # nb = 0 is a no-op
+    assert L.kc_block_gram(0, 1000, 60, None, None, None, None, None, 0, None) == 0
+    assert L.kc_block_update(0, 1000, 20, None, None, None, None, None, None, None, None, 0, None) == 0
+    bad = [L.kc_block_gram(2, 1000, 65, fake, other, fake, fake, fake, need, None),
+           L.kc_block_gram(2, 1000, 60, None, other, fake, fake, fake, need, None),
+           L.kc_block_gram(2, 1000, 60, fake, other, fake, fake, fake, need - 1, None),
+           L.kc_block_update(2, 1000, 22, fake, other, fake, fake, fake, fake, fake, fake, need, None),
+           L.kc_block_update(2, 1000, 0, fake, other, fake, fake, fake, fake, fake, fake, need, None),
+           L.kc_block_update(2, 1000, 20, fake, fake, fake, fake, other, fake, fake, fake, need, None),
+           L.kc_block_update(2, 1000, 20, fake, other, fake, fake, None, fake, fake, fake, need, None),
+           L.kc_block_update(2, 1000, 20, fake, other, fake, fake, ctypes.c_void_p(1 << 42), fake, fake, fake,
+                             10, None)]
+    assert all(st == 1 for st in bad), bad  # KC_ERR_INVALID_ARG
+    assert b"work_bytes" in L.kc_last_error()
