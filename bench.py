@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--precond", choices=["diag", "transverse"], default="transverse",
                     help="LOBPCG preconditioner: diagonal-block K_P^-1 or transverse-projection T_E")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="sweep the path: each timed step after the first starts its k-points from the "
+                         "converged fields of the previous step's (their neighbours on the path)")
     ap.add_argument("--matvec-only", action="store_true",
                     help="only the operator application on one block (and a plain device copy of known "
                          "size, the reference for hardware byte counters); for profiling")
@@ -231,11 +234,15 @@ def main():
         update_only(a, dev)
         return
 
-    def run_step(step):
+    xbuf = None
+    if a.warm_start:  # converged fields of the previous step (position j of batch s-1 is point s-1+jP)
+        xbuf = [torch.empty((a.kpb, a.m, 3, a.N ** 3), dtype=torch.complex128, device=dev) for _ in range(2)]
+
+    def run_step(step, x_init=None, x_out=None):
         ik0 = (step % nsteps_path) * a.kpb
         eig, res, its, st = op.solve(a.m, ik0=ik0, nk=a.kpb, tol=a.tol, maxit=a.maxit, prec=prec,
                                      switch_tol=a.switch_tol, batch_k=a.kpb, guard=a.guard,
-                                     verbose=a.verbose, check=True, precond=pc)
+                                     verbose=a.verbose, check=True, precond=pc, X_out=x_out, x_init=x_init)
         return ik0, eig, res, its, st, op.last_solve_stats()
 
     for w in range(a.warmup):
@@ -244,7 +251,11 @@ def main():
     t0 = time.perf_counter()
     results = []
     for s in range(a.steps):
-        results.append(run_step(s))
+        if xbuf is None:
+            results.append(run_step(s))
+        else:
+            warm = s > 0 and s % nsteps_path != 0
+            results.append(run_step(s, x_init=xbuf[(s + 1) % 2] if warm else None, x_out=xbuf[s % 2]))
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     nkp = a.steps * a.kpb
@@ -293,7 +304,8 @@ def main():
         "config": {"workload": "sc128-woodpile-gyrotropic-crossdof, 16 bands (+%d guard), "
                                "%d k-points/step of the 60-point G-X-M-G-R path" % (a.guard, a.kpb),
                    "N": a.N, "bands": a.m, "kpoints_per_step": a.kpb, "tol": a.tol,
-                   "precision": a.prec, "preconditioner": a.precond},
+                   "precision": a.prec, "preconditioner": a.precond,
+                   "start": "previous step's fields" if a.warm_start else "seeded random"},
         "converged": converged,
         "max_residual": maxres,
         "iterations": iters,

@@ -218,6 +218,11 @@ typedef struct kc_solve_opts {
   int graph;          /* 1: capture each iteration's launches (preconditioner, operator,   */
                       /* Rayleigh-Ritz, update, residuals) once per precision in a hipGraph */
                       /* and replay it, on a private stream; 0: launch them one by one      */
+  const void* x_init; /* NULL: seeded random start.  Else device complex128 [nk][m][3N^3]:   */
+                      /* start vectors per k-point (e.g. the converged fields of the        */
+                      /* neighbouring k-points of a path, kc_solve's X_out); they enter the */
+                      /* first search directions next to the random guard columns.  At k = 0 */
+                      /* their constant (DC) part is removed (Prop 2.5 (1)).  Not modified. */
 } kc_solve_opts;
 
 /* Fill opts with defaults (m = 10, guard = 0, tol = 1e-8, maxit = 500, FP64, batch_k = 1,

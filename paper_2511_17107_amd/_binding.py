@@ -37,6 +37,7 @@ class KcSolveOpts(ctypes.Structure):
         ("verbose", ctypes.c_int),
         ("precond", ctypes.c_int),
         ("graph", ctypes.c_int),
+        ("x_init", ctypes.c_void_p),
     ]
 
 
@@ -318,8 +319,9 @@ class Op:
     def solve(self, m: int, ik0: int = 0, nk: Optional[int] = None, tol: float = 1e-8, maxit: int = 500,
               prec: int = KC_PREC_FP64, switch_tol: float = 1e-3, batch_k: int = 1, guard: int = 0,
               seed: int = 1234, X_out=None, verbose: int = 0, stream=None, check: bool = True,
-              precond: int = KC_PRECOND_DIAG, graph: bool = True):
-        """Smallest positive eigenvalues for k-points ik0 .. ik0+nk-1.  Returns
+              precond: int = KC_PRECOND_DIAG, graph: bool = True, x_init=None):
+        """Smallest positive eigenvalues for k-points ik0 .. ik0+nk-1 (x_init: optional start
+        vectors, complex128 (nk, m, 3, N^3) on the device).  Returns
         (eig (nk, m), res (nk, m), iters (nk,), status)."""
         nk = self.nk - ik0 if nk is None else int(nk)
         o = KcSolveOpts()
@@ -328,6 +330,10 @@ class Op:
         o.switch_tol, o.batch_k, o.seed, o.verbose = float(switch_tol), int(batch_k), int(seed), int(verbose)
         o.precond = int(precond)
         o.graph = 1 if graph else 0
+        if x_init is not None:
+            if tuple(x_init.shape[:2]) != (nk, m):
+                raise ValueError("x_init must hold (nk, m) start vectors")
+            o.x_init = _dev_ptr(x_init, "torch.complex128", "x_init")
         eig = np.zeros((nk, m))
         res = np.zeros((nk, m))
         its = np.zeros(nk, dtype=np.int32)

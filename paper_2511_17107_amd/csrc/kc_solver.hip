@@ -123,7 +123,7 @@ int precond_tp(Batch& B) {
 }
 
 int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig, double* res_out, int* iters,
-                c64* Xout, hipStream_t s, bool* all_conv) {
+                c64* Xout, const c64* xinit, hipStream_t s, bool* all_conv) {
   if (!op->solver) op->solver = new SolverWork();
   SolverWork* w = op->solver;
   Batch B;
@@ -213,6 +213,19 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(random_block(B.S, n, nc, 0, mb, nb, o.seed, B.kglobal, s));
   KC_HIP(hipMemcpyAsync(w->theta.p, htheta.data(), htheta.size() * sizeof(double), hipMemcpyHostToDevice, s));
   KC_TRY(residuals(B, false));
+  if (xinit) {
+    // given start vectors take the first m new directions (the guard columns keep the
+    // preconditioned random ones); at k = 0 their DC entries go, as K_P^{-1} would remove them
+    const size_t N3 = (size_t)B.N * B.N * B.N;
+    for (int b = 0; b < nb; ++b) {
+      c64* w0 = B.S + ((size_t)b * nc + mb) * n;
+      KC_HIP(hipMemcpyAsync(w0, xinit + (size_t)b * m * n, (size_t)m * colbytes, hipMemcpyDeviceToDevice, s));
+      const double* kv = &op->kvec[3 * (size_t)(ik0 + b)];
+      if (kv[0] == 0.0 && kv[1] == 0.0 && kv[2] == 0.0)
+        for (int j = 0; j < m; ++j)
+          for (int c = 0; c < 3; ++c) KC_HIP(hipMemsetAsync(w0 + (size_t)j * n + c * N3, 0, sizeof(c64), s));
+    }
+  }
   // T_E per k-point; with the learned field a k-point falls back to K_P^{-1} when the geometric
   // mean of its band residuals (each floored at tol) stops decreasing or grows
   std::vector<int> lon(nb, tp ? 1 : 0), ht(nb * mb, 0);
@@ -507,6 +520,7 @@ void kc_solve_opts_default(kc_solve_opts* o) {
   o->verbose = 0;
   o->precond = KC_PRECOND_DIAG;
   o->graph = 1;
+  o->x_init = nullptr;
 }
 
 int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_host, double* res_host,
@@ -536,10 +550,10 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   for (int k0 = 0; k0 < nk; k0 += o.batch_k) {
     const int nb = std::min(o.batch_k, nk - k0);
     bool c = true;
+    const size_t vstride = (size_t)k0 * o.m * 3 * op->N * op->N * op->N;
     KC_TRY(kc::solve_batch(op, ik0 + k0, nb, o, eig_host + (size_t)k0 * o.m, res_host + (size_t)k0 * o.m,
-                           iters_host ? iters_host + k0 : nullptr,
-                           X_out ? (kc::c64*)X_out + (size_t)k0 * o.m * 3 * op->N * op->N * op->N : nullptr, s,
-                           &c));
+                           iters_host ? iters_host + k0 : nullptr, X_out ? (kc::c64*)X_out + vstride : nullptr,
+                           o.x_init ? (const kc::c64*)o.x_init + vstride : nullptr, s, &c));
     allc = allc && c;
   }
   KC_HIP(hipStreamSynchronize(s));

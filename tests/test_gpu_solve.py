@@ -187,3 +187,31 @@ def test_solve_n128_woodpile_properties():
         r = torch.linalg.vector_norm(Ab - torch.from_numpy(eig[b]).to(Ab.device)[:, None] * Xb, dim=1)
         assert float(r.max()) <= 1.5 * TOL
         assert np.all(np.diff(eig[b]) >= -1e-12 * eig[b][-1])
+
+
+@pytest.mark.parametrize("precond", [kc.KC_PRECOND_TRANSVERSE, kc.KC_PRECOND_DIAG])
+def test_warm_start_from_neighbouring_kpoints(precond):
+    """Start vectors from the converged fields of nearby k-points (kc_solve_opts.x_init): the
+    same eigenvalues as the oracle's (Gamma included: the constant fields stay out) in fewer
+    iterations than the random start."""
+    import torch
+
+    g = load("sphere16_aniso")
+    cases = [c for c in g["cases"] if c["scheme"] == "crossdof"][:3]
+    kp = np.array([c["k"] for c in cases])
+    wl = W.sphere_anisotropic(N=16, nk=9, m=10)
+    m, nk = 10, len(kp)
+    X = torch.zeros((nk, m, 3, 16 ** 3), dtype=torch.complex128, device="cuda")
+    note("warm start: neighbours", precond)
+    _, _, _, _, st = solve(wl, "crossdof", kp + np.array([0.05, 0.03, 0.02]), m, guard=2, batch_k=nk,
+                           precond=precond, X_out=X)
+    assert st == 0
+    note("warm start: cold and warm solves")
+    _, e0, r0, i0, s0 = solve(wl, "crossdof", kp, m, guard=2, batch_k=nk, precond=precond)
+    _, e1, r1, i1, s1 = solve(wl, "crossdof", kp, m, guard=2, batch_k=nk, precond=precond, x_init=X)
+    assert s0 == 0 and s1 == 0 and r1.max() <= TOL
+    for i, c in enumerate(cases):
+        ref = np.array(c["eigenvalues"][:m])
+        assert np.max(np.abs(e1[i] - ref) / ref) <= REL, (c["k"], e1[i], ref)
+    note("iterations cold", i0.tolist(), "warm", i1.tolist())
+    assert i1.sum() < i0.sum()
