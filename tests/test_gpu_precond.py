@@ -41,7 +41,7 @@ def test_transverse_matches_oracle(N, prec, tol):
         assert rel_err(z[2 * b:2 * b + 2], ref) < tol, (N, ik)
 
 
-@pytest.mark.parametrize("N,tol", [(64, 3e-6), (128, 5e-6)])
+@pytest.mark.parametrize("N,tol", [(32, 2e-6), (64, 3e-6), (96, 4e-6), (128, 5e-6)])
 def test_transverse_plane_pass_large(N, tol):
     """FP32 with the classical field: the x-passes in the x-major layout around the yz-plane
     pass (a whole 128 x 128 plane in LDS at N = 128), one k-point off the symmetry lines and
