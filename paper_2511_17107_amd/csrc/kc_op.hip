@@ -64,7 +64,7 @@ __device__ __forceinline__ void load_eps_table(EpsEntry<T>* lt, const EpsEntry<T
 template <int N, typename T, bool PRE, int P, bool XT = false>
 __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, cpx<T>* __restrict__ E,
                                                     const cpx<T>* __restrict__ ktab, VecMap vm,
-                                                    const cpx<T>* __restrict__ gtw) {
+                                                    const cpx<T>* __restrict__ gtw, cpx<T>* __restrict__ kx) {
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -85,6 +85,9 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
     const cpx<T> x1 = cvt<T>(xv[off]), x2 = cvt<T>(xv[N3 + off]), x3 = cvt<T>(xv[2 * N3 + off]);
     const cpx<T> v1 = conj(K[e]), v2 = conj(K[N + y]);
     cpx<T> c1 = v3 * x2 - v2 * x3, c2 = v1 * x3 - v3 * x1, c3 = v2 * x1 - v1 * x2;
+    // the preconditioner's penalty term needs only K . x: kept here for the last pass, which
+    // then does not re-read x
+    if constexpr (PRE && XT) kx[(size_t)vec * N3 + off] = cmulc(v1, x1) + cmulc(v2, x2) + cmulc(v3, x3);
     if (PRE) {  // K_A^{+} = K_A^H / s
       const T sq = abs2(v1) + abs2(v2) + abs2(v3);
       const T is = sq > T(0) ? T(1) / sq : T(0);
@@ -121,7 +124,8 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
                                                         const cpx<T>* __restrict__ ktab,
                                                         const c64* __restrict__ ktab64,
                                                         const double* __restrict__ gamma,
-                                                        VecMap vm, VecMap vmy, const cpx<T>* __restrict__ gtw) {
+                                                        VecMap vm, VecMap vmy, const cpx<T>* __restrict__ gtw,
+                                                        const cpx<T>* __restrict__ kxin) {
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -163,9 +167,14 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
     const c64 c1 = cvt<double>(K2 * e3 - K3 * e2);
     const c64 c2 = cvt<double>(K3 * e1 - K1 * e3);
     const c64 c3 = cvt<double>(K1 * e2 - K2 * e1);
-    const c64 x1 = xv[off], x2 = xv[N3 + off], x3 = xv[2 * N3 + off];
     const c64 K1d = Kd[e], K2d = Kd[N + yy];
-    const c64 kx = K1d * x1 + K2d * x2 + K3d * x3;  // K . x
+    c64 kx;  // K . x
+    if constexpr (PRE && XT) {
+      kx = cvt<double>(kxin[(size_t)vec * N3 + off]);
+    } else {
+      const c64 x1 = xv[off], x2 = xv[N3 + off], x3 = xv[2 * N3 + off];
+      kx = K1d * x1 + K2d * x2 + K3d * x3;
+    }
     if (PRE) {  // (1/s) [c + (1/gamma) K_B x / s]
       const double sq = abs2(K1d) + abs2(K2d) + abs2(K3d);
       const double is = sq > 0.0 ? 1.0 / sq : 0.0;
@@ -651,21 +660,21 @@ static int tile_of(const kc_op* op, int pass) {
 // The launchers below take the tile width of their pass from the handle.
 template <int N, typename T, bool PRE, bool XT = false>
 static void launch_x1(kc_op* op, int pass, int nvec, const c64* x, cpx<T>* A, const cpx<T>* ktab, const VecMap& vm,
-                      const cpx<T>* tw, hipStream_t s) {
+                      const cpx<T>* tw, hipStream_t s, cpx<T>* kx = nullptr) {
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    k_x1_curl_inv<N, T, PRE, P, XT><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw);
+    k_x1_curl_inv<N, T, PRE, P, XT><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw, kx);
   });
 }
 
 template <int N, typename T, bool PRE, bool XT = false>
 static void launch_x2(kc_op* op, int pass, int nvec, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* ktab,
                       const c64* ktab64, const double* gam, const VecMap& vm, const VecMap& vmy, const cpx<T>* tw,
-                      hipStream_t s) {
+                      hipStream_t s, const cpx<T>* kx = nullptr) {
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
     k_x2_fwd_curl_pen<N, T, PRE, P, XT>
-        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw);
+        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw, kx);
   });
 }
 
@@ -805,11 +814,13 @@ static int apply_tp_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecM
     // the classical field shared by all k-points: x-passes in the x-major layout around one
     // yz-plane pass
     if (fkstride == 0 && field == op->efield.as<float>() && op->efield_t.p != nullptr) {
-      launch_x1<N, T, true, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s);
+      KC_TRY(op->work_k.ensure((size_t)nvec * N3 * sizeof(cpx<T>)));
+      cpx<T>* kx = op->work_k.as<cpx<T>>();
+      launch_x1<N, T, true, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s, kx);
       KC_LAUNCHED();
       launch_yz<N, T>(nvec, A, op->efield_t.as<float>(), pa.tw, act, s);
       KC_LAUNCHED();
-      launch_x2<N, T, true, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s);
+      launch_x2<N, T, true, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s, kx);
       KC_LAUNCHED();
       return KC_OK;
     }
@@ -847,6 +858,7 @@ static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s) {
   KC_TRY(op->work_a.ensure(vb * sizeof(c64)));
   KC_TRY(op->work_b.ensure(vb * sizeof(c64)));
   KC_TRY(op->work_c.ensure(2 * vb * sizeof(c64)));
+  KC_TRY(op->work_k.ensure((size_t)nv * N3 * sizeof(c64)));
   KC_TRY(build_efield(op));
   cpx<T>* A = op->work_a.as<cpx<T>>();
   cpx<T>* B = op->work_b.as<cpx<T>>();
@@ -863,7 +875,9 @@ static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s) {
   auto run_pass = [&](int pass) {
     switch (pass) {
       case TP_X1: launch_x1<N, T, false>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s); break;
-      case TP_X1P: launch_x1<N, T, true, plane_ok<N, T>()>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s); break;
+      case TP_X1P:
+        launch_x1<N, T, true, plane_ok<N, T>()>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s, op->work_k.as<cpx<T>>());
+        break;
       case TP_Y1: launch_y<N, +1, T>(op, pass, nv, A, pa.tw, nullptr, s); break;
       case TP_Y2: launch_y<N, -1, T>(op, pass, nv, A, pa.tw, nullptr, s); break;
       case TP_ZA: launch_zplain<N, +1, T>(op, pass, 3 * nv, A, B, pa.tw, nullptr, 3, s); break;
@@ -872,7 +886,8 @@ static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s) {
       case TP_ZF: launch_zf<N, T>(op, nv, A, fld, nv, 0, pa.tw, nullptr, s); break;
       case TP_X2: launch_x2<N, T, false>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s); break;
       case TP_X2P:
-        launch_x2<N, T, true, plane_ok<N, T>()>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s);
+        launch_x2<N, T, true, plane_ok<N, T>()>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s,
+                                                op->work_k.as<cpx<T>>());
         break;
       default: break;
     }
