@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 # read off a plain 1 GiB device copy in the same run: operator passes keyed by pass, N, vectors,
 # precision (profiles/matvec_woodpile128_fp32_16vec.md), the fused update by N, k-points and
 # block width.
-MEASURED_TRAFFIC = {("X2", 128, 16, "fp32"): 4.030e9,
+MEASURED_TRAFFIC = {("X2", 128, 16, "fp32"): 2.953e9,
                     # fused update + residuals at 128^3, 10 k-points, 20-column blocks
                     # (profiles/update_woodpile128_10k_20col.md)
                     ("update", 128, 10, 20): 221.51e9}
@@ -75,17 +75,18 @@ def parse():
 def pass_bytes(N, nvec, scheme_cross, tbytes):
     """Algorithmic bytes of each pencil pass of one operator application: what the pass must
     read and write once (complex128 input/output vectors, compute-precision intermediates,
-    4-byte packed material ids)."""
+    4-byte packed material ids, and the complex128 K.x per point that X1 hands to X2)."""
     n3 = N ** 3
     v64 = 16 * 3 * n3 * nvec
     vt = tbytes * 3 * n3 * nvec
     ids = 4 * n3 * nvec
+    kx = 16 * n3 * nvec
     if scheme_cross:
         names = ["X1", "Y1", "Za", "Zb", "Y2", "X2"]
-        b = [v64 + vt, 2 * vt, 2 * vt, 2 * vt + ids, 2 * vt, vt + 2 * v64]
+        b = [v64 + vt + kx, 2 * vt, 2 * vt, 2 * vt + ids, 2 * vt, vt + kx + v64]
     else:
         names = ["X1", "Y1", "Z", "Y2", "X2"]
-        b = [v64 + vt, 2 * vt, 2 * vt + ids, 2 * vt, vt + 2 * v64]
+        b = [v64 + vt + kx, 2 * vt, 2 * vt + ids, 2 * vt, vt + kx + v64]
     return names, b
 
 

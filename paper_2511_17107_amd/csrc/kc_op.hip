@@ -4,14 +4,15 @@
 // y = K_A F3^H M F3 K_A^H x + gamma K_B x is evaluated in pencil passes over the
 // [vec][3][z][y][x] layout, each pass one round trip of the block through HBM:
 //
-//   X1  e = -conj(K) x x (curl symbol, prologue), inverse DFT along x         (3 comps)
+//   X1  e = -conj(K) x x (curl symbol, prologue), inverse DFT along x         (3 comps);
+//       also K . x per point for the penalty term of X2
 //   Y1  inverse DFT along y                                                   (per comp)
 //   Z   Trivial/diagonal: inverse DFT along z, E' = M E / N^3 pointwise,
 //       forward DFT along z                                                   (3 comps)
 //       CrossDoF: Za inverse DFT along z (per comp); Zb E' = M E / N^3 with the
 //       four-point cross-DoF averages read around each point, forward DFT along z
 //   Y2  forward DFT along y                                                   (per comp)
-//   X2  forward DFT along x, y = K x e' + gamma conj(K) (K . x) (epilogue, re-reads x)
+//   X2  forward DFT along x, y = K x e' + gamma conj(K) (K . x) (epilogue)
 //
 // The 1D symbols K_a(q) = (1 - e^{-i theta_q})/h + i k_a (1 + e^{-i theta_q})/2 are read from
 // a table of 3N entries per k-point (eq (2.28)), so no per-frequency array is stored.
@@ -64,7 +65,8 @@ __device__ __forceinline__ void load_eps_table(EpsEntry<T>* lt, const EpsEntry<T
 template <int N, typename T, bool PRE, int P, bool XT = false>
 __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, cpx<T>* __restrict__ E,
                                                     const cpx<T>* __restrict__ ktab, VecMap vm,
-                                                    const cpx<T>* __restrict__ gtw, cpx<T>* __restrict__ kx) {
+                                                    const cpx<T>* __restrict__ gtw, cpx<T>* __restrict__ kx,
+                                                    const c64* __restrict__ ktab64, c64* __restrict__ kx64) {
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -85,9 +87,13 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
     const cpx<T> x1 = cvt<T>(xv[off]), x2 = cvt<T>(xv[N3 + off]), x3 = cvt<T>(xv[2 * N3 + off]);
     const cpx<T> v1 = conj(K[e]), v2 = conj(K[N + y]);
     cpx<T> c1 = v3 * x2 - v2 * x3, c2 = v1 * x3 - v3 * x1, c3 = v2 * x1 - v1 * x2;
-    // the preconditioner's penalty term needs only K . x: kept here for the last pass, which
-    // then does not re-read x
+    // the penalty term of the last pass needs only K . x: kept here (FP64 for the operator,
+    // the compute precision for the preconditioner), so that pass does not re-read x
     if constexpr (PRE && XT) kx[(size_t)vec * N3 + off] = cmulc(v1, x1) + cmulc(v2, x2) + cmulc(v3, x3);
+    if constexpr (!PRE) {
+      const c64* Kd = ktab64 + (size_t)(vec / vm.vpk) * 3 * N;
+      kx64[(size_t)vec * N3 + off] = Kd[e] * xv[off] + Kd[N + y] * xv[N3 + off] + Kd[2 * N + z] * xv[2 * N3 + off];
+    }
     if (PRE) {  // K_A^{+} = K_A^H / s
       const T sq = abs2(v1) + abs2(v2) + abs2(v3);
       const T is = sq > T(0) ? T(1) / sq : T(0);
@@ -125,7 +131,7 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
                                                         const c64* __restrict__ ktab64,
                                                         const double* __restrict__ gamma,
                                                         VecMap vm, VecMap vmy, const cpx<T>* __restrict__ gtw,
-                                                        const cpx<T>* __restrict__ kxin) {
+                                                        const cpx<T>* __restrict__ kxin, const c64* __restrict__ kx64) {
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -171,6 +177,8 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
     c64 kx;  // K . x
     if constexpr (PRE && XT) {
       kx = cvt<double>(kxin[(size_t)vec * N3 + off]);
+    } else if constexpr (!PRE) {
+      kx = kx64[(size_t)vec * N3 + off];
     } else {
       const c64 x1 = xv[off], x2 = xv[N3 + off], x3 = xv[2 * N3 + off];
       kx = K1d * x1 + K2d * x2 + K3d * x3;
@@ -660,21 +668,23 @@ static int tile_of(const kc_op* op, int pass) {
 // The launchers below take the tile width of their pass from the handle.
 template <int N, typename T, bool PRE, bool XT = false>
 static void launch_x1(kc_op* op, int pass, int nvec, const c64* x, cpx<T>* A, const cpx<T>* ktab, const VecMap& vm,
-                      const cpx<T>* tw, hipStream_t s, cpx<T>* kx = nullptr) {
+                      const cpx<T>* tw, hipStream_t s, cpx<T>* kx = nullptr, const c64* ktab64 = nullptr,
+                      c64* kx64 = nullptr) {
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    k_x1_curl_inv<N, T, PRE, P, XT><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw, kx);
+    k_x1_curl_inv<N, T, PRE, P, XT>
+        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw, kx, ktab64, kx64);
   });
 }
 
 template <int N, typename T, bool PRE, bool XT = false>
 static void launch_x2(kc_op* op, int pass, int nvec, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* ktab,
                       const c64* ktab64, const double* gam, const VecMap& vm, const VecMap& vmy, const cpx<T>* tw,
-                      hipStream_t s, const cpx<T>* kx = nullptr) {
+                      hipStream_t s, const cpx<T>* kx = nullptr, const c64* kx64 = nullptr) {
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
     k_x2_fwd_curl_pen<N, T, PRE, P, XT>
-        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw, kx);
+        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw, kx, kx64);
   });
 }
 
@@ -770,8 +780,10 @@ static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x,
   const PassArgs<T> pa = pass_args<N, T>(op, ik0);
   const int* act = vm.active;
   if (op->scheme == KC_EPS_CROSSDOF) KC_TRY(op->work_b.ensure(nbuf));
+  KC_TRY(op->work_k.ensure((size_t)nvec * N3 * sizeof(c64)));
+  c64* kx = op->work_k.as<c64>();
   KC_TRY(mark());
-  launch_x1<N, T, false>(op, TP_X1, nvec, x, A, pa.ktab, vm, pa.tw, s);
+  launch_x1<N, T, false>(op, TP_X1, nvec, x, A, pa.ktab, vm, pa.tw, s, nullptr, pa.ktab64, kx);
   KC_LAUNCHED();
   KC_TRY(mark());
   launch_y<N, +1, T>(op, TP_Y1, nvec, A, pa.tw, act, s);
@@ -792,7 +804,7 @@ static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x,
   launch_y<N, -1, T>(op, TP_Y2, nvec, A, pa.tw, act, s);
   KC_LAUNCHED();
   KC_TRY(mark());
-  launch_x2<N, T, false>(op, TP_X2, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s);
+  launch_x2<N, T, false>(op, TP_X2, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s, nullptr, kx);
   KC_LAUNCHED();
   KC_TRY(mark());
   return KC_OK;
@@ -874,7 +886,9 @@ static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s) {
   KC_HIP(hipEventCreate(&e1));
   auto run_pass = [&](int pass) {
     switch (pass) {
-      case TP_X1: launch_x1<N, T, false>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s); break;
+      case TP_X1:
+        launch_x1<N, T, false>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s, nullptr, pa.ktab64, op->work_k.as<c64>());
+        break;
       case TP_X1P:
         launch_x1<N, T, true, plane_ok<N, T>()>(op, pass, nv, X, A, pa.ktab, vm, pa.tw, s, op->work_k.as<cpx<T>>());
         break;
@@ -884,7 +898,10 @@ static int tune_tiles_n(kc_op* op, int nvec, hipStream_t s) {
       case TP_ZB: launch_zb<N, T>(op, nv, B, A, pa.eps, pa.tw, nullptr, s); break;
       case TP_ZT: launch_zt<N, T>(op, nv, A, pa.eps, pa.tw, nullptr, s); break;
       case TP_ZF: launch_zf<N, T>(op, nv, A, fld, nv, 0, pa.tw, nullptr, s); break;
-      case TP_X2: launch_x2<N, T, false>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s); break;
+      case TP_X2:
+        launch_x2<N, T, false>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s, nullptr,
+                               op->work_k.as<c64>());
+        break;
       case TP_X2P:
         launch_x2<N, T, true, plane_ok<N, T>()>(op, pass, nv, A, X, Y, pa.ktab, pa.ktab64, pa.gam, vm, vm, pa.tw, s,
                                                 op->work_k.as<cpx<T>>());

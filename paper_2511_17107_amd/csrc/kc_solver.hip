@@ -183,7 +183,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   // their pointers, so no buffer may move after a capture
   KC_TRY(op->work_a.ensure((size_t)nb * mb * n * sizeof(c64)));
   if (op->scheme == KC_EPS_CROSSDOF) KC_TRY(op->work_b.ensure((size_t)nb * mb * n * sizeof(c64)));
-  if (tp) KC_TRY(op->work_k.ensure((size_t)nb * mb * (n / 3) * sizeof(c32)));
+  KC_TRY(op->work_k.ensure((size_t)nb * mb * (n / 3) * sizeof(c64)));
   B.S = w->S.as<c64>();
   B.AS = w->AS.as<c64>();
   int* ib = w->ints.as<int>();

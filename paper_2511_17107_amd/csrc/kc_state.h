@@ -64,7 +64,7 @@ struct kc_op {
   kc::DevBuf ktab64, ktab32;        // 1D symbols [nk][3][N]
   kc::DevBuf gamma_d;               // double [nk]
   kc::DevBuf work_a, work_b, work_c;  // operator intermediates
-  kc::DevBuf work_k;                  // K . x per point of the preconditioner's plane path
+  kc::DevBuf work_k;                  // K . x per point (first x-pass -> last x-pass)
   kc::SolverWork* solver = nullptr;
   kc::Net* net = nullptr;     // attached learned preconditioner (not owned)
   kc::DevBuf epsfeat;         // f32 [N^3][9] inverse-permittivity features for the network
