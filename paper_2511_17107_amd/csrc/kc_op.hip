@@ -71,7 +71,8 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
   constexpr size_t N3 = (size_t)N * N * N;
-  unsigned b = blockIdx.x;
+  // x-major: the tiles yt, yt + 1 share 128-byte lines, so they go to the same XCD (one L2)
+  unsigned b = XT ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
   const int yt = b % (N / P);
   b /= (N / P);
   const int z = b % N;
@@ -136,7 +137,8 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
   constexpr size_t N3 = (size_t)N * N * N;
-  unsigned b = blockIdx.x;
+  // x-major: the tiles yt, yt + 1 share 128-byte lines, so they go to the same XCD (one L2)
+  unsigned b = XT ? xcd_swizzle(blockIdx.x, gridDim.x) : blockIdx.x;
   const int yt = b % (N / P);
   b /= (N / P);
   const int z = b % N;
