@@ -32,13 +32,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the factors
-# read off a plain 1 GiB device copy in the same run: operator passes keyed by pass, N, vectors,
-# precision (profiles/matvec_woodpile128_fp32_16vec.md), the fused update by N, k-points and
-# block width.
-MEASURED_TRAFFIC = {("X2", 128, 16, "fp32"): 2.953e9,
-                    # fused update + residuals at 128^3, 10 k-points, 20-column blocks
-                    # (profiles/update_woodpile128_10k_20col.md)
-                    ("update", 128, 10, 20): 221.51e9}
+# read off a plain 1 GiB device copy in the same run: operator passes on 16 vectors at 128^3,
+# FP32, keyed by pass and tile width (profiles/matvec_woodpile128_fp32_16vec.md); the fused
+# update keyed by N, k-points and block width (profiles/update_woodpile128_10k_20col.md).
+MEASURED_TRAFFIC = {
+    ("X1", 128, 16, "fp32", 4): 2.953e9, ("X1", 128, 16, "fp32", 8): 2.953e9, ("X1", 128, 16, "fp32", 16): 2.953e9,
+    ("Y1", 128, 16, "fp32", 4): 4.027e9, ("Y1", 128, 16, "fp32", 8): 2.416e9, ("Y1", 128, 16, "fp32", 16): 1.611e9,
+    ("Y1", 128, 16, "fp32", 32): 1.611e9,
+    ("Za", 128, 16, "fp32", 4): 4.027e9, ("Za", 128, 16, "fp32", 8): 2.416e9, ("Za", 128, 16, "fp32", 16): 1.611e9,
+    ("Za", 128, 16, "fp32", 32): 1.611e9,
+    ("Zb", 128, 16, "fp32", 4): 1.794e9, ("Zb", 128, 16, "fp32", 8): 1.776e9, ("Zb", 128, 16, "fp32", 16): 1.959e9,
+    ("Y2", 128, 16, "fp32", 4): 4.027e9, ("Y2", 128, 16, "fp32", 8): 2.416e9, ("Y2", 128, 16, "fp32", 16): 1.611e9,
+    ("Y2", 128, 16, "fp32", 32): 1.611e9,
+    ("X2", 128, 16, "fp32", 4): 2.953e9, ("X2", 128, 16, "fp32", 8): 2.953e9, ("X2", 128, 16, "fp32", 16): 2.954e9,
+    ("update", 128, 10, 20): 221.51e9,
+}
+# tile-width slot of each CrossDoF operator pass in kc_tile_widths
+PASS_SLOT = {"X1": 0, "Y1": 1, "Za": 2, "Zb": 3, "Y2": 5, "X2": 6}
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
@@ -321,7 +331,9 @@ def main():
                    "roofline": {"bound": "hbm", "kernel": "matvec pass " + names[dom],
                                 "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": gbs[dom] / HBM_PEAK_GBS,
-                                "traffic": MEASURED_TRAFFIC.get((names[dom], a.N, a.m, a.prec)),
+                                "traffic": MEASURED_TRAFFIC.get(
+                                    (names[dom], a.N, a.m, a.prec, tiles[a.prec][PASS_SLOT[names[dom]]])),
+                                "tile_width": tiles[a.prec][PASS_SLOT[names[dom]]],
                                 "alg_bytes": pbytes[dom]}},
     }
     if not a.no_cpu_baseline:
