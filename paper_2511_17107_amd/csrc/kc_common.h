@@ -52,6 +52,22 @@ template <typename T>
 __host__ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
   return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
 }
+
+// acc += a b and acc += conj(a) b as four fused multiply-adds (no separate product and sum)
+template <typename T>
+__device__ __forceinline__ void cfma(cpx<T>& acc, cpx<T> a, cpx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+template <typename T>
+__device__ __forceinline__ void cfmac(cpx<T>& acc, cpx<T> a, cpx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+}
 // i * a
 template <typename T>
 __host__ __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) {

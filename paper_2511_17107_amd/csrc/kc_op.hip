@@ -533,32 +533,35 @@ __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E
       auto my = [&](uint32_t id) -> const EpsEntry<T>& { return eps[(id >> 8) & 255u]; };
       auto mz = [&](uint32_t id) -> const EpsEntry<T>& { return eps[(id >> 16) & 255u]; };
       // row 1: d1 E1 + block(1,2) E2 [T12 on plane k] + block(1,3) E3 [T13 on planes k, k+1]
-      cpx<T> a1 = (ex.o[0] + my(cur.id[0]).o[0]) * cur.e2[0];
-      a1 = a1 + (ex.o[0] + my(cur.id[4]).o[0]) * cur.e2[1];
-      a1 = a1 + (ex.o[0] + my(cur.id[5]).o[0]) * cur.e2[2];
-      a1 = a1 + (ex.o[0] + my(cur.id[6]).o[0]) * cur.e2[3];
-      a1 = a1 + (ex.o[1] + mz(cur.id[0]).o[1]) * cur.e3[0];
-      a1 = a1 + (ex.o[1] + mz(cur.id[4]).o[1]) * cur.e3[1];
-      a1 = a1 + (ex.o[1] + mz(next.id[0]).o[1]) * next.e3[0];
-      a1 = a1 + (ex.o[1] + mz(next.id[4]).o[1]) * next.e3[1];
+      cpx<T> a1 = mk(T(0), T(0));
+      cfma(a1, ex.o[0] + my(cur.id[0]).o[0], cur.e2[0]);
+      cfma(a1, ex.o[0] + my(cur.id[4]).o[0], cur.e2[1]);
+      cfma(a1, ex.o[0] + my(cur.id[5]).o[0], cur.e2[2]);
+      cfma(a1, ex.o[0] + my(cur.id[6]).o[0], cur.e2[3]);
+      cfma(a1, ex.o[1] + mz(cur.id[0]).o[1], cur.e3[0]);
+      cfma(a1, ex.o[1] + mz(cur.id[4]).o[1], cur.e3[1]);
+      cfma(a1, ex.o[1] + mz(next.id[0]).o[1], next.e3[0]);
+      cfma(a1, ex.o[1] + mz(next.id[4]).o[1], next.e3[1]);
       // row 2: block(2,1) E1 [T21 on plane k] + d2 E2 + block(2,3) E3 [T23 on planes k, k+1]
-      cpx<T> a2 = cmulc(mx(cur.id[0]).o[0] + ey.o[0], cur.e1[0]);
-      a2 = a2 + cmulc(mx(cur.id[1]).o[0] + ey.o[0], cur.e1[1]);
-      a2 = a2 + cmulc(mx(cur.id[2]).o[0] + ey.o[0], cur.e1[2]);
-      a2 = a2 + cmulc(mx(cur.id[3]).o[0] + ey.o[0], cur.e1[3]);
-      a2 = a2 + (ey.o[2] + mz(cur.id[0]).o[2]) * cur.e3[0];
-      a2 = a2 + (ey.o[2] + mz(cur.id[2]).o[2]) * cur.e3[2];
-      a2 = a2 + (ey.o[2] + mz(next.id[0]).o[2]) * next.e3[0];
-      a2 = a2 + (ey.o[2] + mz(next.id[2]).o[2]) * next.e3[2];
+      cpx<T> a2 = mk(T(0), T(0));
+      cfmac(a2, mx(cur.id[0]).o[0] + ey.o[0], cur.e1[0]);
+      cfmac(a2, mx(cur.id[1]).o[0] + ey.o[0], cur.e1[1]);
+      cfmac(a2, mx(cur.id[2]).o[0] + ey.o[0], cur.e1[2]);
+      cfmac(a2, mx(cur.id[3]).o[0] + ey.o[0], cur.e1[3]);
+      cfma(a2, ey.o[2] + mz(cur.id[0]).o[2], cur.e3[0]);
+      cfma(a2, ey.o[2] + mz(cur.id[2]).o[2], cur.e3[2]);
+      cfma(a2, ey.o[2] + mz(next.id[0]).o[2], next.e3[0]);
+      cfma(a2, ey.o[2] + mz(next.id[2]).o[2], next.e3[2]);
       // row 3: block(3,1) E1 [T31 on planes k, k-1] + block(3,2) E2 [T32 on planes k, k-1] + d3 E3
-      cpx<T> a3 = cmulc(mx(cur.id[0]).o[1] + ez.o[1], cur.e1[0]);
-      a3 = a3 + cmulc(mx(cur.id[1]).o[1] + ez.o[1], cur.e1[1]);
-      a3 = a3 + cmulc(mx(prev.id[0]).o[1] + ez.o[1], prev.e1[0]);
-      a3 = a3 + cmulc(mx(prev.id[1]).o[1] + ez.o[1], prev.e1[1]);
-      a3 = a3 + cmulc(my(cur.id[0]).o[2] + ez.o[2], cur.e2[0]);
-      a3 = a3 + cmulc(my(cur.id[5]).o[2] + ez.o[2], cur.e2[2]);
-      a3 = a3 + cmulc(my(prev.id[0]).o[2] + ez.o[2], prev.e2[0]);
-      a3 = a3 + cmulc(my(prev.id[5]).o[2] + ez.o[2], prev.e2[2]);
+      cpx<T> a3 = mk(T(0), T(0));
+      cfmac(a3, mx(cur.id[0]).o[1] + ez.o[1], cur.e1[0]);
+      cfmac(a3, mx(cur.id[1]).o[1] + ez.o[1], cur.e1[1]);
+      cfmac(a3, mx(prev.id[0]).o[1] + ez.o[1], prev.e1[0]);
+      cfmac(a3, mx(prev.id[1]).o[1] + ez.o[1], prev.e1[1]);
+      cfmac(a3, my(cur.id[0]).o[2] + ez.o[2], cur.e2[0]);
+      cfmac(a3, my(cur.id[5]).o[2] + ez.o[2], cur.e2[2]);
+      cfmac(a3, my(prev.id[0]).o[2] + ez.o[2], prev.e2[0]);
+      cfmac(a3, my(prev.id[5]).o[2] + ez.o[2], prev.e2[2]);
       lds[G::addr3(0, k, p)] = ex.d[0] * cur.e1[0] + e8 * a1;
       lds[G::addr3(1, k, p)] = ey.d[1] * cur.e2[0] + e8 * a2;
       lds[G::addr3(2, k, p)] = ez.d[2] * cur.e3[0] + e8 * a3;
