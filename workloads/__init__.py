@@ -102,6 +102,20 @@ class SlabRod:
         return (d < self.half_width) & (z >= self.z0) & (z < self.z1)
 
 
+@dataclasses.dataclass
+class Slab:
+    """Layer lo <= coordinate < hi along `axis` (0=x, 1=y, 2=z), unbounded in the other two
+    directions; lo and hi in [0, 1]."""
+    axis: int
+    lo: float
+    hi: float
+    mat: int
+
+    def contains(self, pts: np.ndarray) -> np.ndarray:
+        c = pts[:, self.axis]
+        return (c >= self.lo) & (c < self.hi)
+
+
 def sample_ids(N: int, shapes: Sequence) -> np.ndarray:
     """uint8 material ids, shape (4, N^3), rows in POINT_SETS order."""
     ids = np.zeros((4, N ** 3), dtype=np.uint8)
