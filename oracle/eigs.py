@@ -14,6 +14,8 @@ import numpy as np
 import scipy.linalg as sla
 import scipy.sparse.linalg as spla
 
+from . import kspace, yee
+
 
 def op_norm_bound(Op) -> float:
     """Max absolute row sum: an upper bound of the 2-norm of a Hermitian matrix."""
@@ -53,3 +55,67 @@ def smallest_positive(Op, m: int, method: str = "auto", return_vectors: bool = F
 def all_eigenvalues(Op) -> np.ndarray:
     """Whole spectrum by dense LAPACK (brute force for tiny grids)."""
     return np.linalg.eigvalsh(Op.toarray())
+
+
+def smallest_positive_matfree(N: int, k, ids: np.ndarray, table: np.ndarray, scheme: str, m: int,
+                              gamma: float | None = None, stencil_m: int = 1, sigma: float = -1.0,
+                              cg_rtol: float = 1e-12, arpack_tol: float = 1e-10,
+                              return_vectors: bool = False):
+    """m smallest strictly positive eigenvalues of Op = A M A^H + gamma B^H B (eq (2.13)) for
+    grids too large to factor: shift-invert Lanczos (ARPACK) about sigma = -1, the inner solves
+    of (Op - sigma I) y = b by conjugate gradients on the product of the sparse factors A, M, B
+    (eqs (2.7), (3.3)-(3.8)); a Rayleigh-Ritz step with Op on the returned vectors gives the
+    final values.  CG is preconditioned per frequency by the inverse of
+    c K_A K_A^H + gamma K_B + |sigma| I (eq (2.31) with the curl part scaled by the mean diagonal
+    inverse permittivity c), which changes the speed of the inner solves, not their solution."""
+    if gamma is None:
+        gamma = yee.gamma_rule(k)
+    A = yee.curl_matrix(N, k, stencil_m)
+    AH = A.conj().T.tocsr()
+    B = yee.div_matrix(N, k, stencil_m)
+    BH = B.conj().T.tocsr()
+    Mx = yee.eps_matrix(N, ids, table, scheme)
+    n = 3 * N ** 3
+
+    def op(x):
+        return A @ (Mx @ (AH @ x)) + gamma * (BH @ (B @ x))
+
+    # curl part scaled by the mean diagonal inverse permittivity over the edge points
+    P = yee.point_tensors(ids, table)
+    c = float(np.mean([P[a][:, a, a].real.mean() for a in range(3)]))
+    K = kspace.symbols_3d(N, k, stencil_m)
+    KA = kspace.curl_symbol(K)
+    KP = c * (KA @ KA.conj().transpose(0, 2, 1)) + gamma * kspace.div_symbol_gram(K) - sigma * np.eye(3)[None]
+    KPinv = np.linalg.inv(KP)                                  # (N^3, 3, 3)
+
+    def prec(v):
+        xk = kspace.F3H(np.asarray(v, dtype=np.complex128).reshape(1, 3, N ** 3), N)[0]
+        zk = np.einsum("pab,bp->ap", KPinv, xk)
+        return kspace.F3(zk[None], N)[0].reshape(n)
+
+    Lop = spla.LinearOperator((n, n), matvec=lambda v: op(v) - sigma * v, dtype=np.complex128)
+    Pop = spla.LinearOperator((n, n), matvec=prec, dtype=np.complex128)
+
+    def solve(b):
+        y, info = spla.cg(Lop, b, rtol=cg_rtol, atol=0.0, M=Pop, maxiter=5000)
+        if info != 0:
+            raise RuntimeError("inner CG did not converge (info=%d)" % info)
+        return y
+
+    want = m + 3 + 2
+    OPinv = spla.LinearOperator((n, n), matvec=solve, dtype=np.complex128)
+    Aop = spla.LinearOperator((n, n), matvec=op, dtype=np.complex128)
+    _, V = spla.eigsh(Aop, k=want, sigma=sigma, which="LM", OPinv=OPinv, tol=arpack_tol,
+                      ncv=min(n, max(4 * want, 24)))
+    # Rayleigh-Ritz with Op on the Lanczos vectors (orthonormalised)
+    Q, _ = np.linalg.qr(V)
+    OQ = np.stack([op(Q[:, j]) for j in range(Q.shape[1])], axis=1)
+    G = Q.conj().T @ OQ
+    w, C = np.linalg.eigh(0.5 * (G + G.conj().T))
+    thr = 1e-10 * max(1.0, float(np.abs(w).max()))
+    keep = np.nonzero(w > thr)[0][:m]
+    if return_vectors:
+        X = Q @ C[:, keep]
+        R = np.stack([op(X[:, j]) - w[j_] * X[:, j] for j, j_ in enumerate(keep)], axis=1)
+        return w[keep], X, np.linalg.norm(R, axis=0)
+    return w[keep]

@@ -51,20 +51,21 @@ def circulant_eigenvalues(first_row: np.ndarray) -> np.ndarray:
     return W @ c
 
 
-def symbols_1d(N: int, k: Sequence[float]):
+def symbols_1d(N: int, k: Sequence[float], m: int = 1):
     """Diagonal of Lambda_1 + i k_a Lambda_0 for each axis a (Prop 2.8, eq (2.28)), from the
-    first rows of D1 and D0 (eq (2.5)) through Lemma 2.1.  Returns three complex arrays (N,)."""
-    D1 = yee.circulant_d1(N).toarray()
-    D0 = yee.circulant_d0(N).toarray()
+    first rows of D1 and D0 (eq (2.5), or their order-2m forms of eq (2.34)) through Lemma 2.1.
+    Returns three complex arrays (N,)."""
+    D1 = yee.circulant_d1(N, m).toarray()
+    D0 = yee.circulant_d0(N, m).toarray()
     l1 = circulant_eigenvalues(D1[0])
     l0 = circulant_eigenvalues(D0[0])
     return [l1 + 1j * k[a] * l0 for a in range(3)]
 
 
-def symbols_3d(N: int, k: Sequence[float]) -> np.ndarray:
+def symbols_3d(N: int, k: Sequence[float], m: int = 1) -> np.ndarray:
     """K_1, K_2, K_3 as full diagonals over the k-space index p = qx + N qy + N^2 qz (eq (2.28)),
     complex (3, N^3)."""
-    s = symbols_1d(N, k)
+    s = symbols_1d(N, k, m)
     qz, qy, qx = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
     return np.stack([s[0][qx.ravel()], s[1][qy.ravel()], s[2][qz.ravel()]])
 
@@ -84,18 +85,18 @@ def div_symbol_gram(K: np.ndarray) -> np.ndarray:
     return np.einsum("ap,bp->pab", K.conj(), K)
 
 
-def precond_matrices(N: int, k: Sequence[float], gamma: float) -> np.ndarray:
+def precond_matrices(N: int, k: Sequence[float], gamma: float, m: int = 1) -> np.ndarray:
     """K_P = K_A K_A^H + gamma K_B per frequency, (N^3, 3, 3) (eq (2.31))."""
-    K = symbols_3d(N, k)
+    K = symbols_3d(N, k, m)
     A = curl_symbol(K)
     return A @ A.conj().transpose(0, 2, 1) + gamma * div_symbol_gram(K)
 
 
-def precond_apply(N: int, k: Sequence[float], gamma: float, r: np.ndarray) -> np.ndarray:
+def precond_apply(N: int, k: Sequence[float], gamma: float, r: np.ndarray, m: int = 1) -> np.ndarray:
     """z = K_P^{-1} r per frequency (eq (2.32)), r of shape (nvec, 3, N^3).  Where K_P is
     singular (only the DC frequency at k = 0, whose modes are the constant fields of Prop 2.5)
     the output is zero."""
-    KP = precond_matrices(N, k, gamma)
+    KP = precond_matrices(N, k, gamma, m)
     r = np.asarray(r, dtype=np.complex128)
     z = np.zeros_like(r)
     scale = np.abs(KP).reshape(KP.shape[0], -1).max(axis=1)
@@ -129,15 +130,15 @@ def edge_permittivity(ids: np.ndarray, table: np.ndarray) -> np.ndarray:
 
 
 def transverse_precond_apply(N: int, k: Sequence[float], gamma: float, E: np.ndarray,
-                             r: np.ndarray) -> np.ndarray:
+                             r: np.ndarray, m: int = 1) -> np.ndarray:
     """z = T_E r with T_E = K_A^{+H} F3^H diag(E) F3 K_A^{+} + (gamma K_B)^{+}, the
     transverse-projection preconditioner (Johnson & Joannopoulos, Opt. Express 8 (2001) 173)
     written for the operator of eq (2.30): the curl part of Op with the inverse permittivity M
     replaced by the diagonal field E, each factor inverted by its Moore-Penrose pseudo-inverse
     per frequency (numpy.linalg.pinv), plus the pseudo-inverse of the penalty block.
     E: real (3, N^3) on the edge points (component c scales the c-edge values), one field for
-    all vectors or (nvec, 3, N^3); r: (nvec, 3, N^3)."""
-    K = symbols_3d(N, k)
+    all vectors or (nvec, 3, N^3); r: (nvec, 3, N^3); m: stencil order 2m (eq (2.34))."""
+    K = symbols_3d(N, k, m)
     A = curl_symbol(K)
     Ap = np.linalg.pinv(A, rcond=1e-12)                      # (N^3, 3, 3)
     Bp = np.linalg.pinv(gamma * div_symbol_gram(K), rcond=1e-12)

@@ -21,22 +21,60 @@ import scipy.sparse as sp
 SCHEMES = ("diagonal", "trivial", "crossdof")
 
 
-def shift_matrix(N: int) -> sp.csr_matrix:
-    """(S u)_i = u_{i-1} (periodic)."""
-    rows = np.arange(N)
-    cols = (rows - 1) % N
-    return sp.csr_matrix((np.ones(N), (rows, cols)), shape=(N, N))
+def stencil_coefficients(m: int):
+    """Coefficients c_s^(1), c_s^(0), s = 1..m, of the order-2m stencils of eq (2.34), as exact
+    rationals: the solution of the m x m system of eq (2.35),
+        sum_t ((2t - 1)/2)^(2s + kind - 2) c_t^(kind) = 1/2 if s = 1 else 0,
+    by Gaussian elimination over the rationals.  Returns (c1, c0), lists of Fraction."""
+    from fractions import Fraction
+
+    if m < 1:
+        raise ValueError("stencil order 2m needs m >= 1")
+    out = []
+    for kind in (1, 0):
+        A = [[Fraction(2 * t - 1, 2) ** (2 * s + kind - 2) for t in range(1, m + 1)] + [Fraction(1, 2) if s == 1 else Fraction(0)]
+             for s in range(1, m + 1)]
+        for col in range(m):
+            piv = next(r for r in range(col, m) if A[r][col] != 0)
+            A[col], A[piv] = A[piv], A[col]
+            for r in range(m):
+                if r != col and A[r][col] != 0:
+                    f = A[r][col] / A[col][col]
+                    A[r] = [a - f * b for a, b in zip(A[r], A[col])]
+        out.append([A[r][m] / A[r][r] for r in range(m)])
+    return out[0], out[1]
 
 
-def circulant_d1(N: int) -> sp.csr_matrix:
-    """D1 of eq (2.5): first row (1, 0, ..., 0, -1)/h, i.e. (D1 u)_i = (u_i - u_{i-1})/h."""
+def circulant_from_taps(N: int, taps) -> sp.csr_matrix:
+    """Periodic N x N matrix with (C u)_j = sum over (offset, weight) of weight * u_{j + offset}
+    (repeated columns add up)."""
+    rows, cols, vals = [], [], []
+    for off, w in taps:
+        rows.append(np.arange(N))
+        cols.append((np.arange(N) + off) % N)
+        vals.append(np.full(N, float(w)))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+
+
+def circulant_d1(N: int, m: int = 1) -> sp.csr_matrix:
+    """D1 of eq (2.5) (m = 1: first row (1, 0, ..., 0, -1)/h, (D1 u)_j = (u_j - u_{j-1})/h), and
+    its order-2m form of eq (2.34): (D1 u)_j = (1/h) sum_s c_s^(1) (u_{j+s-1} - u_{j-s})."""
     h = 1.0 / N
-    return ((sp.identity(N, format="csr") - shift_matrix(N)) / h).tocsr()
+    c1, _ = stencil_coefficients(m)
+    taps = []
+    for s, c in enumerate(c1, start=1):
+        taps += [(s - 1, float(c) / h), (-s, -float(c) / h)]
+    return circulant_from_taps(N, taps)
 
 
-def circulant_d0(N: int) -> sp.csr_matrix:
-    """D0 of eq (2.5): first row (1, 0, ..., 0, 1)/2, i.e. (D0 u)_i = (u_i + u_{i-1})/2."""
-    return ((sp.identity(N, format="csr") + shift_matrix(N)) * 0.5).tocsr()
+def circulant_d0(N: int, m: int = 1) -> sp.csr_matrix:
+    """D0 of eq (2.5) (m = 1: first row (1, 0, ..., 0, 1)/2, (D0 u)_j = (u_j + u_{j-1})/2), and
+    its order-2m form of eq (2.34): (D0 u)_j = sum_s c_s^(0) (u_{j+s-1} + u_{j-s})."""
+    _, c0 = stencil_coefficients(m)
+    taps = []
+    for s, c in enumerate(c0, start=1):
+        taps += [(s - 1, float(c)), (-s, float(c))]
+    return circulant_from_taps(N, taps)
 
 
 def embed(M1: sp.spmatrix, axis: int, N: int) -> sp.csr_matrix:
@@ -49,21 +87,22 @@ def embed(M1: sp.spmatrix, axis: int, N: int) -> sp.csr_matrix:
     return sp.kron(M1, sp.identity(N * N, format="csr"), format="csr")
 
 
-def deriv_blocks(N: int, k: Sequence[float]):
-    """D_i = D_{1,i} + i k_i D_{0,i}, i = 1, 2, 3 (eq (2.6)), complex sparse N^3 x N^3."""
-    D1, D0 = circulant_d1(N), circulant_d0(N)
+def deriv_blocks(N: int, k: Sequence[float], m: int = 1):
+    """D_i = D_{1,i} + i k_i D_{0,i}, i = 1, 2, 3 (eq (2.6)), complex sparse N^3 x N^3, with the
+    order-2m first rows of eq (2.34) (m = 1 is eq (2.5))."""
+    D1, D0 = circulant_d1(N, m), circulant_d0(N, m)
     return [(embed(D1, a, N) + 1j * k[a] * embed(D0, a, N)).tocsr() for a in range(3)]
 
 
-def curl_matrix(N: int, k: Sequence[float]) -> sp.csr_matrix:
+def curl_matrix(N: int, k: Sequence[float], m: int = 1) -> sp.csr_matrix:
     """Outer curl A (edge -> face), eq (2.7): [[0, -D3, D2], [D3, 0, -D1], [-D2, D1, 0]]."""
-    D1, D2, D3 = deriv_blocks(N, k)
+    D1, D2, D3 = deriv_blocks(N, k, m)
     return sp.bmat([[None, -D3, D2], [D3, None, -D1], [-D2, D1, None]], format="csr")
 
 
-def div_matrix(N: int, k: Sequence[float]) -> sp.csr_matrix:
+def div_matrix(N: int, k: Sequence[float], m: int = 1) -> sp.csr_matrix:
     """Divergence B (face -> volume), eq (2.7): [D1, D2, D3]."""
-    D1, D2, D3 = deriv_blocks(N, k)
+    D1, D2, D3 = deriv_blocks(N, k, m)
     return sp.hstack([D1, D2, D3], format="csr")
 
 
@@ -71,8 +110,11 @@ def transfer_matrices(N: int):
     """Cross-DoF transfer matrices of eqs (3.5)-(3.7), read geometrically: T12 averages the four
     y-edges around an x-edge (x in {i-1, i}, y-edge rows j, j+1), T13 the four z-edges around an
     x-edge, T23 the four z-edges around a y-edge.  D0 acts on the axis of the row component,
-    D0^T on the axis of the column component, the identity on the third axis."""
-    D0 = circulant_d0(N)
+    D0^T on the axis of the column component, the identity on the third axis.  The transfer
+    keeps the two-point average of eq (2.5) whatever the order of the curl stencils: eq (3.5)
+    defines it on the four nearest edges, and the bounds of Props 3.7-3.10 rest on its
+    non-negative weights."""
+    D0 = circulant_d0(N, 1)
     D0T = D0.T.tocsr()
     T12 = (embed(D0, 0, N) @ embed(D0T, 1, N)).tocsr()
     T13 = (embed(D0, 0, N) @ embed(D0T, 2, N)).tocsr()
@@ -128,12 +170,13 @@ def gamma_rule(k: Sequence[float]) -> float:
 
 
 def compensated_operator(N: int, k: Sequence[float], ids: np.ndarray, table: np.ndarray,
-                         scheme: str, gamma: float | None = None) -> sp.csr_matrix:
-    """Op = A M A^H + gamma B^H B, eq (2.13); gamma defaults to eq (2.26)."""
+                         scheme: str, gamma: float | None = None, m: int = 1) -> sp.csr_matrix:
+    """Op = A M A^H + gamma B^H B, eq (2.13); gamma defaults to eq (2.26); curl and divergence
+    with the order-2m stencils of eq (2.34) (Remark 2.10: the penalty rule is unchanged)."""
     if gamma is None:
         gamma = gamma_rule(k)
-    A = curl_matrix(N, k)
-    B = div_matrix(N, k)
+    A = curl_matrix(N, k, m)
+    B = div_matrix(N, k, m)
     M = eps_matrix(N, ids, table, scheme)
     Op = (A @ M @ A.conj().T + gamma * (B.conj().T @ B)).tocsr()
     return Op

@@ -268,3 +268,20 @@ def random_inclusions(N: int, seed: int, nk: int = 1, m: int = 16,
         eps_list.append(rotated_eps(rng, 2.0, 14.0))
     ids = sample_ids(N, shapes)
     return Workload("sc%d-random-%d" % (N, seed), N, ids, eps_table(eps_list), sc_kpath(nk), m, scheme)
+
+
+def smooth_isotropic(N: int, k=(math.pi, math.pi, math.pi), m: int = 8) -> Workload:
+    """Simple-cubic cell with the smooth isotropic permittivity eps = 8.9 sin(2 pi (x+y+z)) + 13
+    (Section 4, eq (4.7)).  Every sample point of the Yee cell has x + y + z = (t - 1/2) h mod 1
+    for an integer t, so the field takes N values: material t (t < N <= 64) holds
+    1/eps((t - 1/2) h) I, and each point gets the material of its own t."""
+    if N > 64:
+        raise ValueError("smooth_isotropic needs N <= 64 (one material per value of x+y+z)")
+    ids = np.zeros((4, N ** 3), dtype=np.uint8)
+    for r, which in enumerate(POINT_SETS):
+        s = point_coords(N, which).sum(axis=1)
+        t = np.round(s * N + 0.5).astype(np.int64) % N
+        ids[r] = t.astype(np.uint8)
+    tab = np.stack([np.eye(3, dtype=np.complex128) /
+                    (8.9 * math.sin(2.0 * math.pi * (t - 0.5) / N) + 13.0) for t in range(N)])
+    return Workload("sc%d-smooth-iso" % N, N, ids, tab, np.array([k], dtype=np.float64), m, "diagonal")
