@@ -33,8 +33,10 @@
  * (per calling thread).  No C++ exception crosses this boundary.  A handle is not
  * thread-safe.
  *
- * Memory.  The library owns the handle and its device workspaces (allocated on first use
- * with hipMalloc, grown as needed, released by kc_destroy).
+ * Memory.  The library owns the handle and its device workspaces (allocated on first use,
+ * grown as needed, released by kc_destroy).  Workspace memory comes from the allocator
+ * callbacks given to kc_create (e.g. a framework's caching allocator), or from hipMalloc /
+ * hipFree when none are given.
  */
 #ifndef KCPC_H
 #define KCPC_H
@@ -69,12 +71,48 @@ enum { KC_PREC_FP64 = 0, KC_PREC_FP32 = 1 };
 
 typedef struct kc_op kc_op;
 
+/* Caller allocator for the device workspaces of a handle: alloc returns `bytes` of device
+ * memory on the current device (NULL on failure), free releases a pointer alloc returned
+ * (with the same byte count).  Both are called from the thread that calls the library, never
+ * during a hipGraph capture, and free only after the library has synchronised the device. */
+typedef void* (*kc_alloc_fn)(void* ctx, size_t bytes);
+typedef void (*kc_free_fn)(void* ctx, void* ptr, size_t bytes);
+
+/* Properties of a handle found by kc_create (bits of kc_op_flags). */
+enum {
+  /* Gershgorin's bound does not prove the discrete inverse permittivity M positive definite:
+   * some row's diagonal does not exceed the sum of the moduli of its off-diagonal entries
+   * (strict diagonal dominance, the sufficient condition behind Props 3.8 and 3.10; for
+   * Trivial, the rows of eq (3.4)).  M may still be HPD; the solver runs anyway. */
+  KC_FLAG_HPD_UNPROVEN = 1
+};
+
+/* Per-k-point warnings (bits of kc_kpoint_flags). */
+enum {
+  /* some |k_i| > pi: the lower bound of Lemma 2.4 (2) on the spectrum of the penalty term
+   * (eq (2.20)) and with it the guarantee of the gamma rule, eq (2.26), is not given */
+  KC_KFLAG_K_OUTSIDE = 1,
+  /* after the last kc_solve: lambda_m >= gamma * s_min (kc_spurious_bound), so a computed
+   * eigenvalue may belong to the penalty term's spurious spectrum (Prop 2.3, Remark 2.6);
+   * a larger gamma (kc_set_kpoints) separates them */
+  KC_KFLAG_SPURIOUS_RISK = 2
+};
+
 /* 1 if N is a supported grid division (FFT length), else 0.  Supported: 4, 6, 8, 12, 16,
  * 24, 32, 48, 64, 96, 128. */
 int kc_supported_n(int N);
 
 /*
  * Create an operator for grid division N and an inverse-permittivity field.
+ *   lattice_host : NULL or float64 [3][3], the primitive lattice vectors as rows (lattice
+ *                  constant 1).  Only the simple-cubic lattice (the identity) is supported;
+ *                  other lattices (the coordinate transform of Section 2.2) give
+ *                  KC_ERR_UNSUPPORTED.
+ *   stencil_m    : 1..5, order 2m of the finite-difference stencils of the curl and
+ *                  divergence (eq (2.34), coefficients from eq (2.35), Table 1); 1 is the
+ *                  second-order Yee scheme of eq (2.5).  The cross-DoF transfer T of eq (3.7)
+ *                  keeps its two-point average at every order.
+ *   eps_scheme   : KC_EPS_DIAGONAL / KC_EPS_TRIVIAL / KC_EPS_CROSSDOF.
  *   mat_ids_host : uint8 [4][N^3] material ids of the x-edge, y-edge, z-edge and volume
  *                  points (eqs (2.1)-(2.3), eq (3.2)); index i + N j + N^2 k.  The points of
  *                  cell (i, j, k) are ((i-1/2)h, jh, kh), (ih, (j-1/2)h, kh),
@@ -82,21 +120,42 @@ int kc_supported_n(int N);
  *   eps_inv_host : float64 [n_mat][3][3][2]: the complex inverse permittivity of each
  *                  material (row-major, (re, im)); must be Hermitian with eigenvalues in
  *                  (0, 1] (Assumption 3.1), else KC_ERR_NOT_HPD.  Material 0 is usually air.
- *   eps_scheme   : KC_EPS_DIAGONAL / KC_EPS_TRIVIAL / KC_EPS_CROSSDOF.
- * The ids and the table are copied; the caller keeps ownership of its buffers.
+ *   alloc, free_fn, alloc_ctx : caller allocator of every device buffer the handle owns
+ *                  (both NULL: hipMalloc / hipFree; exactly one NULL is KC_ERR_INVALID_ARG).
+ *   stream       : stream of the uploads (the call returns when they are complete).
+ * The ids and the table are copied; the caller keeps ownership of its buffers.  Every argument
+ * is checked before any device work.  kc_op_flags reports whether M was proven HPD.
  */
-int kc_create(int N, int eps_scheme, const uint8_t* mat_ids_host, int n_mat,
-              const double* eps_inv_host, kc_op** out);
+int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, const uint8_t* mat_ids_host,
+              int n_mat, const double* eps_inv_host, kc_alloc_fn alloc, kc_free_fn free_fn, void* alloc_ctx,
+              void* stream, kc_op** out);
+
+/* KC_FLAG_* bits of a handle (0: M proven HPD by Gershgorin's bound). */
+int kc_op_flags(const kc_op* op, int* flags_host);
 
 /*
  * Set the Bloch wave vectors (Cartesian, lattice constant 1): k_host float64 [nk][3].
  * gamma_host: float64 [nk] penalty coefficients, or NULL for the rule of Remark 2.6,
- * eq (2.26) (4 pi^2 if k = 0 or |k| >= 1, else 4 pi^2 / |k|^2).
+ * eq (2.26) (4 pi^2 if k = 0 or |k| >= 1, else 4 pi^2 / |k|^2).  Every k and gamma is checked
+ * (finite; gamma > 0) before the handle changes: a rejected call leaves the previous k-points in
+ * place.  A k-point with some |k_i| > pi is accepted with KC_KFLAG_K_OUTSIDE set.
  */
 int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_host);
 
 /* Penalty coefficients in use: gamma_host float64 [nk]. */
 int kc_get_gamma(const kc_op* op, double* gamma_host);
+
+/* KC_KFLAG_* bits of every k-point: flags_host int32 [nk]. */
+int kc_kpoint_flags(const kc_op* op, int* flags_host);
+
+/*
+ * gamma_k * s_min(k) per k-point (float64 [nk]): s_min is the smallest positive eigenvalue of
+ * the penalty term's symbol, min over frequencies p of |K_1(q_x)|^2 + |K_2(q_y)|^2 + |K_3(q_z)|^2
+ * with s(p) > 0 (|k|^2 for k != 0 with the second-order stencils, Lemma 2.4 (2)).  By Prop 2.3
+ * the spurious eigenvalues of Op are gamma s(p) >= this bound, so computed eigenvalues below it
+ * are physical.
+ */
+int kc_spurious_bound(const kc_op* op, double* bound_host);
 
 /*
  * y = Op_k x for nvec vectors (k-space coefficients, eq (2.30)).  Vector v uses the k-point
@@ -160,6 +219,15 @@ int kc_block_gram(int nb, size_t n, int nc, const void* S, const void* AS, void*
  */
 int kc_block_update(int nb, size_t n, int mb, void* S, void* AS, const void* C, const double* theta, void* R,
                     double* res, double* xnorm2, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Real-space face fields of k-space coefficients, H = F3 x (eq (2.30), Lemma 2.1): per component
+ * H[j] = N^{-3/2} sum_q x[q] exp(+2 pi i (j . q) / N).  x, H: device complex128 [nvec][3][N^3]
+ * (H in the index order i + N j + N^2 k of the face points of eqs (2.1)-(2.3)); x == H is
+ * allowed.  kc_to_kspace is the inverse, x = F3^H H.
+ */
+int kc_to_real_space(kc_op* op, int nvec, const void* x, void* H, void* stream);
+int kc_to_kspace(kc_op* op, int nvec, const void* H, void* x, void* stream);
 
 /*
  * Unnormalised 3D DFT of nvec scalar grids along x, y and z:

@@ -14,6 +14,38 @@ KC_EPS_DIAGONAL, KC_EPS_TRIVIAL, KC_EPS_CROSSDOF = 0, 1, 2
 KC_PREC_FP64, KC_PREC_FP32 = 0, 1
 KC_OK, KC_ERR_NO_CONVERGENCE = 0, 6
 KC_PRECOND_DIAG, KC_PRECOND_LEARNED, KC_PRECOND_TRANSVERSE = 0, 1, 2
+KC_FLAG_HPD_UNPROVEN = 1
+KC_KFLAG_K_OUTSIDE, KC_KFLAG_SPURIOUS_RISK = 1, 2
+
+# caller allocator callbacks of kc_create (include/kcpc.h)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+
+
+def _torch_alloc(ctx, nbytes):
+    """Device memory for a handle's workspaces from PyTorch's caching allocator (current device
+    and stream); NULL on failure (the library then reports KC_ERR_ALLOC)."""
+    try:
+        import torch
+
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                      torch.cuda.current_stream()))
+    except Exception:
+        return None
+
+
+def _torch_free(ctx, ptr, nbytes):
+    try:
+        import torch
+
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+_torch_alloc_c = _ALLOC_FN(_torch_alloc)
+_torch_free_c = _FREE_FN(_torch_free)
+_live_ops = None  # weak set of live handles, destroyed at exit before torch shuts down
 
 _lib = None
 
@@ -55,9 +87,14 @@ def lib():
         L = ctypes.CDLL(lib_path)
         vp, i32, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
         L.kc_supported_n.argtypes = [i32]
-        L.kc_create.argtypes = [i32, i32, vp, i32, vp, ctypes.POINTER(vp)]
+        L.kc_create.argtypes = [i32, vp, i32, i32, vp, i32, vp, _ALLOC_FN, _FREE_FN, vp, vp, ctypes.POINTER(vp)]
+        L.kc_op_flags.argtypes = [vp, vp]
         L.kc_set_kpoints.argtypes = [vp, i32, vp, vp]
         L.kc_get_gamma.argtypes = [vp, vp]
+        L.kc_kpoint_flags.argtypes = [vp, vp]
+        L.kc_spurious_bound.argtypes = [vp, vp]
+        L.kc_to_real_space.argtypes = [vp, i32, vp, vp, vp]
+        L.kc_to_kspace.argtypes = [vp, i32, vp, vp, vp]
         L.kc_apply.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
         L.kc_precond.argtypes = [vp, i32, i32, i32, vp, vp, vp]
         L.kc_apply_timed.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp, vp, vp]
@@ -96,7 +133,19 @@ def lib():
         L.kc_last_error.restype = ctypes.c_char_p
         _ = dp
         _lib = L
+        import atexit
+        import weakref
+
+        global _live_ops
+        _live_ops = weakref.WeakSet()
+        atexit.register(_destroy_live_ops)
     return _lib
+
+
+def _destroy_live_ops():
+    """Release every live handle while torch (whose allocator backs their memory) is still up."""
+    for op in list(_live_ops or ()):
+        op.close()
 
 
 def _status_name(st: int) -> str:
@@ -116,6 +165,13 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _numel(t, n: int, what: str):
+    """The library touches exactly n elements of t: anything else is refused here (the C ABI takes
+    raw pointers and cannot check)."""
+    if int(t.numel()) != int(n):
+        raise ValueError("%s must hold %d elements, got %d (shape %s)" % (what, n, t.numel(), tuple(t.shape)))
 
 
 def _dev_ptr(t, dtype_name: str, what: str):
@@ -140,10 +196,12 @@ def kc_fft3d(x, sign: int, prec: int = KC_PREC_FP64, out=None, stream=None):
     import torch
 
     N = int(round(x.shape[-1] ** (1.0 / 3.0))) if x.dim() == 2 else int(x.shape[-1])
-    nvec = x.shape[0]
+    nvec = int(x.shape[0])
     dt = "torch.complex128" if prec == KC_PREC_FP64 else "torch.complex64"
+    _numel(x, nvec * N ** 3, "x")
     if out is None:
         out = torch.empty_like(x)
+    _numel(out, nvec * N ** 3, "out")
     _check(lib().kc_fft3d(N, nvec, int(sign), int(prec), _dev_ptr(x, dt, "x"), _dev_ptr(out, dt, "out"),
                           _stream(stream)), "kc_fft3d")
     return out
@@ -218,26 +276,97 @@ def block_update(S, AS, C, theta, R=None, res=None, xnorm2=None, work=None, stre
 
 
 class Op:
-    """Handle of one operator (grid, inverse-permittivity field, k-points)."""
+    """Handle of one operator (grid, inverse-permittivity field, k-points).
 
-    def __init__(self, N: int, scheme: int, ids: np.ndarray, table: np.ndarray):
+    lattice: None (simple cubic) or (3, 3) lattice vectors as rows; stencil_m: order 2m of the
+    curl/divergence stencils (1..5); allocator: "torch" (PyTorch's caching allocator backs the
+    handle's device workspaces) or "hip" (the library's hipMalloc)."""
+
+    def __init__(self, N: int, scheme: int, ids: np.ndarray, table: np.ndarray, lattice=None,
+                 stencil_m: int = 1, allocator: str = "torch", stream=None):
         ids = np.ascontiguousarray(ids, dtype=np.uint8)
-        assert ids.shape == (4, N ** 3), ids.shape
+        if ids.shape != (4, N ** 3):
+            raise ValueError("ids must have shape (4, N^3), got %s" % (ids.shape,))
         tab = np.ascontiguousarray(np.asarray(table, dtype=np.complex128))
-        assert tab.ndim == 3 and tab.shape[1:] == (3, 3)
+        if tab.ndim != 3 or tab.shape[1:] != (3, 3):
+            raise ValueError("table must have shape (n_mat, 3, 3)")
         tab_r = np.ascontiguousarray(tab.view(np.float64).reshape(tab.shape[0], 3, 3, 2))
+        lat = None
+        if lattice is not None:
+            lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(3, 3))
+        if allocator not in ("torch", "hip"):
+            raise ValueError("allocator must be 'torch' or 'hip'")
+        L = lib()
+        al, fr = (_torch_alloc_c, _torch_free_c) if allocator == "torch" else (_ALLOC_FN(), _FREE_FN())
         h = ctypes.c_void_p()
-        _check(lib().kc_create(int(N), int(scheme), ids.ctypes.data_as(ctypes.c_void_p), int(tab.shape[0]),
-                               tab_r.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)), "kc_create")
+        _check(L.kc_create(int(N), None if lat is None else lat.ctypes.data_as(ctypes.c_void_p), int(stencil_m),
+                           int(scheme), ids.ctypes.data_as(ctypes.c_void_p), int(tab.shape[0]),
+                           tab_r.ctypes.data_as(ctypes.c_void_p), al, fr, None,
+                           None if stream is None else _stream(stream),
+                           ctypes.byref(h)), "kc_create")
         self._h = h
         self.N = int(N)
         self.nk = 0
+        self.stencil_m = int(stencil_m)
+        _live_ops.add(self)
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value and _lib is not None:
             _lib.kc_destroy(h)
-            self._h = None
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def n3(self) -> int:
+        return self.N ** 3
+
+    def flags(self) -> int:
+        f = ctypes.c_int(0)
+        _check(lib().kc_op_flags(self._h, ctypes.byref(f)), "kc_op_flags")
+        return int(f.value)
+
+    def kpoint_flags(self) -> np.ndarray:
+        f = np.zeros(self.nk, dtype=np.int32)
+        _check(lib().kc_kpoint_flags(self._h, f.ctypes.data_as(ctypes.c_void_p)), "kc_kpoint_flags")
+        return f
+
+    def spurious_bound(self) -> np.ndarray:
+        b = np.zeros(self.nk)
+        _check(lib().kc_spurious_bound(self._h, b.ctypes.data_as(ctypes.c_void_p)), "kc_spurious_bound")
+        return b
+
+    def _vpk(self, nvec: int, vecs_per_k: Optional[int]) -> int:
+        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        return max(vpk, 1)
+
+    def to_real_space(self, x, out=None, stream=None):
+        """H = F3 x (face fields) for x complex128 (nvec, 3, N^3) on the GPU; out may be x."""
+        import torch
+
+        nvec = int(x.shape[0])
+        _numel(x, nvec * 3 * self.n3, "x")
+        if out is None:
+            out = torch.empty_like(x)
+        _numel(out, nvec * 3 * self.n3, "H")
+        _check(lib().kc_to_real_space(self._h, nvec, _dev_ptr(x, "torch.complex128", "x"),
+                                      _dev_ptr(out, "torch.complex128", "H"), _stream(stream)), "kc_to_real_space")
+        return out
+
+    def to_kspace(self, H, out=None, stream=None):
+        """x = F3^H H for face fields H complex128 (nvec, 3, N^3) on the GPU; out may be H."""
+        import torch
+
+        nvec = int(H.shape[0])
+        _numel(H, nvec * 3 * self.n3, "H")
+        if out is None:
+            out = torch.empty_like(H)
+        _numel(out, nvec * 3 * self.n3, "x")
+        _check(lib().kc_to_kspace(self._h, nvec, _dev_ptr(H, "torch.complex128", "H"),
+                                  _dev_ptr(out, "torch.complex128", "x"), _stream(stream)), "kc_to_kspace")
+        return out
 
     def set_kpoints(self, k: np.ndarray, gamma: Optional[np.ndarray] = None):
         k = np.ascontiguousarray(np.asarray(k, dtype=np.float64).reshape(-1, 3))
@@ -256,10 +385,12 @@ class Op:
         """y = Op x; x complex128 (nvec, 3, N^3) on the GPU."""
         import torch
 
-        nvec = x.shape[0]
+        nvec = int(x.shape[0])
+        _numel(x, nvec * 3 * self.n3, "x")
         if out is None:
             out = torch.empty_like(x)
-        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _numel(out, nvec * 3 * self.n3, "y")
+        vpk = self._vpk(nvec, vecs_per_k)
         _check(lib().kc_apply(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(x, "torch.complex128", "x"),
                               _dev_ptr(out, "torch.complex128", "y"), int(prec), _stream(stream)), "kc_apply")
         return out
@@ -269,10 +400,12 @@ class Op:
         """kc_apply with per-pass HIP-event timings; returns (y, pass_ms)."""
         import torch
 
-        nvec = x.shape[0]
+        nvec = int(x.shape[0])
+        _numel(x, nvec * 3 * self.n3, "x")
         if out is None:
             out = torch.empty_like(x)
-        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _numel(out, nvec * 3 * self.n3, "y")
+        vpk = self._vpk(nvec, vecs_per_k)
         ms = np.zeros(6)
         npass = ctypes.c_int(0)
         _check(lib().kc_apply_timed(self._h, int(ik0), int(nvec), max(vpk, 1),
@@ -284,10 +417,12 @@ class Op:
     def precond(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, out=None, stream=None):
         import torch
 
-        nvec = r.shape[0]
+        nvec = int(r.shape[0])
+        _numel(r, nvec * 3 * self.n3, "r")
         if out is None:
             out = torch.empty_like(r)
-        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _numel(out, nvec * 3 * self.n3, "z")
+        vpk = self._vpk(nvec, vecs_per_k)
         _check(lib().kc_precond(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(r, "torch.complex128", "r"),
                                 _dev_ptr(out, "torch.complex128", "z"), _stream(stream)), "kc_precond")
         return out
@@ -297,10 +432,14 @@ class Op:
         """z = T_E r; efield None (E_c = 1/(eps^-1)_cc) or float32 [nk_used][3][N^3]."""
         import torch
 
-        nvec = r.shape[0]
+        nvec = int(r.shape[0])
+        _numel(r, nvec * 3 * self.n3, "r")
         if out is None:
             out = torch.empty_like(r)
-        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _numel(out, nvec * 3 * self.n3, "z")
+        vpk = self._vpk(nvec, vecs_per_k)
+        if efield is not None:
+            _numel(efield, ((nvec - 1) // vpk + 1) * 3 * self.n3, "efield")
         ef = None if efield is None else _dev_ptr(efield, "torch.float32", "efield")
         _check(lib().kc_precond_transverse(self._h, int(ik0), int(nvec), max(vpk, 1),
                                            _dev_ptr(r, "torch.complex128", "r"), _dev_ptr(out, "torch.complex128", "z"),
@@ -309,8 +448,14 @@ class Op:
 
     def tp_grad(self, r, e, w, g, ik0: int = 0, vecs_per_k: Optional[int] = None, stream=None):
         """g (float32 [nvec/vpk][3][N^3]) += d/dE sum_j w_j Re<e_j, T_E r_j> (w float64 [nvec])."""
-        nvec = r.shape[0]
-        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        nvec = int(r.shape[0])
+        vpk = self._vpk(nvec, vecs_per_k)
+        if nvec % vpk != 0:
+            raise ValueError("nvec must be a multiple of vecs_per_k")
+        _numel(r, nvec * 3 * self.n3, "r")
+        _numel(e, nvec * 3 * self.n3, "e")
+        _numel(w, nvec, "w")
+        _numel(g, (nvec // vpk) * 3 * self.n3, "g")
         _check(lib().kc_tp_grad(self._h, int(ik0), int(nvec), max(vpk, 1), _dev_ptr(r, "torch.complex128", "r"),
                                 _dev_ptr(e, "torch.complex128", "e"), _dev_ptr(w, "torch.float64", "w"),
                                 _dev_ptr(g, "torch.float32", "g"), _stream(stream)), "kc_tp_grad")
@@ -333,7 +478,10 @@ class Op:
         if x_init is not None:
             if tuple(x_init.shape[:2]) != (nk, m):
                 raise ValueError("x_init must hold (nk, m) start vectors")
+            _numel(x_init, nk * m * 3 * self.n3, "x_init")
             o.x_init = _dev_ptr(x_init, "torch.complex128", "x_init")
+        if X_out is not None:
+            _numel(X_out, nk * m * 3 * self.n3, "X_out")
         eig = np.zeros((nk, m))
         res = np.zeros((nk, m))
         its = np.zeros(nk, dtype=np.int32)
@@ -366,6 +514,7 @@ class Op:
 
         if out is None:
             out = torch.empty((nk, self.N ** 3, 32), dtype=torch.bfloat16, device=torch.device("cuda"))
+        _numel(out, nk * self.n3 * 32, "feat")
         _check(lib().kc_net_features(self._h, int(ik0), int(nk), _dev_ptr(out, "torch.bfloat16", "feat"),
                                      _stream(stream)), "kc_net_features")
         return out
@@ -376,6 +525,7 @@ class Op:
 
         if out is None:
             out = torch.empty((nk, 3, self.N ** 3), dtype=torch.float32, device=torch.device("cuda"))
+        _numel(out, nk * 3 * self.n3, "efield")
         _check(lib().kc_net_efield(self._h, int(ik0), int(nk), _dev_ptr(out, "torch.float32", "efield"),
                                    _stream(stream)), "kc_net_efield")
         return out
@@ -384,10 +534,12 @@ class Op:
                         out=None, stream=None):
         import torch
 
-        nvec = r.shape[0]
+        nvec = int(r.shape[0])
+        _numel(r, nvec * 3 * self.n3, "r")
         if out is None:
             out = torch.empty_like(r)
-        vpk = nvec if vecs_per_k is None else int(vecs_per_k)
+        _numel(out, nvec * 3 * self.n3, "z")
+        vpk = self._vpk(nvec, vecs_per_k)
         _check(lib().kc_precond_learned(self._h, int(ik0), int(nvec), max(vpk, 1),
                                         _dev_ptr(r, "torch.complex128", "r"), _dev_ptr(out, "torch.complex128", "z"),
                                         int(prec), _stream(stream)), "kc_precond_learned")
@@ -426,16 +578,20 @@ class Net:
         """x: bf16 [batch][N^3][32] -> float32 [batch][N^3][16]."""
         import torch
 
-        batch = x.shape[0]
+        batch = int(x.shape[0])
+        _numel(x, batch * N ** 3 * 32, "x")
         if out is None:
             out = torch.empty((batch, N ** 3, 16), dtype=torch.float32, device=x.device)
+        _numel(out, batch * N ** 3 * 16, "out")
         _check(lib().kc_net_forward(self._h, int(N), int(batch), _dev_ptr(x, "torch.bfloat16", "x"),
                                     _dev_ptr(out, "torch.float32", "out"), _stream(stream)), "kc_net_forward")
         return out
 
     def gradients(self, x, target, N: int, host_grads: bool = True, stream=None):
         """MSE loss and parameter gradients (numpy float32, or None with host_grads=False)."""
-        batch = x.shape[0]
+        batch = int(x.shape[0])
+        _numel(x, batch * N ** 3 * 32, "x")
+        _numel(target, batch * N ** 3 * 16, "target")
         loss = ctypes.c_double(0.0)
         g = np.zeros(self.param_count(), dtype=np.float32) if host_grads else None
         _check(lib().kc_net_gradients(self._h, int(N), int(batch), _dev_ptr(x, "torch.bfloat16", "x"),
@@ -446,7 +602,9 @@ class Net:
 
     def backward(self, x, gout, N: int, host_grads: bool = True, stream=None):
         """Parameter gradients for the output gradient gout (float32 [batch][N^3][16])."""
-        batch = x.shape[0]
+        batch = int(x.shape[0])
+        _numel(x, batch * N ** 3 * 32, "x")
+        _numel(gout, batch * N ** 3 * 16, "gout")
         g = np.zeros(self.param_count(), dtype=np.float32) if host_grads else None
         _check(lib().kc_net_backward(self._h, int(N), int(batch), _dev_ptr(x, "torch.bfloat16", "x"),
                                      _dev_ptr(gout, "torch.float32", "gout"),
@@ -459,5 +617,5 @@ class Net:
                "kc_net_adam_step")
 
 
-def kc_create(N: int, scheme: int, ids: np.ndarray, table: np.ndarray) -> Op:
-    return Op(N, scheme, ids, table)
+def kc_create(N: int, scheme: int, ids: np.ndarray, table: np.ndarray, **kw) -> Op:
+    return Op(N, scheme, ids, table, **kw)

@@ -21,23 +21,38 @@ int DevBuf::ensure(size_t n) {
   if (n <= bytes && p != nullptr) return KC_OK;
   release();
   if (n == 0) return KC_OK;
-  hipError_t e = hipMalloc(&p, n);
-  if (e != hipSuccess) {
-    p = nullptr;
-    set_error(std::string("hipMalloc(") + std::to_string(n) + "): " + hipGetErrorString(e));
-    return KC_ERR_ALLOC;
+  if (al != nullptr && al->alloc != nullptr) {
+    p = al->alloc(al->ctx, n);
+    if (p == nullptr) {
+      set_error("caller allocator returned NULL for " + std::to_string(n) + " bytes");
+      return KC_ERR_ALLOC;
+    }
+    // the caller's memory may have been in use on another stream until now
+    KC_HIP(hipDeviceSynchronize());
+  } else {
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      set_error(std::string("hipMalloc(") + std::to_string(n) + "): " + hipGetErrorString(e));
+      return KC_ERR_ALLOC;
+    }
   }
-  e = hipMemset(p, 0, n);
+  bytes = n;
+  hipError_t e = hipMemset(p, 0, n);
   if (e != hipSuccess) {
     set_error(std::string("hipMemset: ") + hipGetErrorString(e));
     return KC_ERR_HIP;
   }
-  bytes = n;
   return KC_OK;
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (al != nullptr && al->free != nullptr)
+      al->free(al->ctx, p, bytes);
+    else
+      (void)hipFree(p);
+  }
   p = nullptr;
   bytes = 0;
 }
@@ -68,10 +83,91 @@ static void make_twiddles(int N, std::vector<c64>& d, std::vector<c32>& f) {
 }
 
 template <typename T>
-static int upload(DevBuf& b, const std::vector<T>& v) {
+static int upload(DevBuf& b, const std::vector<T>& v, hipStream_t s = nullptr) {
   KC_TRY(b.ensure(v.size() * sizeof(T)));
-  KC_HIP(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  KC_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  KC_HIP(hipStreamSynchronize(s));
   return KC_OK;
+}
+
+// Coefficients c_s^(1), c_s^(0) (s = 1..m) of the order-2m stencils of eq (2.34): the m x m
+// system of eq (2.35), sum_t ((2t - 1)/2)^(2s + kind - 2) c_t = 1/2 for s = 1 and 0 for s > 1,
+// solved by Gaussian elimination with partial pivoting in long double (the solution is a set of
+// small dyadic-like rationals, Table 1; the result is exact to double rounding).
+static void stencil_coeffs(int m, double c1[5], double c0[5]) {
+  for (int kind = 1; kind >= 0; --kind) {
+    long double A[5][6] = {};
+    for (int s = 1; s <= m; ++s) {
+      for (int t = 1; t <= m; ++t) {
+        const long double b = (2.0L * t - 1.0L) / 2.0L;
+        long double pw = 1.0L;
+        for (int e = 0; e < 2 * s + kind - 2; ++e) pw *= b;
+        A[s - 1][t - 1] = pw;
+      }
+      A[s - 1][m] = (s == 1) ? 0.5L : 0.0L;
+    }
+    for (int c = 0; c < m; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < m; ++r)
+        if (std::fabs((double)A[r][c]) > std::fabs((double)A[piv][c])) piv = r;
+      for (int j = 0; j <= m; ++j) std::swap(A[c][j], A[piv][j]);
+      for (int r = 0; r < m; ++r) {
+        if (r == c) continue;
+        const long double f = A[r][c] / A[c][c];
+        for (int j = c; j <= m; ++j) A[r][j] -= f * A[c][j];
+      }
+    }
+    for (int s = 0; s < 5; ++s) (kind ? c1 : c0)[s] = s < m ? (double)(A[s][m] / A[s][s]) : 0.0;
+  }
+}
+
+// Gershgorin test of the discrete inverse permittivity M: every row's diagonal entry exceeds the
+// sum of the moduli of its off-diagonal entries (then the Hermitian M is positive definite).
+// Trivial (eq (3.4)): row c of cell p couples to the two other components of the same cell
+// through the volume-point entries.  CrossDoF (eq (3.8) with the entries sampled per point set):
+// the (c, d) block is (Q_c T + T Q_d) / 2 with four transfer weights 1/4, so an entry between
+// a c-edge P and a d-edge S is (eps_cd(P) + eps_cd(S)) / 8; for c > d the conjugate transpose.
+static bool gershgorin_hpd(int N, int scheme, const uint8_t* ids, const double* tab) {
+  if (scheme == KC_EPS_DIAGONAL) return true;  // diagonal entries are positive (Assumption 3.1)
+  const size_t N3 = (size_t)N * N * N;
+  auto ent = [&](int mat, int r, int c) {
+    const double* t = tab + ((size_t)mat * 9 + r * 3 + c) * 2;
+    return std::hypot(t[0], t[1]);
+  };
+  auto idx = [&](int i, int j, int k) {
+    return (size_t)((i % N + N) % N) + (size_t)N * ((j % N + N) % N) + (size_t)N * N * ((k % N + N) % N);
+  };
+  for (int k = 0; k < N; ++k)
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i) {
+        const size_t p = idx(i, j, k);
+        for (int c = 0; c < 3; ++c) {
+          const double d = tab[((size_t)ids[c * N3 + p] * 9 + c * 4) * 2];
+          double off = 0.0;
+          if (scheme == KC_EPS_TRIVIAL) {
+            for (int e = 0; e < 3; ++e)
+              if (e != c) off += ent(ids[3 * N3 + p], c, e);
+          } else {
+            // the four e-edges nearest to the c-edge of cell p (the transfer stencils of
+            // eqs (3.5)-(3.7) read geometrically, and their transposes): cell offsets {0, -1}
+            // along the c axis and {0, +1} along the e axis, for c < e and for c > e alike
+            for (int e = 0; e < 3; ++e) {
+              if (e == c) continue;
+              const double ep = ent(ids[c * N3 + p], c, e);
+              for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                  int o[3] = {0, 0, 0};
+                  o[c] = -a;
+                  o[e] = b;
+                  const size_t q = idx(i + o[0], j + o[1], k + o[2]);
+                  off += 0.125 * (ep + ent(ids[e * N3 + q], c, e));
+                }
+            }
+          }
+          if (!(d > off)) return false;
+        }
+      }
+  return true;
 }
 
 // Hermitian 3x3 check of Assumption 3.1 (eigenvalues in (0, 1]): Cholesky of A (positive
@@ -117,6 +213,12 @@ static int check_table(int n_mat, const double* t) {
   return KC_OK;
 }
 
+// v *= a over a flat array (grid-stride)
+__global__ void k_scale(c64* v, size_t n, double a) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v[i] = a * v[i];
+}
+
 // per-N twiddle tables for kc_fft3d (one set per process and device)
 struct TwCache {
   std::mutex mu;
@@ -135,19 +237,33 @@ extern "C" {
 
 int kc_supported_n(int N) { return supported_n(N) ? 1 : 0; }
 
-int kc_create(int N, int eps_scheme, const uint8_t* mat_ids_host, int n_mat, const double* eps_inv_host,
-              kc_op** out) {
+int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, const uint8_t* mat_ids_host,
+              int n_mat, const double* eps_inv_host, kc_alloc_fn alloc, kc_free_fn free_fn, void* alloc_ctx,
+              void* stream, kc_op** out) {
   KC_ARG(out != nullptr, "out is NULL");
   *out = nullptr;
   if (!supported_n(N)) {
     set_error("grid division N=" + std::to_string(N) + " is not a supported FFT length");
     return KC_ERR_UNSUPPORTED;
   }
+  if (lattice_host != nullptr) {
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        KC_ARG(std::isfinite(lattice_host[r * 3 + c]), "non-finite lattice vector");
+        if (std::fabs(lattice_host[r * 3 + c] - (r == c ? 1.0 : 0.0)) > 1e-12) {
+          set_error("only the simple-cubic lattice (identity lattice vectors) is supported");
+          return KC_ERR_UNSUPPORTED;
+        }
+      }
+  }
+  KC_ARG(stencil_m >= 1 && stencil_m <= 5, "stencil_m must be in [1, 5] (orders 2 to 10)");
+  KC_ARG((alloc == nullptr) == (free_fn == nullptr), "alloc and free_fn must be given together");
   KC_ARG(eps_scheme == KC_EPS_DIAGONAL || eps_scheme == KC_EPS_TRIVIAL || eps_scheme == KC_EPS_CROSSDOF,
          "eps_scheme");
   KC_ARG(mat_ids_host != nullptr && eps_inv_host != nullptr, "NULL ids or table");
   KC_ARG(n_mat >= 1 && n_mat <= KC_MAX_MAT, "n_mat must be in [1, 64]");
   KC_TRY(check_table(n_mat, eps_inv_host));
+  hipStream_t hs = (hipStream_t)stream;
   const size_t N3 = (size_t)N * N * N;
   std::vector<uint32_t> packed(N3);
   for (size_t p = 0; p < N3; ++p) {
@@ -166,6 +282,12 @@ int kc_create(int N, int eps_scheme, const uint8_t* mat_ids_host, int n_mat, con
   op->N = N;
   op->scheme = eps_scheme;
   op->n_mat = n_mat;
+  op->stencil_m = stencil_m;
+  op->alloc.alloc = alloc;
+  op->alloc.free = free_fn;
+  op->alloc.ctx = alloc_ctx;
+  op->bind_allocator();
+  if (!gershgorin_hpd(N, eps_scheme, mat_ids_host, eps_inv_host)) op->flags |= KC_FLAG_HPD_UNPROVEN;
   op->eps_host.assign(eps_inv_host, eps_inv_host + (size_t)n_mat * 18);
   // permittivity entries scaled by 1/N^3 (normalisation of the two unnormalised DFTs)
   const double sc = 1.0 / (double)N3;
@@ -186,14 +308,14 @@ int kc_create(int N, int eps_scheme, const uint8_t* mat_ids_host, int n_mat, con
       e32[m].o[q] = mk((float)re, (float)im);
     }
   }
-  int st = upload(op->ids, packed);
-  if (st == KC_OK) st = upload(op->eps64, e64);
-  if (st == KC_OK) st = upload(op->eps32, e32);
+  int st = upload(op->ids, packed, hs);
+  if (st == KC_OK) st = upload(op->eps64, e64, hs);
+  if (st == KC_OK) st = upload(op->eps32, e32, hs);
   std::vector<c64> twd;
   std::vector<c32> twf;
   make_twiddles(N, twd, twf);
-  if (st == KC_OK) st = upload(op->tw64, twd);
-  if (st == KC_OK) st = upload(op->tw32, twf);
+  if (st == KC_OK) st = upload(op->tw64, twd, hs);
+  if (st == KC_OK) st = upload(op->tw32, twf, hs);
   if (st == KC_OK) st = prepare_kernels(N);
   if (st != KC_OK) {
     delete op;
@@ -209,15 +331,15 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
   const int N = op->N;
   const double h = 1.0 / N;
   const double fourpi2 = 4.0 * M_PI * M_PI;
-  op->nk = nk;
-  op->kvec.assign(k_host, k_host + 3 * (size_t)nk);
-  op->gamma.resize(nk);
-  std::vector<c64> kt((size_t)nk * 3 * N);
-  std::vector<c32> kf(kt.size());
+  // every argument is checked before the handle changes
+  std::vector<double> gam(nk);
+  std::vector<int> kfl(nk, 0);
   for (int ik = 0; ik < nk; ++ik) {
     const double* k = k_host + 3 * ik;
-    for (int a = 0; a < 3; ++a)
+    for (int a = 0; a < 3; ++a) {
       KC_ARG(std::isfinite(k[a]), "non-finite wave vector");
+      if (std::fabs(k[a]) > M_PI) kfl[ik] |= KC_KFLAG_K_OUTSIDE;
+    }
     const double kn2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
     double g;
     if (gamma_host) {
@@ -227,31 +349,89 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
       // Remark 2.6, eq (2.26)
       g = (kn2 == 0.0 || kn2 >= 1.0) ? fourpi2 : fourpi2 / kn2;
     }
-    op->gamma[ik] = g;
+    gam[ik] = g;
+  }
+  double c1[5], c0[5];
+  stencil_coeffs(op->stencil_m, c1, c0);
+  std::vector<c64> kt((size_t)nk * 3 * N);
+  std::vector<c32> kf(kt.size());
+  std::vector<double> smin(nk);
+  for (int ik = 0; ik < nk; ++ik) {
+    const double* k = k_host + 3 * ik;
+    double lo0[3], lo1[3];  // smallest and second smallest |K_a(q)|^2 over q, per axis
     for (int a = 0; a < 3; ++a) {
+      lo0[a] = lo1[a] = INFINITY;
       for (int q = 0; q < N; ++q) {
-        // eigenvalues of D1 and D0 (first rows (1,0,...,0,-1)/h and (1,0,...,0,1)/2) by
-        // Lemma 2.1: (1 - e^{-i theta})/h and (1 + e^{-i theta})/2, theta = 2 pi q/N
+        // eigenvalues of the circulants D1 and D0 (first rows from eq (2.34)) by Lemma 2.1,
+        // theta = 2 pi q/N: D1 -> (1/h) sum_s c1_s (e^{i(s-1)theta} - e^{-i s theta}),
+        // D0 -> sum_s c0_s (e^{i(s-1)theta} + e^{-i s theta}); m = 1 gives (1 - e^{-i theta})/h
+        // and (1 + e^{-i theta})/2 of eq (2.5).  K_a = D1 + i k_a D0 (eq (2.6)).
         const double th = 2.0 * M_PI * (double)q / (double)N;
-        const std::complex<double> em(std::cos(th), -std::sin(th));
-        const std::complex<double> l1 = (1.0 - em) / h;
-        const std::complex<double> l0 = 0.5 * (1.0 + em);
+        std::complex<double> l1(0.0, 0.0), l0(0.0, 0.0);
+        for (int s = 1; s <= op->stencil_m; ++s) {
+          const std::complex<double> ep = std::polar(1.0, (s - 1) * th), em = std::polar(1.0, -s * th);
+          l1 += c1[s - 1] * (ep - em);
+          l0 += c0[s - 1] * (ep + em);
+        }
+        l1 /= h;
         const std::complex<double> K = l1 + std::complex<double>(0.0, k[a]) * l0;
         kt[((size_t)ik * 3 + a) * N + q] = mk(K.real(), K.imag());
         kf[((size_t)ik * 3 + a) * N + q] = mk((float)K.real(), (float)K.imag());
+        const double v = std::norm(K);
+        if (v < lo0[a]) {
+          lo1[a] = lo0[a];
+          lo0[a] = v;
+        } else if (v < lo1[a]) {
+          lo1[a] = v;
+        }
       }
     }
+    // smallest positive s(p) = sum_a |K_a(q_a)|^2: all axes at their minimum unless that sum
+    // vanishes (k = 0: the DC frequency), then one axis at its second smallest value
+    const double s0 = lo0[0] + lo0[1] + lo0[2];
+    double sm = s0;
+    if (!(s0 > 1e-300)) {
+      sm = INFINITY;
+      for (int a = 0; a < 3; ++a) sm = std::min(sm, s0 - lo0[a] + lo1[a]);
+    }
+    smin[ik] = sm;
   }
-  KC_TRY(upload(op->kdev, op->kvec));
+  // no k-points while the tables change (a failed upload leaves none), then the sizes that the
+  // range checks of the other calls read
+  op->nk = 0;
+  KC_TRY(upload(op->kdev, std::vector<double>(k_host, k_host + 3 * (size_t)nk)));
   KC_TRY(upload(op->ktab64, kt));
   KC_TRY(upload(op->ktab32, kf));
-  KC_TRY(upload(op->gamma_d, op->gamma));
+  KC_TRY(upload(op->gamma_d, gam));
+  op->kvec.assign(k_host, k_host + 3 * (size_t)nk);
+  op->gamma = gam;
+  op->smin = smin;
+  op->kflags = kfl;
+  op->nk = nk;
   return KC_OK;
 }
 
 int kc_get_gamma(const kc_op* op, double* gamma_host) {
   KC_ARG(op != nullptr && gamma_host != nullptr, "NULL argument");
   for (int i = 0; i < op->nk; ++i) gamma_host[i] = op->gamma[i];
+  return KC_OK;
+}
+
+int kc_op_flags(const kc_op* op, int* flags_host) {
+  KC_ARG(op != nullptr && flags_host != nullptr, "NULL argument");
+  *flags_host = op->flags;
+  return KC_OK;
+}
+
+int kc_kpoint_flags(const kc_op* op, int* flags_host) {
+  KC_ARG(op != nullptr && flags_host != nullptr, "NULL argument");
+  for (int i = 0; i < op->nk; ++i) flags_host[i] = op->kflags[i];
+  return KC_OK;
+}
+
+int kc_spurious_bound(const kc_op* op, double* bound_host) {
+  KC_ARG(op != nullptr && bound_host != nullptr, "NULL argument");
+  for (int i = 0; i < op->nk; ++i) bound_host[i] = op->gamma[i] * op->smin[i];
   return KC_OK;
 }
 
@@ -390,8 +570,34 @@ int kc_last_solve_stats(const kc_op* op, double* stats_host) {
 
 void kc_destroy(kc_op* op) {
   if (!op) return;
+  // a caller allocator may hand the memory to other work as soon as it is freed
+  if (op->alloc.free != nullptr) (void)hipDeviceSynchronize();
   solver_release(op);
   delete op;
+}
+
+static int to_space(kc_op* op, int nvec, const void* in, void* out, int sign, void* stream) {
+  KC_ARG(op != nullptr, "op is NULL");
+  KC_ARG(nvec >= 0, "nvec >= 0");
+  if (nvec == 0) return KC_OK;
+  KC_ARG(in != nullptr && out != nullptr, "NULL vector");
+  const int N = op->N;
+  const size_t N3 = (size_t)N * N * N;
+  hipStream_t s = (hipStream_t)stream;
+  KC_TRY(fft3d(N, 3 * nvec, sign, KC_PREC_FP64, in, out, op->tw64.p, s));
+  const size_t total = 3 * (size_t)nvec * N3;
+  k_scale<<<(unsigned)std::min<size_t>((total + 255) / 256, 65536), 256, 0, s>>>((c64*)out, total,
+                                                                                1.0 / std::sqrt((double)N3));
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+int kc_to_real_space(kc_op* op, int nvec, const void* x, void* H, void* stream) {
+  return to_space(op, nvec, x, H, +1, stream);
+}
+
+int kc_to_kspace(kc_op* op, int nvec, const void* H, void* x, void* stream) {
+  return to_space(op, nvec, H, x, -1, stream);
 }
 
 const char* kc_status_string(int status) {

@@ -35,6 +35,11 @@ struct SolverWork {
   DevBuf R, tmask;  // residuals (input of T_E) and the columns that get T_E R
   DevBuf ints;  // xmask, wmask, pmask, pvalid [nb*mb each], kskip, flags, kglobal, wskip [nb each]
   hipStream_t gstream = nullptr;  // private stream of graph-captured solves (default priority)
+  void bind_allocator(const Allocator* al) {
+    DevBuf* bufs[] = {&S, &AS, &part_gram, &part_res, &part_upd, &GA, &GB, &Cu, &Lsave, &GApp, &theta, &res, &xn2,
+                      &R, &tmask, &ints};
+    for (DevBuf* b : bufs) b->al = al;
+  }
   ~SolverWork() {
     if (gstream) (void)hipStreamDestroy(gstream);
   }
@@ -126,6 +131,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
                 c64* Xout, const c64* xinit, hipStream_t s, bool* all_conv) {
   if (!op->solver) op->solver = new SolverWork();
   SolverWork* w = op->solver;
+  w->bind_allocator(&op->alloc);
   Batch B;
   B.op = op;
   B.w = w;
@@ -559,6 +565,13 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   }
   KC_HIP(hipStreamSynchronize(s));
   op->stats[2] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  // Prop 2.3: the penalty term's eigenvalues are gamma s(p) >= gamma s_min; the m computed
+  // eigenvalues are free of them when the largest lies below that bound
+  for (int b = 0; b < nk; ++b) {
+    int& f = op->kflags[ik0 + b];
+    f &= ~KC_KFLAG_SPURIOUS_RISK;
+    if (eig_host[(size_t)b * o.m + o.m - 1] >= op->gamma[ik0 + b] * op->smin[ik0 + b]) f |= KC_KFLAG_SPURIOUS_RISK;
+  }
   if (!allc) {
     kc::set_error("some k-points did not reach tol within maxit");
     return KC_ERR_NO_CONVERGENCE;

@@ -22,10 +22,20 @@ struct EpsEntry {
   cpx<T> o[3];
 };
 
-// Device buffer that grows on demand (contents are not preserved when it grows).
+// Device memory source of a handle: the caller's allocator callbacks (kc_create), or hipMalloc /
+// hipFree when none are given.
+struct Allocator {
+  kc_alloc_fn alloc = nullptr;
+  kc_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+
+// Device buffer that grows on demand (contents are not preserved when it grows).  Memory comes
+// from `al` (nullptr: hipMalloc).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  const Allocator* al = nullptr;
   int ensure(size_t n);  // zero-fills newly allocated memory
   void release();
   ~DevBuf() { release(); }
@@ -55,6 +65,11 @@ struct kc_op {
   int N = 0;
   int scheme = 0;
   int n_mat = 0;
+  int stencil_m = 1;             // order 2m of the curl/divergence stencils (eq (2.34))
+  kc::Allocator alloc;           // source of every device buffer of the handle
+  int flags = 0;                 // KC_FLAG_* found by kc_create
+  std::vector<double> smin;      // [nk] smallest positive s(p) = |K(p)|^2 (spurious-mode bound)
+  std::vector<int> kflags;       // [nk] KC_KFLAG_* of each k-point
   std::vector<double> eps_host;  // [n_mat][3][3][2]
   kc::DevBuf ids;                // uint32 [N^3]: x-edge | y-edge << 8 | z-edge << 16 | vol << 24
   kc::DevBuf eps64, eps32;       // EpsEntry<double/float> [n_mat]
@@ -75,6 +90,12 @@ struct kc_op {
   double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int8_t tiles[2][16] = {};     // tile width per pass (kc::TilePass), [FP32, FP64]; 0 = default
   bool tuned[2] = {false, false};
+  // every device buffer of the handle takes its memory from `alloc`
+  void bind_allocator() {
+    kc::DevBuf* bufs[] = {&ids, &eps64, &eps32, &tw64, &tw32, &ktab64, &ktab32, &gamma_d, &work_a, &work_b,
+                          &work_c, &work_k, &epsfeat, &efield, &efield_t, &efield_k, &kdev};
+    for (kc::DevBuf* b : bufs) b->al = &alloc;
+  }
 };
 
 namespace kc {

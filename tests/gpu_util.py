@@ -35,3 +35,8 @@ def rel_err(a: np.ndarray, b: np.ndarray) -> float:
 def note(*args):
     """Print (and flush) what names the case before a GPU step."""
     print(*args, file=sys.stderr, flush=True)
+
+
+def max_err(a: np.ndarray, b: np.ndarray) -> float:
+    """Element-wise error: max |a - b| over max |b| (every entry is held to the same scale)."""
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))

@@ -128,3 +128,71 @@ def test_block_calls_check_arguments():
                              10, None)]
     assert all(st == 1 for st in bad), bad  # KC_ERR_INVALID_ARG
     assert b"work_bytes" in L.kc_last_error()
+
+
+def test_header_declares_boundary_extensions():
+    names = declared_functions()
+    for n in ["kc_to_real_space", "kc_to_kspace", "kc_op_flags", "kc_kpoint_flags", "kc_spurious_bound",
+              "kc_get_gamma"]:
+        assert n in names
+
+
+def test_create_checks_lattice_stencil_and_allocator_before_device_work():
+    """Non-cubic lattices are KC_ERR_UNSUPPORTED; stencil orders outside 2..10 and a lone
+    allocator callback are KC_ERR_INVALID_ARG; all found before any device call."""
+    N = 4
+    ids = np.zeros((4, N ** 3), dtype=np.uint8)
+    tab = W.eps_table([])
+    fcc = 0.5 * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+    with pytest.raises(kc.KcError) as e:
+        kc.Op(N, kc.KC_EPS_CROSSDOF, ids, tab, lattice=fcc)
+    assert e.value.status == 2
+    for m in (0, 6):
+        with pytest.raises(kc.KcError) as e:
+            kc.Op(N, kc.KC_EPS_CROSSDOF, ids, tab, stencil_m=m)
+        assert e.value.status == 1
+    from paper_2511_17107_amd import _binding as B
+
+    L = B.lib()
+    h = ctypes.c_void_p()
+    tab_r = np.ascontiguousarray(tab.view(np.float64))
+    st = L.kc_create(N, None, 1, kc.KC_EPS_CROSSDOF, ids.ctypes.data_as(ctypes.c_void_p), 1,
+                     tab_r.ctypes.data_as(ctypes.c_void_p), B._torch_alloc_c, B._FREE_FN(), None, None,
+                     ctypes.byref(h))
+    assert st == 1 and b"together" in L.kc_last_error()
+
+
+def _fake_op(N=4, nk=2):
+    """A binding object with no library handle: its argument checks run before any call."""
+    op = kc.Op.__new__(kc.Op)
+    op._h, op.N, op.nk, op.stencil_m = None, N, nk, 1
+    return op
+
+
+def test_binding_checks_sizes_before_the_library():
+    """The C ABI takes raw pointers; the binding refuses tensors whose element count differs from
+    what the library would read or write (ValueError, before any device access)."""
+    import torch
+
+    N = 4
+    op = _fake_op(N)
+    n = 3 * N ** 3
+    good = torch.zeros((2, 3, N ** 3), dtype=torch.complex128)
+    short = torch.zeros((2, 3, N ** 3 - 1), dtype=torch.complex128)
+    wrongN = torch.zeros((2, 3, 6 ** 3), dtype=torch.complex128)
+    for call in [lambda: op.apply(short), lambda: op.apply(wrongN), lambda: op.apply(good, out=short),
+                 lambda: op.precond(short), lambda: op.precond(good, out=wrongN),
+                 lambda: op.precond_transverse(good, efield=torch.zeros(n - 1, dtype=torch.float32)),
+                 lambda: op.tp_grad(good, good, torch.zeros(2, dtype=torch.float64), torch.zeros(n - 1)),
+                 lambda: op.tp_grad(good, good, torch.zeros(3, dtype=torch.float64), torch.zeros(2 * n)),
+                 lambda: op.to_real_space(short), lambda: op.to_kspace(good, out=short),
+                 lambda: op.solve(2, nk=2, X_out=torch.zeros((2, 2, n - 1), dtype=torch.complex128)),
+                 lambda: op.solve(2, nk=2, x_init=torch.zeros((2, 2, n + 1), dtype=torch.complex128)),
+                 lambda: op.net_efield(nk=2, out=torch.zeros((2, 3, N ** 3 - 1), dtype=torch.float32)),
+                 lambda: kc.kc_fft3d(torch.zeros((2, N ** 3), dtype=torch.complex128), 1,
+                                     out=torch.zeros((2, N ** 3 - 2), dtype=torch.complex128))]:
+        with pytest.raises(ValueError):
+            call()
+    # the right sizes get past the size checks to the device check
+    with pytest.raises(TypeError):
+        op.apply(good)

@@ -165,7 +165,7 @@ def test_solve_n128_woodpile_properties():
     FP32 operator then FP64, transverse preconditioner, batched, graph-replayed) on two k-points
     of the path, checked through properties that hold at any size with the FP64 operator (itself
     checked at N = 128 against the oracle): Res_j <= 1e-8 from a fresh application, eigenvalues
-    ascending and equal to the Rayleigh quotients, eigenvectors orthonormal."""
+    ascending and equal to the Rayleigh quotients, eigenvectors orthonormal and divergence-free."""
     import torch
 
     wl = W.woodpile_gyrotropic(N=128, nk=60, m=16)
@@ -187,6 +187,13 @@ def test_solve_n128_woodpile_properties():
         r = torch.linalg.vector_norm(Ab - torch.from_numpy(eig[b]).to(Ab.device)[:, None] * Xb, dim=1)
         assert float(r.max()) <= 1.5 * TOL
         assert np.all(np.diff(eig[b]) >= -1e-12 * eig[b][-1])
+        # no spurious (longitudinal) mode: the discrete divergence B H vanishes (Prop 2.2), i.e.
+        # sum_a K_a(p) x_a(p) = 0 per frequency; a penalty-term eigenvector would give |k| or more
+        K = torch.from_numpy(kspace.symbols_3d(128, wl.kpoints[[7, 41]][b])).to(X.device)
+        div = torch.linalg.vector_norm((K[None] * X[16 * b:16 * (b + 1)]).sum(dim=1), dim=1)
+        assert float(div.max()) <= 1e-6, div.cpu().numpy()
+        # every band lies below the penalty term's spectrum (Prop 2.3)
+        assert eig[b, -1] < op.spurious_bound()[b]
 
 
 @pytest.mark.parametrize("precond", [kc.KC_PRECOND_TRANSVERSE, kc.KC_PRECOND_DIAG])
@@ -215,3 +222,69 @@ def test_warm_start_from_neighbouring_kpoints(precond):
         assert np.max(np.abs(e1[i] - ref) / ref) <= REL, (c["k"], e1[i], ref)
     note("iterations cold", i0.tolist(), "warm", i1.tolist())
     assert i1.sum() < i0.sum()
+
+
+def _homogeneous_lowest(N, k, eps1, scheme, nb, qmax=6):
+    """The nb smallest eigenvalues of Op for a homogeneous medium from its per-frequency 3 x 3
+    blocks (Lemma 2.1, Prop 2.8; CrossDoF symbol as pinned by
+    test_oracle_operator::test_homogeneous_anisotropic_per_frequency), over the frequencies with
+    |q_a| <= qmax, and a lower bound of every eigenvalue outside that cube:
+    K_A M_p K_A^H >= lambda_min(eps1) s(p) on the transverse modes (M_p >= lambda_min(eps1) I),
+    gamma s(p) on the longitudinal one."""
+    g = yee.gamma_rule(k)
+    s1 = kspace.symbols_1d(N, k)
+    qs = np.array([q % N for q in range(-qmax, qmax + 1)])
+    th = 2 * math.pi * qs / N
+    lam0 = 0.5 * (1.0 + np.exp(-1j * th))
+    qz, qy, qx = np.meshgrid(np.arange(len(qs)), np.arange(len(qs)), np.arange(len(qs)), indexing="ij")
+    idx = [qx.ravel(), qy.ravel(), qz.ravel()]
+    K = np.stack([s1[a][qs[idx[a]]] for a in range(3)], axis=1)     # (P, 3)
+    KA = np.zeros((K.shape[0], 3, 3), dtype=complex)
+    KA[:, 0, 1], KA[:, 0, 2] = -K[:, 2], K[:, 1]
+    KA[:, 1, 0], KA[:, 1, 2] = K[:, 2], -K[:, 0]
+    KA[:, 2, 0], KA[:, 2, 1] = -K[:, 1], K[:, 0]
+    Mp = np.broadcast_to(eps1, KA.shape).copy()
+    if scheme == "crossdof":
+        for c in range(3):
+            for d in range(c + 1, 3):
+                t = lam0[idx[c]] * np.conj(lam0[idx[d]])
+                Mp[:, c, d] = eps1[c, d] * t
+                Mp[:, d, c] = np.conj(Mp[:, c, d])
+    v = K.conj()
+    Opp = KA @ Mp @ KA.conj().transpose(0, 2, 1) + g * v[:, :, None] * v.conj()[:, None, :]
+    ev = np.sort(np.linalg.eigvalsh(Opp).ravel())
+    ev = ev[ev > 1e-9 * ev.max()]
+    # outside the cube some |q_a| > qmax: s(p) >= min_a min_{|q| > qmax} |K_a(q)|^2
+    far = np.array([q for q in range(N) if min(q, N - q) > qmax], dtype=np.int64)
+    if far.size == 0:
+        return ev[:nb], math.inf
+    s_out = min(np.min(np.abs(s1[a][far]) ** 2) for a in range(3))
+    bound = min(np.linalg.eigvalsh(eps1).min(), g) * s_out
+    return ev[:nb], bound
+
+
+@pytest.mark.parametrize("case", ["isotropic", "gyro-trivial", "gyro-crossdof"])
+def test_solve_n128_homogeneous_closed_form(case):
+    """Eigen-parity at the benchmark's size and through its exact path (FP32 operator phase then
+    FP64, transverse preconditioner, 16 bands + 4 guard columns, two k-points batched, graph
+    replay): homogeneous media whose spectra are known per frequency, every band within 1e-6
+    relative, so a missed or spurious band fails."""
+    N, m = 128, 16
+    if case == "isotropic":
+        eps, scheme = 13.0 * np.eye(3), "crossdof"
+    else:
+        eps, scheme = W.gyrotropic_eps(12.0, 0.5, 10.0), case.split("-")[1]
+    tab = W.eps_table([eps])
+    eps1 = tab[1]
+    ids = np.ones((4, N ** 3), dtype=np.uint8)
+    kp = np.array([[0.31, 0.17, 0.07], [1.9, -0.8, 0.45]])
+    op = kc.Op(N, kc.SCHEMES[scheme], ids, tab)
+    op.set_kpoints(kp)
+    note("solve n128 homogeneous", case)
+    eig, res, its, st = op.solve(m, tol=TOL, guard=4, batch_k=2, prec=kc.KC_PREC_FP32, switch_tol=3e-4,
+                                 precond=kc.KC_PRECOND_TRANSVERSE)
+    assert st == 0 and res.max() <= TOL
+    for b in range(2):
+        ref, bound = _homogeneous_lowest(N, kp[b], eps1, scheme, m)
+        assert ref[-1] < bound  # the cube holds the m lowest eigenvalues
+        assert np.max(np.abs(eig[b] - ref) / ref) <= REL, (case, b, eig[b], ref)
