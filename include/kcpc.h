@@ -209,6 +209,22 @@ int kc_block_gram(int nb, size_t n, int nc, const void* S, const void* AS, void*
                   size_t work_bytes, void* stream);
 
 /*
+ * kc_block_gram for callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid allocation): no workspace argument and no
+ * allocation; the partial sums live in a fixed static device array of KC_NOALLOC_SCRATCH_BYTES
+ * (32 MiB) per GPU, held until the process ends.  Same arguments, layout and results as
+ * kc_block_gram (up to the order of the partial sums: fewer, longer row chunks when the array
+ * would not hold the usual number).  Sizes with nb * ceil(nc/16) * (ceil(nc/16) + 1) * 4096 >
+ * KC_NOALLOC_SCRATCH_BYTES (e.g. nb > 409 at nc > 48) give KC_ERR_INVALID_ARG before any device
+ * work.  Every call on a GPU uses that GPU's one array, so calls that overlap on one GPU (other
+ * streams, other threads) race; the array needs no clearing (each call writes every partial sum
+ * before it reads it).
+ */
+#define KC_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int kc_block_gram_noalloc(int nb, size_t n, int nc, const void* S, const void* AS, void* GA, void* GB,
+                          void* stream);
+
+/*
  * One Rayleigh-Ritz update with the next residuals (eq (4.3)), in place.  Per k-point b the
  * block holds 3mb columns S_b = [X W P] and AS_b = [AX AW AP] (1 <= mb <= 21), and
  * C_b = [C1 | Cp] is 3mb x 2mb (row-major, complex128 [nb][3mb][2mb]):

@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     KcError,
     Net,
     block_gram,
+    block_gram_noalloc,
     block_update,
     block_work_bytes,
     Op,

@@ -126,6 +126,7 @@ def lib():
         L.kc_block_work_bytes.argtypes = [i32, ctypes.c_size_t, i32]
         L.kc_block_work_bytes.restype = ctypes.c_size_t
         L.kc_block_gram.argtypes = [i32, ctypes.c_size_t, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+        L.kc_block_gram_noalloc.argtypes = [i32, ctypes.c_size_t, i32, vp, vp, vp, vp, vp]
         L.kc_block_update.argtypes = [i32, ctypes.c_size_t, i32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
         L.kc_status_string.argtypes = [i32]
         L.kc_status_string.restype = ctypes.c_char_p
@@ -245,6 +246,21 @@ def block_gram(S, AS, GA=None, GB=None, work=None, stream=None):
                                _dev_ptr(AS, "torch.complex128", "AS"), _dev_ptr(GA, "torch.complex128", "GA"),
                                _dev_ptr(GB, "torch.complex128", "GB"), ctypes.c_void_p(work.data_ptr()),
                                work.numel(), _stream(stream)), "kc_block_gram")
+    return GA, GB
+
+
+def block_gram_noalloc(S, AS, GA, GB, stream=None):
+    """kc_block_gram_noalloc: GA_b = S_b^H AS_b, GB_b = S_b^H S_b for blocks (nb, nc, n),
+    complex128, into caller-provided GA, GB (nb, nc, nc); the library allocates nothing."""
+    nb, nc, n = _block_shape(S, "S")
+    if tuple(AS.shape) != (nb, nc, n):
+        raise ValueError("AS must have the shape of S")
+    _numel(GA, nb * nc * nc, "GA")
+    _numel(GB, nb * nc * nc, "GB")
+    _check(lib().kc_block_gram_noalloc(nb, n, nc, _dev_ptr(S, "torch.complex128", "S"),
+                                       _dev_ptr(AS, "torch.complex128", "AS"), _dev_ptr(GA, "torch.complex128", "GA"),
+                                       _dev_ptr(GB, "torch.complex128", "GB"), _stream(stream)),
+           "kc_block_gram_noalloc")
     return GA, GB
 
 

@@ -13,6 +13,11 @@ int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, De
 int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, c64* part, c64* GA, c64* GB,
           const int* kskip, hipStream_t s);
 size_t gram2_part_bytes(int nc, size_t n, int nb);
+// gram2 (contiguous blocks, kstride = nc) with its partial sums in a buffer of part_bytes bytes:
+// the chunks are made longer (fewer partial sums) until they fit; KC_ERR_INVALID_ARG when even
+// one chunk per k-point does not.
+int gram2_bounded(const c64* S, const c64* AS, int nc, size_t n, int nb, c64* part, size_t part_bytes, c64* GA,
+                  c64* GB, hipStream_t s);
 
 // The W columns of the Gram matrices of S = [X W P] (kstride-spaced blocks of 3mb columns):
 // GB(:, W) = S^H W, GA(:, W) = S^H AW, with the X/P blocks filled from the previous

@@ -733,15 +733,45 @@ size_t gram2_part_bytes(int nc, size_t n, int nb) {
   return (size_t)nb * ((n + rows - 1) / rows) * (T * (T + 1)) * 256 * sizeof(c64);
 }
 
+// gram2 with the rows of a chunk given (a multiple of G2_ROWS)
+static int gram2_rows(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, c64* part, c64* GA,
+                      c64* GB, const int* kskip, size_t rows, hipStream_t s);
+
 int gram2(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, c64* part, c64* GA, c64* GB,
           const int* kskip, hipStream_t s) {
+  return gram2_rows(S, AS, kstride, nc, n, nb, part, GA, GB, kskip, gram_rows(n, nb), s);
+}
+
+int gram2_bounded(const c64* S, const c64* AS, int nc, size_t n, int nb, c64* part, size_t part_bytes, c64* GA,
+                  c64* GB, hipStream_t s) {
+  const int T = (nc + 15) / 16;
+  const size_t per_chunk = (size_t)nb * (T * (T + 1)) * 256 * sizeof(c64);  // one chunk per k-point
+  if (per_chunk > part_bytes) {
+    set_error("gram2: partial sums of " + std::to_string(nb) + " k-points exceed the " + std::to_string(part_bytes) +
+              "-byte buffer");
+    return KC_ERR_INVALID_ARG;
+  }
+  const size_t max_chunks = part_bytes / per_chunk;
+  size_t rows = gram_rows(n, nb);
+  if ((n + rows - 1) / rows > max_chunks) {
+    rows = (n + max_chunks - 1) / max_chunks;
+    rows = (rows + G2_ROWS - 1) / G2_ROWS * G2_ROWS;
+  }
+  if (rows > (size_t)INT32_MAX) {
+    set_error("gram2: too many rows per chunk");
+    return KC_ERR_INVALID_ARG;
+  }
+  return gram2_rows(S, AS, nc, nc, n, nb, part, GA, GB, nullptr, rows, s);
+}
+
+static int gram2_rows(const c64* S, const c64* AS, int kstride, int nc, size_t n, int nb, c64* part, c64* GA,
+                      c64* GB, const int* kskip, size_t rows, hipStream_t s) {
   const int T = (nc + 15) / 16;
   const int ntile = T * (T + 1);
   if (nc > 64 || ntile > 20) {
     set_error("gram2: too many columns");
     return KC_ERR_INVALID_ARG;
   }
-  const size_t rows = gram_rows(n, nb);
   const int nchunk = (int)((n + rows - 1) / rows);
   dim3 grid(nchunk, nb);
   switch ((ntile + G2_WAVES - 1) / G2_WAVES) {

@@ -733,6 +733,31 @@ size_t kc_block_work_bytes(int nb, size_t n, int nc) {
   return std::max(gram2_part_bytes(nc, n, nb), upd);
 }
 
+// Partial sums of kc_block_gram_noalloc: a fixed array per device, held until the process ends.
+// Host code never passes `scratch` itself (on the host it names a stand-in, not device memory):
+// the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[KC_NOALLOC_SCRATCH_BYTES];
+
+static int scratch_address(void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;  // device -> address of its copy of `scratch`
+  int dev = 0;
+  KC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    KC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) {
+      set_error("hipGetSymbolAddress returned NULL for the scratch array");
+      return KC_ERR_HIP;
+    }
+    it = addr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return KC_OK;
+}
+
 static bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
   return (const char*)a + na <= (const char*)b || (const char*)b + nb <= (const char*)a;
 }
@@ -745,6 +770,22 @@ int kc_block_gram(int nb, size_t n, int nc, const void* S, const void* AS, void*
   KC_ARG(work_bytes >= gram2_part_bytes(nc, n, nb), "work_bytes below kc_block_work_bytes");
   return gram2((const c64*)S, (const c64*)AS, nc, nc, n, nb, (c64*)work, (c64*)GA, (c64*)GB, nullptr,
                (hipStream_t)stream);
+}
+
+int kc_block_gram_noalloc(int nb, size_t n, int nc, const void* S, const void* AS, void* GA, void* GB,
+                          void* stream) {
+  KC_ARG(nb >= 0 && n >= 1 && nc >= 1 && nc <= RR_NMAX, "nb >= 0, n >= 1, 1 <= nc <= 64");
+  if (nb == 0) return KC_OK;
+  KC_ARG(S != nullptr && AS != nullptr && GA != nullptr && GB != nullptr, "NULL buffer");
+  const size_t T = (size_t)(nc + 15) / 16;
+  KC_ARG((size_t)nb * T * (T + 1) * 256 * sizeof(c64) <= KC_NOALLOC_SCRATCH_BYTES,
+         "nb * ceil(nc/16) * (ceil(nc/16) + 1) * 4096 must not exceed KC_NOALLOC_SCRATCH_BYTES");
+  void* part = nullptr;
+  KC_TRY(scratch_address(&part));
+  // every partial sum is written by the product kernel before the reduction reads it, so the
+  // array needs no clearing between calls
+  return gram2_bounded((const c64*)S, (const c64*)AS, nc, n, nb, (c64*)part, KC_NOALLOC_SCRATCH_BYTES, (c64*)GA,
+                       (c64*)GB, (hipStream_t)stream);
 }
 
 int kc_block_update(int nb, size_t n, int mb, void* S, void* AS, const void* C, const double* theta, void* R,
