@@ -78,6 +78,10 @@ def parse():
     ap.add_argument("--update-only", action="store_true",
                     help="only the fused block update (kc_block_update) at the solve's batch shape, three "
                          "launches, and the 1 GiB device copy; for profiling")
+    ap.add_argument("--workload", choices=["c4", "c2", "c3"], default="c4",
+                    help="c4: the headline (128^3 woodpile); c2: 64^3 anisotropic sphere, 20 bands, 40 "
+                         "k-points, FP64; c3: the same sphere, 16 bands, 120 k-points in two launch sets, "
+                         "mixed precision against the FP64 path (per-band eigenvalue differences)")
     ap.add_argument("--verbose", type=int, default=0)
     return ap.parse_args()
 
@@ -212,6 +216,67 @@ def update_only(a, dev):
                       "copy_bytes_each_way": src.numel() * 8, "res0": float(res[0, 0])}), flush=True)
 
 
+def sphere64_run(a, dev):
+    """The 64^3 anisotropic-sphere configurations (sphere r = 0.3a, eps = R diag(e) R^T with
+    e_i ~ U[4,14], seed 0, CrossDoF, k-points uniform on Gamma-X-M-Gamma-R):
+      c2: 20 bands (+1 guard column, the largest block the one-workgroup Rayleigh-Ritz takes), 40
+          k-points in one launch set, FP64 operator;
+      c3: 16 bands (+4 guard), 120 k-points in two launch sets of 60, FP32 operator phase with FP64
+          block algebra and finish, against the FP64 path on the same k-points (per-band relative
+          eigenvalue differences) and the FP64 path one k-point at a time.
+    Each solve is timed on its own (inputs resident, one untimed solve first for the tile tuner)."""
+    import torch
+
+    import paper_2511_17107_amd as kc
+    import workloads as W
+
+    c2 = a.workload == "c2"
+    m, guard, nk, kpb = (20, 1, 40, 40) if c2 else (16, 4, 120, 60)
+    wl = W.sphere_anisotropic(N=64, nk=nk, m=m)
+    op = kc.Op(64, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(wl.kpoints)
+    pc = kc.KC_PRECOND_TRANSVERSE
+
+    def timed(prec, ik0, nkk, batch):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        eig, res, its, st = op.solve(m, ik0=ik0, nk=nkk, tol=a.tol, maxit=a.maxit, prec=prec, switch_tol=a.switch_tol,
+                                     batch_k=batch, guard=guard, precond=pc)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, eig, res, its, st, op.last_solve_stats()
+
+    for prec in (kc.KC_PREC_FP64, kc.KC_PREC_FP32):  # tile tuning, first-use allocations
+        timed(prec, 0, 2, 2)
+    out = {"workload": "sc64-sphere-aniso-crossdof (r=0.3, eps=R diag(e) R^T, e~U[4,14], seed 0), %d bands "
+                       "(+%d guard), %d k-points G-X-M-G-R" % (m, guard, nk),
+           "mode": a.workload, "N": 64, "bands": m, "kpoints": nk, "tol": a.tol, "preconditioner": "transverse",
+           "unit": "k-points/s", "data": "synthetic"}
+    runs = {}
+    for name, prec in ([("fp64", kc.KC_PREC_FP64)] if c2 else [("mixed", kc.KC_PREC_FP32), ("fp64", kc.KC_PREC_FP64)]):
+        T, E, R, I, S, ST = 0.0, [], [], [], [], np.zeros(8)
+        for ik0 in range(0, nk, kpb):
+            t, eig, res, its, st, stats = timed(prec, ik0, min(kpb, nk - ik0), kpb)
+            T += t
+            E.append(eig), R.append(res), I.append(its), S.append(st)
+            ST += stats
+        runs[name] = (np.concatenate(E), np.concatenate(R), np.concatenate(I))
+        out[name] = {"value": nk / T, "seconds": T, "launch_sets": (nk + kpb - 1) // kpb, "batch_k": kpb,
+                     "converged": all(st == 0 for st in S), "max_residual": float(np.concatenate(R).max()),
+                     "iterations_mean": float(np.concatenate(I).mean()), "matvecs_fp64": float(ST[0]),
+                     "matvecs_fp32": float(ST[1])}
+    if not c2:
+        e_m, e_d = runs["mixed"][0], runs["fp64"][0]
+        rel = np.abs(e_m - e_d) / np.abs(e_d)
+        out["band_rel_diff_mixed_vs_fp64"] = {"max": float(rel.max()),
+                                              "per_band_max": [float(v) for v in rel.max(axis=0)]}
+        # the FP64 path one k-point at a time, on every tenth k-point of the path
+        sel = list(range(0, nk, 10))
+        T = sum(timed(kc.KC_PREC_FP64, ik, 1, 1)[0] for ik in sel)
+        out["fp64_sequential"] = {"value": len(sel) / T, "kpoints": len(sel), "batch_k": 1}
+    out["eigenvalues_first_kpoints"] = [[float(v) for v in runs["fp64"][0][i]] for i in range(3)]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -226,6 +291,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.workload != "c4":
+        sphere64_run(a, dev)
+        return
     wl = W.woodpile_gyrotropic(N=a.N, nk=a.nk, m=a.m)
     op = kc.Op(wl.N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
     op.set_kpoints(wl.kpoints)

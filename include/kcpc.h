@@ -334,6 +334,15 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
 int kc_last_solve_stats(const kc_op* op, double* stats_host);
 
 /*
+ * Residual history of k-point ik0 + k of the last kc_solve (0 <= k < its nk): the largest
+ * Res_j (j < m, eq (4.3)) before each iteration, and the precision (KC_PREC_*) of that
+ * iteration's operator applications.  res_host float64 [cap], prec_host int32 [cap] (either may
+ * be NULL); *count receives the number of iterations recorded (the first min(cap, count) are
+ * written).
+ */
+int kc_last_residual_history(const kc_op* op, int k, double* res_host, int* prec_host, int cap, int* count);
+
+/*
  * Tile widths (pencils per workgroup) chosen for the handle's passes in precision prec, int32
  * [10] in the order X1, Y (inverse), Za, Zb, Z (Trivial/diagonal), Y (forward), X2, then the
  * transverse preconditioner's X1, Z and X2; 0 while not yet chosen.  On a handle's first

@@ -105,6 +105,7 @@ def lib():
         L.kc_solve_opts_default.restype = None
         L.kc_solve.argtypes = [vp, i32, i32, ctypes.POINTER(KcSolveOpts), vp, vp, vp, vp, vp]
         L.kc_last_solve_stats.argtypes = [vp, vp]
+        L.kc_last_residual_history.argtypes = [vp, i32, vp, vp, i32, vp]
         L.kc_tile_widths.argtypes = [vp, i32, vp]
         L.kc_destroy.argtypes = [vp]
         L.kc_destroy.restype = None
@@ -513,6 +514,18 @@ class Op:
         w = np.zeros(10, dtype=np.int32)
         _check(lib().kc_tile_widths(self._h, int(prec), w.ctypes.data_as(ctypes.c_void_p)), "kc_tile_widths")
         return w
+
+    def residual_history(self, k: int = 0):
+        """(max Res_j per iteration, precision per iteration) of k-point k of the last solve."""
+        cnt = ctypes.c_int(0)
+        _check(lib().kc_last_residual_history(self._h, int(k), None, None, 0, ctypes.byref(cnt)),
+               "kc_last_residual_history")
+        r = np.zeros(cnt.value)
+        p = np.zeros(cnt.value, dtype=np.int32)
+        _check(lib().kc_last_residual_history(self._h, int(k), r.ctypes.data_as(ctypes.c_void_p),
+                                              p.ctypes.data_as(ctypes.c_void_p), cnt.value, ctypes.byref(cnt)),
+               "kc_last_residual_history")
+        return r, p
 
     def last_solve_stats(self) -> np.ndarray:
         s = np.zeros(8)

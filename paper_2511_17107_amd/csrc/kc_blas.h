@@ -46,11 +46,17 @@ int update_res_prepare();
 
 // W_j = K_P^{-1} (AX_j - theta_j X_j), res_j = |AX_j - theta_j X_j| / |X_j|; optionally the
 // residuals themselves (Rout, contiguous [nb*mb][3N^3]) and |r_j|^2 (rnorm2); W is left
-// untouched for the k-points b with wskip[b] != 0.
+// untouched for the k-points b with wskip[b] != 0.  sfl (device double [nb], or nullptr): per
+// k-point floor of s = |K|^2 in the gains 1/s and 1/(gamma s) (the frequency s = 0 stays zero).
 int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
                   const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
                   double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout = nullptr,
-                  double* rnorm2 = nullptr, const int* wskip = nullptr);
+                  double* rnorm2 = nullptr, const int* wskip = nullptr, const double* sfl = nullptr);
+
+// Removes the DC longitudinal direction (x(0) along conj(K(0))) from columns [col0, col0 + ncol)
+// of the k-points b with dcl[b] != 0 (kstride-spaced groups; FP64).
+int deflate_dc_long(c64* S, int kstride, int col0, int ncol, int nb, const c64* ktab64, int N, const int* dcl,
+                    hipStream_t s);
 
 int random_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, uint64_t seed, const int* kglobal,
                  hipStream_t s);

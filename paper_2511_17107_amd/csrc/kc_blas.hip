@@ -617,7 +617,8 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
                                                        const double* __restrict__ gamma, int N, int kstride,
                                                        int xcol0, int wcol0, int mb, double* __restrict__ part,
                                                        const int* __restrict__ kskip, c64* __restrict__ Rout,
-                                                       const int* __restrict__ wskip) {
+                                                       const int* __restrict__ wskip,
+                                                       const double* __restrict__ sfl) {
   const int b = blockIdx.z, j = blockIdx.y;
   if (kskip && kskip[b]) return;
   const bool ww = !(wskip && wskip[b]);
@@ -628,6 +629,7 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
   const double th = theta[b * mb + j];
   const c64* K = ktab64 + (size_t)b * 3 * N;
   const double g = gamma[b];
+  const double fl = sfl ? sfl[b] : 0.0;
   c64* rc = Rout ? Rout + ((size_t)b * mb + j) * n : nullptr;
   double rr = 0.0, xx = 0.0;
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N3; p += (size_t)gridDim.x * blockDim.x) {
@@ -640,11 +642,13 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
     const double s = abs2(K1) + abs2(K2) + abs2(K3);
     c64 w1 = mk(0.0, 0.0), w2 = w1, w3 = w1;
     if (s != 0.0) {
-      const double is = 1.0 / s;
-      const c64 u = ((1.0 / g - 1.0) * is * is) * (K1 * r1 + K2 * r2 + K3 * r3);
-      w1 = is * r1 + cmulc(K1, u);
-      w2 = is * r2 + cmulc(K2, u);
-      w3 = is * r3 + cmulc(K3, u);
+      // 1/s on the transverse and 1/(gamma s) on the longitudinal part, with s floored at fl
+      // (the floor bounds the gain near k = 0, where s at the DC frequency is |k|^2)
+      const double is = 1.0 / s, ie = s < fl ? 1.0 / fl : is;
+      const c64 u = ((1.0 / g - 1.0) * ie * is) * (K1 * r1 + K2 * r2 + K3 * r3);
+      w1 = ie * r1 + cmulc(K1, u);
+      w2 = ie * r2 + cmulc(K2, u);
+      w3 = ie * r3 + cmulc(K3, u);
     }
     if (ww) {
       w[p] = w1;
@@ -674,6 +678,39 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
     o[0] = sr[0];
     o[1] = sx[0];
   }
+}
+
+// ------------------------------------------------------------------------------------
+// Deflation of the DC longitudinal direction for the k-points with dcl[b] != 0: at the
+// frequency p = 0, x(0) <- x(0) - conj(K(0)) (K(0) . x(0)) / |K(0)|^2.  That direction (the
+// constant field along k) is an eigenvector of Op with eigenvalue gamma |k|^2 (Prop 2.3).
+// Columns [col0, col0 + ncol) of each k-point's group (kstride-spaced); one thread per column.
+// ------------------------------------------------------------------------------------
+__global__ void k_deflate_dc_long(c64* __restrict__ S, int kstride, int col0, int ncol, int nb,
+                                  const c64* __restrict__ ktab64, int N, const int* __restrict__ dcl) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nb * ncol) return;
+  const int b = t / ncol, j = t % ncol;
+  if (!dcl[b]) return;
+  const size_t N3 = (size_t)N * N * N;
+  c64* x = S + ((size_t)b * kstride + col0 + j) * 3 * N3;
+  const c64* K = ktab64 + (size_t)b * 3 * N;
+  const c64 K1 = K[0], K2 = K[N], K3 = K[2 * N];
+  const double s = abs2(K1) + abs2(K2) + abs2(K3);
+  if (s == 0.0) return;
+  const c64 x1 = x[0], x2 = x[N3], x3 = x[2 * N3];
+  const c64 u = (1.0 / s) * (K1 * x1 + K2 * x2 + K3 * x3);
+  x[0] = x1 - cmulc(K1, u);
+  x[N3] = x2 - cmulc(K2, u);
+  x[2 * N3] = x3 - cmulc(K3, u);
+}
+
+int deflate_dc_long(c64* S, int kstride, int col0, int ncol, int nb, const c64* ktab64, int N, const int* dcl,
+                    hipStream_t s) {
+  const int tot = nb * ncol;
+  k_deflate_dc_long<<<(tot + 255) / 256, 256, 0, s>>>(S, kstride, col0, ncol, nb, ktab64, N, dcl);
+  KC_LAUNCHED();
+  return KC_OK;
 }
 
 __global__ void k_resid_reduce(const double* __restrict__ part, int nblk, int nvec, double* __restrict__ res,
@@ -911,13 +948,13 @@ int update_res(c64* S, c64* AS, int kstride, int mb, const c64* C, size_t n, int
 int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
                   const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
                   double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout, double* rnorm2,
-                  const int* wskip) {
+                  const int* wskip, const double* sfl) {
   const size_t N3 = (size_t)N * N * N;
   const int nblk = (int)std::max<size_t>(1, std::min<size_t>((N3 + 255) / 256, 256));
   KC_TRY(part.ensure((size_t)nb * mb * nblk * 2 * sizeof(double)));
   dim3 grid(nblk, mb, nb);
   k_resid_precond<<<grid, 256, 0, s>>>(S, AS, W, theta, ktab64, gamma, N, kstride, xcol0, wcol0, mb,
-                                       part.as<double>(), kskip, Rout, wskip);
+                                       part.as<double>(), kskip, Rout, wskip, sfl);
   KC_LAUNCHED();
   const int nv = nb * mb;
   k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2, rnorm2);

@@ -356,6 +356,7 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
   std::vector<c64> kt((size_t)nk * 3 * N);
   std::vector<c32> kf(kt.size());
   std::vector<double> smin(nk);
+  std::vector<int> dcl(nk, 0);
   for (int ik = 0; ik < nk; ++ik) {
     const double* k = k_host + 3 * ik;
     double lo0[3], lo1[3];  // smallest and second smallest |K_a(q)|^2 over q, per axis
@@ -389,12 +390,21 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
     // smallest positive s(p) = sum_a |K_a(q_a)|^2: all axes at their minimum unless that sum
     // vanishes (k = 0: the DC frequency), then one axis at its second smallest value
     const double s0 = lo0[0] + lo0[1] + lo0[2];
-    double sm = s0;
-    if (!(s0 > 1e-300)) {
-      sm = INFINITY;
-      for (int a = 0; a < 3; ++a) sm = std::min(sm, s0 - lo0[a] + lo1[a]);
+    double s2 = INFINITY;  // the next value: one axis at its second smallest
+    for (int a = 0; a < 3; ++a) s2 = std::min(s2, s0 - lo0[a] + lo1[a]);
+    smin[ik] = (s0 > 1e-300) ? s0 : s2;
+    // Near Gamma (0 < |k| < 0.1) the rule of eq (2.26) gives gamma > 3948, growing as |k|^-2,
+    // and the penalty block then dominates the Rayleigh-Ritz pencil in FP64.  There the solver
+    // deflates the DC longitudinal direction instead (the constant field along k, an exact
+    // eigenvector with eigenvalue gamma |k|^2, Prop 2.3) and gamma = 4 pi^2 / s2 keeps every
+    // remaining penalty eigenvalue at or above 4 pi^2, the level the rule aims at.  Not applied
+    // to a gamma the caller gives.
+    const double kn2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    if (!gamma_host && kn2 > 0.0 && kn2 < 0.01) {
+      dcl[ik] = 1;
+      gam[ik] = fourpi2 / s2;
+      smin[ik] = s2;
     }
-    smin[ik] = sm;
   }
   // no k-points while the tables change (a failed upload leaves none), then the sizes that the
   // range checks of the other calls read
@@ -403,10 +413,18 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
   KC_TRY(upload(op->ktab64, kt));
   KC_TRY(upload(op->ktab32, kf));
   KC_TRY(upload(op->gamma_d, gam));
+  // The solver's preconditioners (K_P^{-1}, T_E) take s = |K(p)|^2 no smaller than this floor:
+  // near k = 0 the DC frequency has s = |k|^2 and a gain 1/|k|^2 that makes every new search
+  // direction nearly the same constant field, so the Rayleigh-Ritz pencil loses its rank.  The
+  // floor (1e-3 of (2 pi)^2, the size of s at the next frequencies) only changes the
+  // preconditioner, not the operator or its eigenpairs.
+  KC_TRY(upload(op->sfloor_d, std::vector<double>(nk, 4e-3 * M_PI * M_PI)));
+  KC_TRY(upload(op->dcl_d, dcl));
   op->kvec.assign(k_host, k_host + 3 * (size_t)nk);
   op->gamma = gam;
   op->smin = smin;
   op->kflags = kfl;
+  op->dcl = dcl;
   op->nk = nk;
   return KC_OK;
 }

@@ -66,7 +66,8 @@ template <int N, typename T, bool PRE, int P, bool XT = false>
 __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, cpx<T>* __restrict__ E,
                                                     const cpx<T>* __restrict__ ktab, VecMap vm,
                                                     const cpx<T>* __restrict__ gtw, cpx<T>* __restrict__ kx,
-                                                    const c64* __restrict__ ktab64, c64* __restrict__ kx64) {
+                                                    const c64* __restrict__ ktab64, c64* __restrict__ kx64,
+                                                    const double* __restrict__ sfl) {
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -95,9 +96,10 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
       const c64* Kd = ktab64 + (size_t)(vec / vm.vpk) * 3 * N;
       kx64[(size_t)vec * N3 + off] = Kd[e] * xv[off] + Kd[N + y] * xv[N3 + off] + Kd[2 * N + z] * xv[2 * N3 + off];
     }
-    if (PRE) {  // K_A^{+} = K_A^H / s
+    if (PRE) {  // K_A^{+} = K_A^H / s (s floored at sfl near k = 0)
       const T sq = abs2(v1) + abs2(v2) + abs2(v3);
-      const T is = sq > T(0) ? T(1) / sq : T(0);
+      const T fl = sfl ? static_cast<T>(sfl[vec / vm.vpk]) : T(0);
+      const T is = sq > T(0) ? T(1) / (sq < fl ? fl : sq) : T(0);
       c1 = is * c1;
       c2 = is * c2;
       c3 = is * c3;
@@ -132,7 +134,8 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
                                                         const c64* __restrict__ ktab64,
                                                         const double* __restrict__ gamma,
                                                         VecMap vm, VecMap vmy, const cpx<T>* __restrict__ gtw,
-                                                        const cpx<T>* __restrict__ kxin, const c64* __restrict__ kx64) {
+                                                        const cpx<T>* __restrict__ kxin, const c64* __restrict__ kx64,
+                                                        const double* __restrict__ sfl) {
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -185,13 +188,14 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
       const c64 x1 = xv[off], x2 = xv[N3 + off], x3 = xv[2 * N3 + off];
       kx = K1d * x1 + K2d * x2 + K3d * x3;
     }
-    if (PRE) {  // (1/s) [c + (1/gamma) K_B x / s]
+    if (PRE) {  // (1/s) [c + (1/gamma) K_B x / s], the outer 1/s floored at sfl near k = 0
       const double sq = abs2(K1d) + abs2(K2d) + abs2(K3d);
-      const double is = sq > 0.0 ? 1.0 / sq : 0.0;
+      const double fl = sfl ? sfl[ik] : 0.0;
+      const double is = sq > 0.0 ? 1.0 / sq : 0.0, ie = sq < fl ? 1.0 / fl : is;
       const c64 gk = (g * is) * kx;
-      yv[off] = is * (c1 + cmulc(K1d, gk));
-      yv[N3 + off] = is * (c2 + cmulc(K2d, gk));
-      yv[2 * N3 + off] = is * (c3 + cmulc(K3d, gk));
+      yv[off] = ie * (c1 + cmulc(K1d, gk));
+      yv[N3 + off] = ie * (c2 + cmulc(K2d, gk));
+      yv[2 * N3 + off] = ie * (c3 + cmulc(K3d, gk));
     } else {
       const c64 gk = g * kx;
       yv[off] = c1 + cmulc(K1d, gk);
@@ -674,22 +678,23 @@ static int tile_of(const kc_op* op, int pass) {
 template <int N, typename T, bool PRE, bool XT = false>
 static void launch_x1(kc_op* op, int pass, int nvec, const c64* x, cpx<T>* A, const cpx<T>* ktab, const VecMap& vm,
                       const cpx<T>* tw, hipStream_t s, cpx<T>* kx = nullptr, const c64* ktab64 = nullptr,
-                      c64* kx64 = nullptr) {
+                      c64* kx64 = nullptr, const double* sfl = nullptr) {
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
     k_x1_curl_inv<N, T, PRE, P, XT>
-        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw, kx, ktab64, kx64);
+        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw, kx, ktab64, kx64, sfl);
   });
 }
 
 template <int N, typename T, bool PRE, bool XT = false>
 static void launch_x2(kc_op* op, int pass, int nvec, const cpx<T>* A, const c64* x, c64* y, const cpx<T>* ktab,
                       const c64* ktab64, const double* gam, const VecMap& vm, const VecMap& vmy, const cpx<T>* tw,
-                      hipStream_t s, const cpx<T>* kx = nullptr, const c64* kx64 = nullptr) {
+                      hipStream_t s, const cpx<T>* kx = nullptr, const c64* kx64 = nullptr,
+                      const double* sfl = nullptr) {
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    k_x2_fwd_curl_pen<N, T, PRE, P, XT>
-        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(A, x, y, ktab, ktab64, gam, vm, vmy, tw, kx, kx64);
+    k_x2_fwd_curl_pen<N, T, PRE, P, XT><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(
+        A, x, y, ktab, ktab64, gam, vm, vmy, tw, kx, kx64, sfl);
   });
 }
 
@@ -819,8 +824,9 @@ static int apply_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const c64* x,
 // (same k-point grouping and active mask), and the two must not overlap.
 template <int N, typename T>
 static int apply_tp_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecMap& vmy, const c64* x, c64* y,
-                      const float* field, int fkstride, hipStream_t s) {
+                      const float* field, int fkstride, hipStream_t s, const double* sfl) {
   KC_TRY((tune_tiles_n<N, T>(op, nvec, s)));
+  if (sfl) sfl += ik0;
   constexpr size_t N3 = (size_t)N * N * N;
   const size_t nbuf = (size_t)nvec * 3 * N3 * sizeof(cpx<T>);
   KC_TRY(op->work_a.ensure(nbuf));
@@ -833,16 +839,17 @@ static int apply_tp_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecM
     if (fkstride == 0 && field == op->efield.as<float>() && op->efield_t.p != nullptr) {
       KC_TRY(op->work_k.ensure((size_t)nvec * N3 * sizeof(cpx<T>)));
       cpx<T>* kx = op->work_k.as<cpx<T>>();
-      launch_x1<N, T, true, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s, kx);
+      launch_x1<N, T, true, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s, kx, nullptr, nullptr, sfl);
       KC_LAUNCHED();
       launch_yz<N, T>(nvec, A, op->efield_t.as<float>(), pa.tw, act, s);
       KC_LAUNCHED();
-      launch_x2<N, T, true, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s, kx);
+      launch_x2<N, T, true, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s, kx,
+                                  nullptr, sfl);
       KC_LAUNCHED();
       return KC_OK;
     }
   }
-  launch_x1<N, T, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s);
+  launch_x1<N, T, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s, nullptr, nullptr, nullptr, sfl);
   KC_LAUNCHED();
   launch_y<N, +1, T>(op, TP_Y1, nvec, A, pa.tw, act, s);
   KC_LAUNCHED();
@@ -850,7 +857,8 @@ static int apply_tp_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecM
   KC_LAUNCHED();
   launch_y<N, -1, T>(op, TP_Y2, nvec, A, pa.tw, act, s);
   KC_LAUNCHED();
-  launch_x2<N, T, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s);
+  launch_x2<N, T, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s, nullptr, nullptr,
+                        sfl);
   KC_LAUNCHED();
   return KC_OK;
 }
@@ -1076,12 +1084,12 @@ int apply_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* r, c6
 }
 
 int apply_tp(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecMap& vmy, const c64* x, c64* y,
-             const float* field, int fkstride, int prec, hipStream_t s) {
+             const float* field, int fkstride, int prec, hipStream_t s, const double* sfl) {
   if (nvec == 0) return KC_OK;
   if (prec == KC_PREC_FP64) {
-    KC_DISPATCH_N(op->N, (apply_tp_n<NN, double>(op, ik0, nvec, vm, vmy, x, y, field, fkstride, s)))
+    KC_DISPATCH_N(op->N, (apply_tp_n<NN, double>(op, ik0, nvec, vm, vmy, x, y, field, fkstride, s, sfl)))
   } else {
-    KC_DISPATCH_N(op->N, (apply_tp_n<NN, float>(op, ik0, nvec, vm, vmy, x, y, field, fkstride, s)))
+    KC_DISPATCH_N(op->N, (apply_tp_n<NN, float>(op, ik0, nvec, vm, vmy, x, y, field, fkstride, s, sfl)))
   }
   set_error("unsupported N");
   return KC_ERR_UNSUPPORTED;

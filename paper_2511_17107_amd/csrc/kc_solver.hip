@@ -105,6 +105,13 @@ int rayleigh_ritz(Batch& B, bool implicit = false, bool fused = false) {
   return KC_OK;
 }
 
+// The new directions W of the k-points near Gamma whose DC longitudinal direction is deflated
+// (kc_set_kpoints) lose that component, so the search space never holds it.
+int deflate_w(Batch& B) {
+  return deflate_dc_long(B.S, B.nc, B.mb, B.mb, B.nb, B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N, B.N,
+                         B.op->dcl_d.as<int>() + B.ik0, B.s);
+}
+
 // Res and W = K_P^{-1} R; with copy_r also a contiguous copy of R for T_E, and W = K_P^{-1} R
 // only for the k-points that do not use T_E (wskip)
 int residuals(Batch& B, bool copy_r) {
@@ -112,8 +119,8 @@ int residuals(Batch& B, bool copy_r) {
   KC_TRY(resid_precond(B.S, B.AS, B.S, B.w->theta.as<double>(), B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N,
                        B.op->gamma_d.as<double>() + B.ik0, B.N, B.nc, 0, B.mb, B.mb, B.nb, B.w->part_res,
                        B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, R, nullptr,
-                       copy_r ? B.wskip : nullptr));
-  return KC_OK;
+                       copy_r ? B.wskip : nullptr, B.op->sfloor_d.as<double>() + B.ik0));
+  return deflate_w(B);
 }
 
 // W = T_E R (FP32 transforms) for the columns whose tmask is set; the others keep K_P^{-1} R
@@ -123,8 +130,9 @@ int precond_tp(Batch& B) {
   vx.kstride = B.mb;
   vy.kstride = B.nc;
   vx.active = vy.active = B.w->tmask.as<int>();
-  return apply_tp(B.op, B.ik0, B.nb * B.mb, vx, vy, B.w->R.as<c64>(), B.S + (size_t)B.mb * B.n, B.field, B.fks,
-                  KC_PREC_FP32, B.s);
+  KC_TRY(apply_tp(B.op, B.ik0, B.nb * B.mb, vx, vy, B.w->R.as<c64>(), B.S + (size_t)B.mb * B.n, B.field, B.fks,
+                  KC_PREC_FP32, B.s, B.op->sfloor_d.as<double>()));
+  return deflate_w(B);
 }
 
 int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig, double* res_out, int* iters,
@@ -232,6 +240,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
         for (int j = 0; j < m; ++j)
           for (int c = 0; c < 3; ++c) KC_HIP(hipMemsetAsync(w0 + (size_t)j * n + c * N3, 0, sizeof(c64), s));
     }
+    KC_TRY(deflate_w(B));
   }
   // T_E per k-point; with the learned field a k-point falls back to K_P^{-1} when the geometric
   // mean of its band residuals (each floored at tol) stops decreasing or grows
@@ -472,6 +481,17 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       KC_TRY(upload_ints(B.w->tmask.as<int>(), ht, s));
       napp += nt;
     }
+    // residual history: the largest Res_j (j < m) of every live k-point before this iteration
+    for (int b = 0; b < nb; ++b) {
+      if (done[b]) continue;
+      double mx = 0.0;
+      for (int j = 0; j < m; ++j) mx = std::max(mx, hres[b * mb + j]);
+      const size_t h = (size_t)(ik0 + b - op->hist_ik0);
+      if (h < op->hist.size()) {
+        op->hist[h].push_back(mx);
+        op->histp[h].push_back((int8_t)prec);
+      }
+    }
     const bool implicit = !full_gram && mxres > 1e4 * o.tol;
     KC_TRY(run_body(prec, implicit));
     ngram_w += implicit;
@@ -553,6 +573,9 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   }
   auto t0 = std::chrono::steady_clock::now();
   for (int i = 0; i < 8; ++i) op->stats[i] = 0.0;
+  op->hist.assign(nk, {});
+  op->histp.assign(nk, {});
+  op->hist_ik0 = ik0;
   bool allc = true;
   for (int k0 = 0; k0 < nk; k0 += o.batch_k) {
     const int nb = std::min(o.batch_k, nk - k0);
@@ -575,6 +598,18 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   if (!allc) {
     kc::set_error("some k-points did not reach tol within maxit");
     return KC_ERR_NO_CONVERGENCE;
+  }
+  return KC_OK;
+}
+
+int kc_last_residual_history(const kc_op* op, int k, double* res_host, int* prec_host, int cap, int* count) {
+  KC_ARG(op != nullptr && count != nullptr, "NULL op or count");
+  KC_ARG(k >= 0 && (size_t)k < op->hist.size(), "k outside the last solve's k-points");
+  const auto& h = op->hist[k];
+  *count = (int)h.size();
+  for (int i = 0; i < cap && (size_t)i < h.size(); ++i) {
+    if (res_host) res_host[i] = h[i];
+    if (prec_host) prec_host[i] = op->histp[k][i];
   }
   return KC_OK;
 }

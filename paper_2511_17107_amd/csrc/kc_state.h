@@ -78,6 +78,9 @@ struct kc_op {
   std::vector<double> kvec, gamma;  // [nk][3], [nk]
   kc::DevBuf ktab64, ktab32;        // 1D symbols [nk][3][N]
   kc::DevBuf gamma_d;               // double [nk]
+  kc::DevBuf sfloor_d;              // double [nk] floor of |K|^2 in the solver's preconditioners
+  kc::DevBuf dcl_d;                 // int [nk] 1: the solver deflates the DC longitudinal direction
+  std::vector<int> dcl;             // the same on the host
   kc::DevBuf work_a, work_b, work_c;  // operator intermediates
   kc::DevBuf work_k;                  // K . x per point (first x-pass -> last x-pass)
   kc::SolverWork* solver = nullptr;
@@ -88,11 +91,14 @@ struct kc_op {
   kc::DevBuf efield_k;        // f32 [nb][3][N^3] learned fields of the k-points being solved
   kc::DevBuf kdev;            // double [nk][3] wave vectors
   double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<std::vector<double>> hist;  // per k-point of the last kc_solve: max Res_j per iteration
+  std::vector<std::vector<int8_t>> histp; // ... and the precision of that iteration's AW
+  int hist_ik0 = 0;
   int8_t tiles[2][16] = {};     // tile width per pass (kc::TilePass), [FP32, FP64]; 0 = default
   bool tuned[2] = {false, false};
   // every device buffer of the handle takes its memory from `alloc`
   void bind_allocator() {
-    kc::DevBuf* bufs[] = {&ids, &eps64, &eps32, &tw64, &tw32, &ktab64, &ktab32, &gamma_d, &work_a, &work_b,
+    kc::DevBuf* bufs[] = {&ids, &eps64, &eps32, &tw64, &tw32, &ktab64, &ktab32, &gamma_d, &sfloor_d, &dcl_d, &work_a, &work_b,
                           &work_c, &work_k, &epsfeat, &efield, &efield_t, &efield_k, &kdev};
     for (kc::DevBuf* b : bufs) b->al = &alloc;
   }
@@ -109,9 +115,10 @@ int apply_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* r, c6
                   hipStream_t s);
 // y = T_E x, the transverse-projection preconditioner with the positive diagonal field E
 // (f32 [3][N^3] per k-point group at field + (v / vm.vpk) * fkstride * 3N^3); x is addressed
-// through vm, y through vmy (same grouping and active mask); x and y must not overlap.
+// through vm, y through vmy (same grouping and active mask); x and y must not overlap.  sfl
+// (device double per k-point of the call, or nullptr): floor of s = |K|^2 in the gains 1/s.
 int apply_tp(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecMap& vmy, const c64* x, c64* y,
-             const float* field, int fkstride, int prec, hipStream_t s);
+             const float* field, int fkstride, int prec, hipStream_t s, const double* sfl = nullptr);
 // per-grid kernel attributes (the LDS limit of the yz-plane pass); called by kc_create
 int prepare_kernels(int N);
 // E_c = 1/(eps^-1)_cc at the c-edge points (built on first use)

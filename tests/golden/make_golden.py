@@ -44,11 +44,23 @@ def case_sphere32_aniso():
     return wl, [(wl.kpoints[i], "crossdof") for i in sel]
 
 
+def case_illcond16():
+    wl = W.sphere_illconditioned(16)
+    return wl, [(wl.kpoints[0], s) for s in ("crossdof", "trivial")]
+
+
+def case_illcond32():
+    wl = W.sphere_illconditioned(32)
+    return wl, [(wl.kpoints[0], s) for s in ("crossdof", "trivial")]
+
+
 CASES = {
     "sphere16_iso": case_sphere16_iso,
     "sphere16_aniso": case_sphere16_aniso,
     "woodpile16_gyro": case_woodpile16_gyro,
     "sphere32_aniso": case_sphere32_aniso,
+    "illcond16": case_illcond16,
+    "illcond32": case_illcond32,
 }
 
 
@@ -72,7 +84,35 @@ def run(name):
         json.dump(out, f, indent=1)
 
 
+def run_neargamma(name="sphere16_neargamma"):
+    """Wave vectors within 0.1 of Gamma along Gamma-R.  The oracle uses gamma = 1000 (not the rule
+    of eq (2.26), whose gamma ~ |k|^-2 would leave the small eigenvalues at the accuracy floor of
+    the eigensolve); the physical eigenvalues do not depend on gamma (Prop 2.3), and the one
+    penalty eigenvalue among the lowest, gamma |k|^2 (the DC longitudinal field), is identified
+    by value and dropped."""
+    wl = W.sphere_anisotropic(N=16, nk=9, m=10)
+    g = 1000.0
+    out = {"workload": wl.name, "N": wl.N, "m": wl.m, "gamma": g, "cases": []}
+    for kn in (0.007, 0.02, 0.05):
+        k = kn * np.ones(3) / math.sqrt(3.0)
+        t = time.time()
+        Op = yee.compensated_operator(wl.N, k, wl.ids, wl.table, "crossdof", gamma=g)
+        w = eigs.smallest_positive(Op, wl.m + 1, method="shift_invert", zero_rel=1e-14)
+        pen = g * float(k @ k)
+        i = int(np.argmin(np.abs(w - pen)))
+        assert abs(w[i] - pen) <= 1e-8 * pen, (w, pen)
+        phys = np.delete(w, i)
+        out["cases"].append({"k": [float(v) for v in k], "scheme": "crossdof", "penalty_eigenvalue": float(w[i]),
+                             "eigenvalues": [float(v) for v in phys], "seconds": time.time() - t})
+        print(name, k, phys[:4], "%.1fs" % (time.time() - t), flush=True)
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
+    if sys.argv[1:] == ["sphere16_neargamma"]:
+        run_neargamma()
+        sys.exit(0)
     names = sys.argv[1:] or list(CASES)
     for nm in names:
         run(nm)

@@ -288,3 +288,48 @@ def test_solve_n128_homogeneous_closed_form(case):
         ref, bound = _homogeneous_lowest(N, kp[b], eps1, scheme, m)
         assert ref[-1] < bound  # the cube holds the m lowest eigenvalues
         assert np.max(np.abs(eig[b] - ref) / ref) <= REL, (case, b, eig[b], ref)
+
+
+def test_sphere64_mixed_matches_fp64_path():
+    """A reduced form of the 120-k-point mixed-precision launch set at 64^3 (anisotropic sphere,
+    16 bands + 4 guard, CrossDoF, T_E): the k-points Gamma, X, M, R and two interior points of the
+    path in one batch, FP32 operator phase + FP64 block algebra and finish, against the FP64
+    path per band (<= 1e-6 relative); k = 0 deflated in both."""
+    wl = W.sphere_anisotropic(N=64, nk=120, m=16)
+    kp = np.array([W.SC_POINTS[s] for s in ("G", "X", "M", "R")] + [wl.kpoints[17], wl.kpoints[93]])
+    op = kc.Op(64, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(kp)
+    out = {}
+    for prec in (kc.KC_PREC_FP32, kc.KC_PREC_FP64):
+        note("solve sphere64 prec", prec)
+        eig, res, its, st = op.solve(16, tol=TOL, guard=4, batch_k=len(kp), prec=prec, switch_tol=3e-4,
+                                     precond=kc.KC_PRECOND_TRANSVERSE)
+        assert st == 0 and res.max() <= TOL
+        out[prec] = eig
+        if prec == kc.KC_PREC_FP32:
+            assert op.last_solve_stats()[1] > 0  # FP32 applications happened
+    rel = np.abs(out[kc.KC_PREC_FP32] - out[kc.KC_PREC_FP64]) / out[kc.KC_PREC_FP64]
+    note("max per-band relative difference mixed vs fp64: %.2e" % rel.max())
+    assert rel.max() <= REL
+    assert np.all(out[kc.KC_PREC_FP64][0] > 1e-3)  # Gamma: the three constant fields stay out
+
+
+@pytest.mark.parametrize("prec,pc", [(kc.KC_PREC_FP64, kc.KC_PRECOND_DIAG), (kc.KC_PREC_FP32, kc.KC_PRECOND_TRANSVERSE)])
+def test_near_gamma_kpoints_match_oracle(prec, pc):
+    """Wave vectors 0.007, 0.02 and 0.05 from Gamma (where the rule of eq (2.26) would give gamma up
+    to 8e5): the library deflates the DC longitudinal direction and keeps gamma s2 = 4 pi^2; the
+    ten physical bands, including the two acoustic ones of size |k|^2 / eps, match the oracle's
+    (computed with gamma = 1000, the penalty eigenvalue gamma |k|^2 removed by value)."""
+    g = load("sphere16_neargamma")
+    wl = W.sphere_anisotropic(N=16, nk=9, m=10)
+    kp = np.array([c["k"] for c in g["cases"]])
+    op = kc.Op(16, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(kp)
+    note("near gamma solve", prec, pc)
+    eig, res, its, st = op.solve(10, tol=TOL, guard=4, batch_k=len(kp), prec=prec, switch_tol=1e-4, precond=pc)
+    assert st == 0 and res.max() <= TOL
+    assert not (op.kpoint_flags() & kc.KC_KFLAG_SPURIOUS_RISK).any()
+    assert np.all(op.spurious_bound() == pytest.approx(4 * math.pi ** 2, rel=1e-12))
+    for i, c in enumerate(g["cases"]):
+        ref = np.array(c["eigenvalues"])
+        assert np.max(np.abs(eig[i] - ref) / ref) <= REL, (c["k"], eig[i], ref)

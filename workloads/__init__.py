@@ -270,6 +270,31 @@ def random_inclusions(N: int, seed: int, nk: int = 1, m: int = 16,
     return Workload("sc%d-random-%d" % (N, seed), N, ids, eps_table(eps_list), sc_kpath(nk), m, scheme)
 
 
+def random_unitary(rng: np.random.Generator) -> np.ndarray:
+    """Haar-distributed 3x3 unitary: Q of the QR of a complex standard normal matrix, columns
+    scaled by the phases of diag(R)."""
+    g = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    q, r = np.linalg.qr(g)
+    d = np.diag(r)
+    return q * (d / np.abs(d))[None, :]
+
+
+def sphere_illconditioned(N: int, seed: int = 0, radius: float = 0.25, m: int = 10,
+                          k=(math.pi / 7, 3 * math.pi / 5, 4 * math.pi / 13),
+                          scheme: str = "crossdof") -> Workload:
+    """Section 4, robustness under extreme cases: an inclusion whose inverse permittivity is
+    U diag(1e-1, 1e-3, 1e-5) U^H with U a random unitary from `seed` (complex Hermitian, condition
+    number 1e4), here a sphere of radius `radius` at the cell centre in air, at the paper's wave
+    vector (1/7, 3/5, 4/13) pi."""
+    rng = np.random.default_rng(seed)
+    U = random_unitary(rng)
+    einv = (U * np.array([1e-1, 1e-3, 1e-5])[None, :]) @ U.conj().T
+    einv = 0.5 * (einv + einv.conj().T)
+    ids = sample_ids(N, [Sphere((0.5, 0.5, 0.5), radius, 1)])
+    table = np.stack([np.eye(3, dtype=np.complex128), einv])
+    return Workload("sc%d-sphere-illcond" % N, N, ids, table, np.array([k], dtype=np.float64), m, scheme)
+
+
 def smooth_isotropic(N: int, k=(math.pi, math.pi, math.pi), m: int = 8) -> Workload:
     """Simple-cubic cell with the smooth isotropic permittivity eps = 8.9 sin(2 pi (x+y+z)) + 13
     (Section 4, eq (4.7)).  Every sample point of the Yee cell has x + y + z = (t - 1/2) h mod 1
