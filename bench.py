@@ -15,8 +15,9 @@ reuses it.  Prints one JSON line (see the keys below).
     python bench.py --matvec-only | --update-only     (single kernels, for rocprofv3)
 
 `roofline` is the fused block update + residual pass (the largest kernel of a step), timed live
-at the solve's batch shape after the solve; `matvec` lists the operator passes with their own
-`roofline` entry for the longest one.
+at the solve's batch shape after the solve; `matvec` lists the operator passes, the roofline of
+the whole application (pass-structure bytes, counter bytes and the boundary's bytes over its
+time) and that of its longest pass.
 """
 import argparse
 import json
@@ -78,10 +79,15 @@ def parse():
     ap.add_argument("--update-only", action="store_true",
                     help="only the fused block update (kc_block_update) at the solve's batch shape, three "
                          "launches, and the 1 GiB device copy; for profiling")
-    ap.add_argument("--workload", choices=["c4", "c2", "c3"], default="c4",
+    ap.add_argument("--workload", choices=["c4", "c2", "c3", "c5"], default="c4",
                     help="c4: the headline (128^3 woodpile); c2: 64^3 anisotropic sphere, 20 bands, 40 "
                          "k-points, FP64; c3: the same sphere, 16 bands, 120 k-points in two launch sets, "
-                         "mixed precision against the FP64 path (per-band eigenvalue differences)")
+                         "mixed precision against the FP64 path (per-band eigenvalue differences); c5: train "
+                         "the learned preconditioner on 500 random geometries (32^3 and 64^3) and compare it at "
+                         "96^3 (40 k-points) with the FP64 diagonal-preconditioned path")
+    ap.add_argument("--c5-geoms", type=int, nargs=2, default=[400, 100],
+                    help="training geometries at 32^3 and at 64^3 (c5)")
+    ap.add_argument("--c5-steps", type=int, default=600)
     ap.add_argument("--verbose", type=int, default=0)
     return ap.parse_args()
 
@@ -291,6 +297,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.workload == "c5":
+        from paper_2511_17107_amd import learned
+
+        out = learned.c5(geoms32=a.c5_geoms[0], geoms64=a.c5_geoms[1], steps=a.c5_steps,
+                         log=lambda *v: print(*v, file=sys.stderr, flush=True))
+        print(json.dumps(out), flush=True)
+        return
     if a.workload != "c4":
         sphere64_run(a, dev)
         return
@@ -360,6 +373,21 @@ def main():
     mv_time = float(ms.sum())
     alg_mv = (16 * 3 * a.N ** 3 * 2 + 4 * a.N ** 3) * a.m  # read x, write y, read ids
     tiles = {"fp32": op.tile_widths(kc.KC_PREC_FP32).tolist(), "fp64": op.tile_widths(kc.KC_PREC_FP64).tolist()}
+    # the whole operator application (all passes of one kc_apply on a.m vectors): the pass
+    # structure's algorithmic bytes, the counter-measured HBM bytes at the tuned widths (when the
+    # profile covers them), and the boundary's bytes (read x, write y, read the ids) over its time
+    traffic = [MEASURED_TRAFFIC.get((nm, a.N, a.m, a.prec, tiles[a.prec][PASS_SLOT[nm]])) for nm in names]
+    tsum = None if any(t is None for t in traffic) else float(sum(traffic))
+    alg_sum = float(sum(pbytes))
+    sec = mv_time * 1e-3
+    app_roofline = {"bound": "hbm", "kernel": "operator application (%d pencil passes)" % len(names),
+                    "achieved": alg_sum / sec / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": alg_sum / sec / 1e9 / HBM_PEAK_GBS, "alg_bytes": alg_sum, "ms_per_launch": mv_time,
+                    "traffic": tsum,
+                    "traffic_GBps": None if tsum is None else tsum / sec / 1e9,
+                    "traffic_frac": None if tsum is None else tsum / sec / 1e9 / HBM_PEAK_GBS,
+                    "boundary_bytes": float(alg_mv), "boundary_GBps": alg_mv / sec / 1e9,
+                    "boundary_frac": alg_mv / sec / 1e9 / HBM_PEAK_GBS}
     del x
     # the solver's block workspace (~180 GB at the default batch) goes with the handle, which
     # makes room for the update measurement's own blocks
@@ -396,13 +424,14 @@ def main():
                    "alg_GBps": [round(g, 1) for g in gbs], "nvec": a.m,
                    "ms_per_band": mv_time / a.m,
                    "effective_GBps": alg_mv / (mv_time * 1e-3) / 1e9,
-                   "roofline": {"bound": "hbm", "kernel": "matvec pass " + names[dom],
-                                "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                "frac": gbs[dom] / HBM_PEAK_GBS,
-                                "traffic": MEASURED_TRAFFIC.get(
-                                    (names[dom], a.N, a.m, a.prec, tiles[a.prec][PASS_SLOT[names[dom]]])),
-                                "tile_width": tiles[a.prec][PASS_SLOT[names[dom]]],
-                                "alg_bytes": pbytes[dom]}},
+                   "roofline": app_roofline,
+                   "longest_pass": {"bound": "hbm", "kernel": "matvec pass " + names[dom],
+                                    "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                    "frac": gbs[dom] / HBM_PEAK_GBS,
+                                    "traffic": MEASURED_TRAFFIC.get(
+                                        (names[dom], a.N, a.m, a.prec, tiles[a.prec][PASS_SLOT[names[dom]]])),
+                                    "tile_width": tiles[a.prec][PASS_SLOT[names[dom]]],
+                                    "alg_bytes": pbytes[dom]}},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.kpoints)

@@ -104,10 +104,13 @@ int kc_supported_n(int N);
 
 /*
  * Create an operator for grid division N and an inverse-permittivity field.
- *   lattice_host : NULL or float64 [3][3], the primitive lattice vectors as rows (lattice
- *                  constant 1).  Only the simple-cubic lattice (the identity) is supported;
- *                  other lattices (the coordinate transform of Section 2.2) give
- *                  KC_ERR_UNSUPPORTED.
+ *   lattice_host : NULL (simple cubic) or float64 [3][3], the primitive lattice vectors a_1,
+ *                  a_2, a_3 as rows (lattice constant 1; e.g. FCC, BCC of eq (4.1)).  The grid is
+ *                  the unit cube of fractional coordinates (the coordinate transform of
+ *                  Section 2.2): the point of index (i, j, k) sits at x = sum_r xi_r a_r, and the
+ *                  difference blocks become sum_j b_ji D_{1,j} + i k_i D_{0,i}, b = A^{-1},
+ *                  A = (a_1 a_2 a_3) (eq (2.12), the sum taken over the axis of D_1).  Wave
+ *                  vectors stay Cartesian.  Dependent vectors: KC_ERR_INVALID_ARG.
  *   stencil_m    : 1..5, order 2m of the finite-difference stencils of the curl and
  *                  divergence (eq (2.34), coefficients from eq (2.35), Table 1); 1 is the
  *                  second-order Yee scheme of eq (2.5).  The cross-DoF transfer T of eq (3.7)
@@ -320,8 +323,10 @@ void kc_solve_opts_default(kc_solve_opts* opts);
  *   iters_host : int32 [nk] iterations used (may be NULL)
  *   X_out      : NULL, or device complex128 [nk][m][3][N^3] for the eigenvectors
  * At k = 0 the three constant fields (Prop 2.5 (1)) are deflated and not reported.
- * Returns KC_ERR_NO_CONVERGENCE if some k-point did not reach tol within maxit (outputs
- * then hold the last iterate).
+ * Returns KC_ERR_NO_CONVERGENCE if some k-point did not reach tol within maxit, or stagnated
+ * (in the FP64 phase its largest band residual did not halve in 200 iterations, e.g. with a tol
+ * below the rounding floor of the operator's FP64 application); the outputs then hold that
+ * k-point's last iterate.
  */
 int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_host,
              double* res_host, int* iters_host, void* X_out, void* stream);
@@ -350,6 +355,11 @@ int kc_last_residual_history(const kc_op* op, int k, double* res_host, int* prec
  * up to 32 vectors and the fastest kept; smaller grids use a fixed rule.
  */
 int kc_tile_widths(const kc_op* op, int prec, int* widths_host);
+
+/* Release the handle's work buffers (the LOBPCG blocks of kc_solve and the operator's
+ * intermediates; they are allocated again on the next call that needs them), keeping the
+ * geometry, tables and k-points.  Waits for the device first. */
+int kc_release_workspaces(kc_op* op);
 
 /* Release the handle and every device buffer it owns.  NULL is allowed. */
 void kc_destroy(kc_op* op);

@@ -60,7 +60,7 @@ def all_eigenvalues(Op) -> np.ndarray:
 def smallest_positive_matfree(N: int, k, ids: np.ndarray, table: np.ndarray, scheme: str, m: int,
                               gamma: float | None = None, stencil_m: int = 1, sigma: float = -1.0,
                               cg_rtol: float = 1e-12, arpack_tol: float = 1e-10,
-                              return_vectors: bool = False):
+                              return_vectors: bool = False, lattice=None):
     """m smallest strictly positive eigenvalues of Op = A M A^H + gamma B^H B (eq (2.13)) for
     grids too large to factor: shift-invert Lanczos (ARPACK) about sigma = -1, the inner solves
     of (Op - sigma I) y = b by conjugate gradients on the product of the sparse factors A, M, B
@@ -70,9 +70,9 @@ def smallest_positive_matfree(N: int, k, ids: np.ndarray, table: np.ndarray, sch
     inverse permittivity c), which changes the speed of the inner solves, not their solution."""
     if gamma is None:
         gamma = yee.gamma_rule(k)
-    A = yee.curl_matrix(N, k, stencil_m)
+    A = yee.curl_matrix(N, k, stencil_m, lattice)
     AH = A.conj().T.tocsr()
-    B = yee.div_matrix(N, k, stencil_m)
+    B = yee.div_matrix(N, k, stencil_m, lattice)
     BH = B.conj().T.tocsr()
     Mx = yee.eps_matrix(N, ids, table, scheme)
     n = 3 * N ** 3
@@ -83,7 +83,7 @@ def smallest_positive_matfree(N: int, k, ids: np.ndarray, table: np.ndarray, sch
     # curl part scaled by the mean diagonal inverse permittivity over the edge points
     P = yee.point_tensors(ids, table)
     c = float(np.mean([P[a][:, a, a].real.mean() for a in range(3)]))
-    K = kspace.symbols_3d(N, k, stencil_m)
+    K = kspace.symbols_3d(N, k, stencil_m, lattice)
     KA = kspace.curl_symbol(K)
     KP = c * (KA @ KA.conj().transpose(0, 2, 1)) + gamma * kspace.div_symbol_gram(K) - sigma * np.eye(3)[None]
     KPinv = np.linalg.inv(KP)                                  # (N^3, 3, 3)

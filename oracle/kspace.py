@@ -62,12 +62,24 @@ def symbols_1d(N: int, k: Sequence[float], m: int = 1):
     return [l1 + 1j * k[a] * l0 for a in range(3)]
 
 
-def symbols_3d(N: int, k: Sequence[float], m: int = 1) -> np.ndarray:
+def symbols_3d(N: int, k: Sequence[float], m: int = 1, lattice=None) -> np.ndarray:
     """K_1, K_2, K_3 as full diagonals over the k-space index p = qx + N qy + N^2 qz (eq (2.28)),
-    complex (3, N^3)."""
-    s = symbols_1d(N, k, m)
+    complex (3, N^3).  For a general lattice, the eigenvalues of the blocks of eq (2.12):
+    K_i(p) = sum_j b_ji Lambda_1(q_j) + i k_i Lambda_0(q_i), b = A^{-1} (Lemma 2.1 per axis)."""
     qz, qy, qx = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
-    return np.stack([s[0][qx.ravel()], s[1][qy.ravel()], s[2][qz.ravel()]])
+    q = [qx.ravel(), qy.ravel(), qz.ravel()]
+    if lattice is None:
+        s = symbols_1d(N, k, m)
+        return np.stack([s[0][q[0]], s[1][q[1]], s[2][q[2]]])
+    D1 = yee.circulant_d1(N, m).toarray()
+    D0 = yee.circulant_d0(N, m).toarray()
+    l1 = circulant_eigenvalues(D1[0])
+    l0 = circulant_eigenvalues(D0[0])
+    b = yee.lattice_inverse(lattice)
+    K = np.zeros((3, N ** 3), dtype=np.complex128)
+    for i in range(3):
+        K[i] = 1j * k[i] * l0[q[i]] + sum(b[j, i] * l1[q[j]] for j in range(3))
+    return K
 
 
 def curl_symbol(K: np.ndarray) -> np.ndarray:
@@ -85,18 +97,19 @@ def div_symbol_gram(K: np.ndarray) -> np.ndarray:
     return np.einsum("ap,bp->pab", K.conj(), K)
 
 
-def precond_matrices(N: int, k: Sequence[float], gamma: float, m: int = 1) -> np.ndarray:
+def precond_matrices(N: int, k: Sequence[float], gamma: float, m: int = 1, lattice=None) -> np.ndarray:
     """K_P = K_A K_A^H + gamma K_B per frequency, (N^3, 3, 3) (eq (2.31))."""
-    K = symbols_3d(N, k, m)
+    K = symbols_3d(N, k, m, lattice)
     A = curl_symbol(K)
     return A @ A.conj().transpose(0, 2, 1) + gamma * div_symbol_gram(K)
 
 
-def precond_apply(N: int, k: Sequence[float], gamma: float, r: np.ndarray, m: int = 1) -> np.ndarray:
+def precond_apply(N: int, k: Sequence[float], gamma: float, r: np.ndarray, m: int = 1,
+                  lattice=None) -> np.ndarray:
     """z = K_P^{-1} r per frequency (eq (2.32)), r of shape (nvec, 3, N^3).  Where K_P is
     singular (only the DC frequency at k = 0, whose modes are the constant fields of Prop 2.5)
     the output is zero."""
-    KP = precond_matrices(N, k, gamma, m)
+    KP = precond_matrices(N, k, gamma, m, lattice)
     r = np.asarray(r, dtype=np.complex128)
     z = np.zeros_like(r)
     scale = np.abs(KP).reshape(KP.shape[0], -1).max(axis=1)
@@ -130,7 +143,7 @@ def edge_permittivity(ids: np.ndarray, table: np.ndarray) -> np.ndarray:
 
 
 def transverse_precond_apply(N: int, k: Sequence[float], gamma: float, E: np.ndarray,
-                             r: np.ndarray, m: int = 1) -> np.ndarray:
+                             r: np.ndarray, m: int = 1, lattice=None) -> np.ndarray:
     """z = T_E r with T_E = K_A^{+H} F3^H diag(E) F3 K_A^{+} + (gamma K_B)^{+}, the
     transverse-projection preconditioner (Johnson & Joannopoulos, Opt. Express 8 (2001) 173)
     written for the operator of eq (2.30): the curl part of Op with the inverse permittivity M
@@ -138,7 +151,7 @@ def transverse_precond_apply(N: int, k: Sequence[float], gamma: float, E: np.nda
     per frequency (numpy.linalg.pinv), plus the pseudo-inverse of the penalty block.
     E: real (3, N^3) on the edge points (component c scales the c-edge values), one field for
     all vectors or (nvec, 3, N^3); r: (nvec, 3, N^3); m: stencil order 2m (eq (2.34))."""
-    K = symbols_3d(N, k, m)
+    K = symbols_3d(N, k, m, lattice)
     A = curl_symbol(K)
     Ap = np.linalg.pinv(A, rcond=1e-12)                      # (N^3, 3, 3)
     Bp = np.linalg.pinv(gamma * div_symbol_gram(K), rcond=1e-12)

@@ -87,22 +87,43 @@ def embed(M1: sp.spmatrix, axis: int, N: int) -> sp.csr_matrix:
     return sp.kron(M1, sp.identity(N * N, format="csr"), format="csr")
 
 
-def deriv_blocks(N: int, k: Sequence[float], m: int = 1):
+def lattice_inverse(lattice) -> np.ndarray:
+    """b = A^{-1} for the lattice matrix A = (a_1, a_2, a_3) whose COLUMNS are the primitive
+    vectors (Section 2.2, eq (2.8)); `lattice` lists the vectors as rows (None: simple cubic)."""
+    if lattice is None:
+        return np.eye(3)
+    A = np.asarray(lattice, dtype=np.float64).reshape(3, 3).T
+    return np.linalg.inv(A)
+
+
+def deriv_blocks(N: int, k: Sequence[float], m: int = 1, lattice=None):
     """D_i = D_{1,i} + i k_i D_{0,i}, i = 1, 2, 3 (eq (2.6)), complex sparse N^3 x N^3, with the
-    order-2m first rows of eq (2.34) (m = 1 is eq (2.5))."""
+    order-2m first rows of eq (2.34) (m = 1 is eq (2.5)).  For a general lattice (Section 2.2,
+    eq (2.12)) the difference part follows the transformed gradient of eq (2.11):
+    D_i = sum_j b_ji D_{1,j} + i k_i D_{0,i}, b = A^{-1} (the printed eq (2.12) has D_{1,i} under
+    the sum over j; the derivative along lattice axis j is D_{1,j})."""
     D1, D0 = circulant_d1(N, m), circulant_d0(N, m)
-    return [(embed(D1, a, N) + 1j * k[a] * embed(D0, a, N)).tocsr() for a in range(3)]
+    b = lattice_inverse(lattice)
+    E1 = [embed(D1, j, N) for j in range(3)]
+    out = []
+    for i in range(3):
+        Di = 1j * k[i] * embed(D0, i, N)
+        for j in range(3):
+            if b[j, i] != 0.0:
+                Di = Di + b[j, i] * E1[j]
+        out.append(Di.tocsr())
+    return out
 
 
-def curl_matrix(N: int, k: Sequence[float], m: int = 1) -> sp.csr_matrix:
+def curl_matrix(N: int, k: Sequence[float], m: int = 1, lattice=None) -> sp.csr_matrix:
     """Outer curl A (edge -> face), eq (2.7): [[0, -D3, D2], [D3, 0, -D1], [-D2, D1, 0]]."""
-    D1, D2, D3 = deriv_blocks(N, k, m)
+    D1, D2, D3 = deriv_blocks(N, k, m, lattice)
     return sp.bmat([[None, -D3, D2], [D3, None, -D1], [-D2, D1, None]], format="csr")
 
 
-def div_matrix(N: int, k: Sequence[float], m: int = 1) -> sp.csr_matrix:
+def div_matrix(N: int, k: Sequence[float], m: int = 1, lattice=None) -> sp.csr_matrix:
     """Divergence B (face -> volume), eq (2.7): [D1, D2, D3]."""
-    D1, D2, D3 = deriv_blocks(N, k, m)
+    D1, D2, D3 = deriv_blocks(N, k, m, lattice)
     return sp.hstack([D1, D2, D3], format="csr")
 
 
@@ -170,13 +191,14 @@ def gamma_rule(k: Sequence[float]) -> float:
 
 
 def compensated_operator(N: int, k: Sequence[float], ids: np.ndarray, table: np.ndarray,
-                         scheme: str, gamma: float | None = None, m: int = 1) -> sp.csr_matrix:
+                         scheme: str, gamma: float | None = None, m: int = 1, lattice=None) -> sp.csr_matrix:
     """Op = A M A^H + gamma B^H B, eq (2.13); gamma defaults to eq (2.26); curl and divergence
-    with the order-2m stencils of eq (2.34) (Remark 2.10: the penalty rule is unchanged)."""
+    with the order-2m stencils of eq (2.34) (Remark 2.10: the penalty rule is unchanged) and the
+    lattice's transformed blocks of eq (2.12) (lattice vectors as rows, None: simple cubic)."""
     if gamma is None:
         gamma = gamma_rule(k)
-    A = curl_matrix(N, k, m)
-    B = div_matrix(N, k, m)
+    A = curl_matrix(N, k, m, lattice)
+    B = div_matrix(N, k, m, lattice)
     M = eps_matrix(N, ids, table, scheme)
     Op = (A @ M @ A.conj().T + gamma * (B.conj().T @ B)).tocsr()
     return Op

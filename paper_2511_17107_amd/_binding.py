@@ -107,6 +107,7 @@ def lib():
         L.kc_last_solve_stats.argtypes = [vp, vp]
         L.kc_last_residual_history.argtypes = [vp, i32, vp, vp, i32, vp]
         L.kc_tile_widths.argtypes = [vp, i32, vp]
+        L.kc_release_workspaces.argtypes = [vp]
         L.kc_destroy.argtypes = [vp]
         L.kc_destroy.restype = None
         L.kc_net_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(vp)]
@@ -295,7 +296,8 @@ def block_update(S, AS, C, theta, R=None, res=None, xnorm2=None, work=None, stre
 class Op:
     """Handle of one operator (grid, inverse-permittivity field, k-points).
 
-    lattice: None (simple cubic) or (3, 3) lattice vectors as rows; stencil_m: order 2m of the
+    lattice: None (simple cubic) or (3, 3) primitive lattice vectors as rows (Section 2.2); ids and
+    table then describe the unit-cube grid of fractional coordinates; stencil_m: order 2m of the
     curl/divergence stencils (1..5); allocator: "torch" (PyTorch's caching allocator backs the
     handle's device workspaces) or "hip" (the library's hipMalloc)."""
 
@@ -335,6 +337,10 @@ class Op:
 
     def __del__(self):
         self.close()
+
+    def release_workspaces(self):
+        """Free the solver blocks and operator intermediates (allocated again when needed)."""
+        _check(lib().kc_release_workspaces(self._h), "kc_release_workspaces")
 
     @property
     def n3(self) -> int:

@@ -51,7 +51,8 @@ int update_res_prepare();
 int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
                   const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
                   double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout = nullptr,
-                  double* rnorm2 = nullptr, const int* wskip = nullptr, const double* sfl = nullptr);
+                  double* rnorm2 = nullptr, const int* wskip = nullptr, const double* sfl = nullptr,
+                  const Skew* sk = nullptr);
 
 // Removes the DC longitudinal direction (x(0) along conj(K(0))) from columns [col0, col0 + ncol)
 // of the k-points b with dcl[b] != 0 (kstride-spaced groups; FP64).
@@ -70,8 +71,11 @@ constexpr int RR_THREADS = 1024;  // one workgroup per k-point: 16 waves hide th
 // (P_new orthonormal and orthogonal to X_new in the GB inner product).  The columns of S need
 // not be normalised or orthogonal: the pencil is scaled to unit diagonal first.
 // Also writes gapp_out[b] = P_new^H A P_new = Cp^H GA Cp (mb x mb) for the next step's gramw.
+// res (device [nb * mb], or nullptr): the current residual norms |r_j| of the (orthonormal) X
+// block, theta its current Ritz values: a step whose Ritz values fall below what they allow is
+// rejected (X kept, P dropped, flags[b] |= 2).
 int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,
              double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, c64* gapp_out,
-             hipStream_t s);
+             hipStream_t s, const double* res = nullptr);
 
 }  // namespace kc

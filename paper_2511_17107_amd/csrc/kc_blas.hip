@@ -618,7 +618,7 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
                                                        int xcol0, int wcol0, int mb, double* __restrict__ part,
                                                        const int* __restrict__ kskip, c64* __restrict__ Rout,
                                                        const int* __restrict__ wskip,
-                                                       const double* __restrict__ sfl) {
+                                                       const double* __restrict__ sfl, Skew sk) {
   const int b = blockIdx.z, j = blockIdx.y;
   if (kskip && kskip[b]) return;
   const bool ww = !(wskip && wskip[b]);
@@ -634,7 +634,8 @@ __global__ __launch_bounds__(256) void k_resid_precond(const c64* __restrict__ S
   double rr = 0.0, xx = 0.0;
   for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N3; p += (size_t)gridDim.x * blockDim.x) {
     const int qx = (int)(p % N), qy = (int)((p / N) % N), qz = (int)(p / ((size_t)N * N));
-    const c64 K1 = K[qx], K2 = K[N + qy], K3 = K[2 * N + qz];
+    c64 K1 = K[qx], K2 = K[N + qy], K3 = K[2 * N + qz];
+    skew_fix<double>(sk, qx, qy, qz, K1, K2, K3);
     const c64 x1 = x[p], x2 = x[N3 + p], x3 = x[2 * N3 + p];
     const c64 r1 = ax[p] - th * x1, r2 = ax[N3 + p] - th * x2, r3 = ax[2 * N3 + p] - th * x3;
     rr += abs2(r1) + abs2(r2) + abs2(r3);
@@ -948,13 +949,13 @@ int update_res(c64* S, c64* AS, int kstride, int mb, const c64* C, size_t n, int
 int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, const c64* ktab64,
                   const double* gamma, int N, int kstride, int xcol0, int wcol0, int mb, int nb, DevBuf& part,
                   double* res, double* xnorm2, const int* kskip, hipStream_t s, c64* Rout, double* rnorm2,
-                  const int* wskip, const double* sfl) {
+                  const int* wskip, const double* sfl, const Skew* sk) {
   const size_t N3 = (size_t)N * N * N;
   const int nblk = (int)std::max<size_t>(1, std::min<size_t>((N3 + 255) / 256, 256));
   KC_TRY(part.ensure((size_t)nb * mb * nblk * 2 * sizeof(double)));
   dim3 grid(nblk, mb, nb);
   k_resid_precond<<<grid, 256, 0, s>>>(S, AS, W, theta, ktab64, gamma, N, kstride, xcol0, wcol0, mb,
-                                       part.as<double>(), kskip, Rout, wskip, sfl);
+                                       part.as<double>(), kskip, Rout, wskip, sfl, sk ? *sk : Skew());
   KC_LAUNCHED();
   const int nv = nb * mb;
   k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2, rnorm2);

@@ -246,14 +246,34 @@ int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, 
     set_error("grid division N=" + std::to_string(N) + " is not a supported FFT length");
     return KC_ERR_UNSUPPORTED;
   }
+  // lattice: A = (a_1 a_2 a_3) with the primitive vectors as columns, b = A^{-1} (Section 2.2);
+  // the symbols need C_ij = b_ji - delta_ij (eq (2.12))
+  double cmat[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  bool skewed = false;
   if (lattice_host != nullptr) {
+    double A[3][3];
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) {
         KC_ARG(std::isfinite(lattice_host[r * 3 + c]), "non-finite lattice vector");
-        if (std::fabs(lattice_host[r * 3 + c] - (r == c ? 1.0 : 0.0)) > 1e-12) {
-          set_error("only the simple-cubic lattice (identity lattice vectors) is supported");
-          return KC_ERR_UNSUPPORTED;
-        }
+        A[c][r] = lattice_host[r * 3 + c];  // vector r is column r of A
+      }
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                       A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    double nrm = 0.0;
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) nrm = std::max(nrm, std::fabs(A[r][c]));
+    KC_ARG(std::fabs(det) > 1e-9 * nrm * nrm * nrm, "lattice vectors are linearly dependent");
+    double b[3][3];  // inverse by cofactors
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        const int r1 = (c + 1) % 3, r2 = (c + 2) % 3, c1 = (r + 1) % 3, c2 = (r + 2) % 3;
+        b[r][c] = (A[r1][c1] * A[r2][c2] - A[r1][c2] * A[r2][c1]) / det;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        cmat[i * 3 + j] = b[j][i] - (i == j ? 1.0 : 0.0);
+        if (std::fabs(cmat[i * 3 + j]) > 1e-15) skewed = true;
       }
   }
   KC_ARG(stencil_m >= 1 && stencil_m <= 5, "stencil_m must be in [1, 5] (orders 2 to 10)");
@@ -316,6 +336,36 @@ int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, 
   make_twiddles(N, twd, twf);
   if (st == KC_OK) st = upload(op->tw64, twd, hs);
   if (st == KC_OK) st = upload(op->tw32, twf, hs);
+  if (st == KC_OK && skewed) {
+    // Lambda_1(q) = (1/h) sum_s c1_s (e^{i(s-1)theta} - e^{-i s theta}), theta = 2 pi q/N
+    double c1[5], c0[5];
+    stencil_coeffs(stencil_m, c1, c0);
+    std::vector<c64> l64(N);
+    std::vector<c32> l32(N);
+    for (int q = 0; q < N; ++q) {
+      const double th = 2.0 * M_PI * (double)q / (double)N;
+      std::complex<double> l(0.0, 0.0);
+      for (int t = 1; t <= stencil_m; ++t) l += c1[t - 1] * (std::polar(1.0, (t - 1) * th) - std::polar(1.0, -t * th));
+      l *= (double)N;
+      l64[q] = mk(l.real(), l.imag());
+      l32[q] = mk((float)l.real(), (float)l.imag());
+    }
+    st = op->lam1.ensure(N * (sizeof(c64) + sizeof(c32)));
+    if (st == KC_OK) {
+      hipError_t e = hipMemcpyAsync(op->lam1.p, l64.data(), N * sizeof(c64), hipMemcpyHostToDevice, hs);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync((char*)op->lam1.p + N * sizeof(c64), l32.data(), N * sizeof(c32), hipMemcpyHostToDevice,
+                           hs);
+      if (e == hipSuccess) e = hipStreamSynchronize(hs);
+      if (e != hipSuccess) {
+        set_error(std::string("upload of the lattice symbols: ") + hipGetErrorString(e));
+        st = KC_ERR_HIP;
+      }
+    }
+    op->skew.l1d = op->lam1.as<c64>();
+    op->skew.l1f = (const c32*)((const char*)op->lam1.p + N * sizeof(c64));
+    for (int i = 0; i < 9; ++i) op->skew.c[i] = cmat[i];
+  }
   if (st == KC_OK) st = prepare_kernels(N);
   if (st != KC_OK) {
     delete op;
@@ -355,13 +405,14 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
   stencil_coeffs(op->stencil_m, c1, c0);
   std::vector<c64> kt((size_t)nk * 3 * N);
   std::vector<c32> kf(kt.size());
-  std::vector<double> smin(nk);
+  std::vector<double> smin(nk), smax(nk);
   std::vector<int> dcl(nk, 0);
   for (int ik = 0; ik < nk; ++ik) {
     const double* k = k_host + 3 * ik;
-    double lo0[3], lo1[3];  // smallest and second smallest |K_a(q)|^2 over q, per axis
+    double lo0[3], lo1[3], hi[3];  // smallest, second smallest and largest |K_a(q)|^2 over q
     for (int a = 0; a < 3; ++a) {
       lo0[a] = lo1[a] = INFINITY;
+      hi[a] = 0.0;
       for (int q = 0; q < N; ++q) {
         // eigenvalues of the circulants D1 and D0 (first rows from eq (2.34)) by Lemma 2.1,
         // theta = 2 pi q/N: D1 -> (1/h) sum_s c1_s (e^{i(s-1)theta} - e^{-i s theta}),
@@ -379,6 +430,7 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
         kt[((size_t)ik * 3 + a) * N + q] = mk(K.real(), K.imag());
         kf[((size_t)ik * 3 + a) * N + q] = mk((float)K.real(), (float)K.imag());
         const double v = std::norm(K);
+        hi[a] = std::max(hi[a], v);
         if (v < lo0[a]) {
           lo1[a] = lo0[a];
           lo0[a] = v;
@@ -387,11 +439,45 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
         }
       }
     }
-    // smallest positive s(p) = sum_a |K_a(q_a)|^2: all axes at their minimum unless that sum
-    // vanishes (k = 0: the DC frequency), then one axis at its second smallest value
-    const double s0 = lo0[0] + lo0[1] + lo0[2];
-    double s2 = INFINITY;  // the next value: one axis at its second smallest
+    // smallest s(p) = sum_a |K_a(p)|^2 (s0) and the next value over the other frequencies (s2):
+    // on the cubic lattice s is a sum of per-axis terms (all axes at their minimum; then one axis
+    // at its second smallest), otherwise every frequency is visited
+    double s0 = lo0[0] + lo0[1] + lo0[2];
+    double s2 = INFINITY;
     for (int a = 0; a < 3; ++a) s2 = std::min(s2, s0 - lo0[a] + lo1[a]);
+    double smx = hi[0] + hi[1] + hi[2];
+    if (op->skew.l1d != nullptr) {
+      const double* C = op->skew.c;
+      std::vector<std::complex<double>> l1(N);
+      for (int q = 0; q < N; ++q) {
+        const double th = 2.0 * M_PI * (double)q / (double)N;
+        std::complex<double> l(0.0, 0.0);
+        for (int t = 1; t <= op->stencil_m; ++t)
+          l += c1[t - 1] * (std::polar(1.0, (t - 1) * th) - std::polar(1.0, -t * th));
+        l1[q] = l / h;
+      }
+      s0 = s2 = INFINITY;
+      for (int qz = 0; qz < N; ++qz)
+        for (int qy = 0; qy < N; ++qy)
+          for (int qx = 0; qx < N; ++qx) {
+            const int qq[3] = {qx, qy, qz};
+            double sp = 0.0;
+            for (int i = 0; i < 3; ++i) {
+              const c64 t = kt[((size_t)ik * 3 + i) * N + qq[i]];
+              std::complex<double> Ki(t.re, t.im);
+              for (int j = 0; j < 3; ++j) Ki += C[i * 3 + j] * l1[qq[j]];
+              sp += std::norm(Ki);
+            }
+            if (qx == 0 && qy == 0 && qz == 0) smx = 0.0;
+            smx = std::max(smx, sp);
+            if (sp < s0) {
+              s2 = s0;
+              s0 = sp;
+            } else if (sp < s2) {
+              s2 = sp;
+            }
+          }
+    }
     smin[ik] = (s0 > 1e-300) ? s0 : s2;
     // Near Gamma (0 < |k| < 0.1) the rule of eq (2.26) gives gamma > 3948, growing as |k|^-2,
     // and the penalty block then dominates the Rayleigh-Ritz pencil in FP64.  There the solver
@@ -399,6 +485,7 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
     // eigenvector with eigenvalue gamma |k|^2, Prop 2.3) and gamma = 4 pi^2 / s2 keeps every
     // remaining penalty eigenvalue at or above 4 pi^2, the level the rule aims at.  Not applied
     // to a gamma the caller gives.
+    smax[ik] = smx;
     const double kn2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
     if (!gamma_host && kn2 > 0.0 && kn2 < 0.01) {
       dcl[ik] = 1;
@@ -423,6 +510,7 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
   op->kvec.assign(k_host, k_host + 3 * (size_t)nk);
   op->gamma = gam;
   op->smin = smin;
+  op->smax = smax;
   op->kflags = kfl;
   op->dcl = dcl;
   op->nk = nk;
@@ -583,6 +671,18 @@ int kc_tile_widths(const kc_op* op, int prec, int* widths_host) {
 int kc_last_solve_stats(const kc_op* op, double* stats_host) {
   KC_ARG(op != nullptr && stats_host != nullptr, "NULL argument");
   for (int i = 0; i < 8; ++i) stats_host[i] = op->stats[i];
+  return KC_OK;
+}
+
+int kc_release_workspaces(kc_op* op) {
+  KC_ARG(op != nullptr, "op is NULL");
+  KC_HIP(hipDeviceSynchronize());
+  solver_release(op);
+  op->work_a.release();
+  op->work_b.release();
+  op->work_c.release();
+  op->work_k.release();
+  op->efield_k.release();
   return KC_OK;
 }
 

@@ -124,6 +124,40 @@ const char* get_error();
     }                                                                                  \
   } while (0)
 
+// Lattice transform of the difference symbols (Section 2.2, eq (2.12)): for primitive vectors
+// other than the unit ones, K_i(p) = sum_j b_ji Lambda_1(q_j) + i k_i Lambda_0(q_i) with
+// b = A^{-1}.  The per-axis tables hold K_i(q_i) = Lambda_1(q_i) + i k_i Lambda_0(q_i), so
+// K_i(p) = K_i(q_i) + sum_j C_ij Lambda_1(q_j) with C_ij = b_ji - delta_ij.  l1d == nullptr
+// means the simple-cubic lattice (C = 0).
+struct Skew {
+  const c32* l1f = nullptr;  // Lambda_1(q), q < N (complex64)
+  const c64* l1d = nullptr;  // the same in complex128
+  double c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+template <typename T>
+__device__ __forceinline__ const cpx<T>* skew_l1(const Skew& s);
+template <>
+__device__ __forceinline__ const c32* skew_l1<float>(const Skew& s) {
+  return s.l1f;
+}
+template <>
+__device__ __forceinline__ const c64* skew_l1<double>(const Skew& s) {
+  return s.l1d;
+}
+
+// K_1, K_2, K_3 of frequency (qx, qy, qz) from the per-axis values (no-op on the cubic lattice)
+template <typename T>
+__device__ __forceinline__ void skew_fix(const Skew& s, int qx, int qy, int qz, cpx<T>& K1, cpx<T>& K2,
+                                         cpx<T>& K3) {
+  if (s.l1d == nullptr) return;
+  const cpx<T>* l = skew_l1<T>(s);
+  const cpx<T> a = l[qx], b = l[qy], c = l[qz];
+  K1 = K1 + static_cast<T>(s.c[0]) * a + static_cast<T>(s.c[1]) * b + static_cast<T>(s.c[2]) * c;
+  K2 = K2 + static_cast<T>(s.c[3]) * a + static_cast<T>(s.c[4]) * b + static_cast<T>(s.c[5]) * c;
+  K3 = K3 + static_cast<T>(s.c[6]) * a + static_cast<T>(s.c[7]) * b + static_cast<T>(s.c[8]) * c;
+}
+
 // Workgroup ids are dealt to the 8 XCDs of an MI355X round-robin (id % 8).  Remapping makes
 // consecutive logical tiles land on the same XCD (and hence share its L2) while the grid is
 // still spread evenly over the chip.  Requires nblocks to be a multiple of 8 to be a

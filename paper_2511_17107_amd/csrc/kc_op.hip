@@ -67,7 +67,7 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
                                                     const cpx<T>* __restrict__ ktab, VecMap vm,
                                                     const cpx<T>* __restrict__ gtw, cpx<T>* __restrict__ kx,
                                                     const c64* __restrict__ ktab64, c64* __restrict__ kx64,
-                                                    const double* __restrict__ sfl) {
+                                                    const double* __restrict__ sfl, Skew sk) {
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -82,19 +82,22 @@ __global__ __launch_bounds__(NT) void k_x1_curl_inv(const c64* __restrict__ x, c
   const cpx<T>* K = ktab + (size_t)(vec / vm.vpk) * 3 * N;
   load_twiddles<N>(tw, gtw);
   const c64* xv = x + vm.off(vec) * 3 * N3;
-  const cpx<T> v3 = conj(K[2 * N + z]);
   for (int w = threadIdx.x; w < N * P; w += NT) {
     const int e = w % N, p = w / N, y = yt * P + p;
     const size_t off = (size_t)z * N * N + (size_t)y * N + e;
     const cpx<T> x1 = cvt<T>(xv[off]), x2 = cvt<T>(xv[N3 + off]), x3 = cvt<T>(xv[2 * N3 + off]);
-    const cpx<T> v1 = conj(K[e]), v2 = conj(K[N + y]);
+    cpx<T> K1 = K[e], K2 = K[N + y], K3 = K[2 * N + z];
+    skew_fix<T>(sk, e, y, z, K1, K2, K3);
+    const cpx<T> v1 = conj(K1), v2 = conj(K2), v3 = conj(K3);
     cpx<T> c1 = v3 * x2 - v2 * x3, c2 = v1 * x3 - v3 * x1, c3 = v2 * x1 - v1 * x2;
     // the penalty term of the last pass needs only K . x: kept here (FP64 for the operator,
     // the compute precision for the preconditioner), so that pass does not re-read x
     if constexpr (PRE && XT) kx[(size_t)vec * N3 + off] = cmulc(v1, x1) + cmulc(v2, x2) + cmulc(v3, x3);
     if constexpr (!PRE) {
       const c64* Kd = ktab64 + (size_t)(vec / vm.vpk) * 3 * N;
-      kx64[(size_t)vec * N3 + off] = Kd[e] * xv[off] + Kd[N + y] * xv[N3 + off] + Kd[2 * N + z] * xv[2 * N3 + off];
+      c64 K1d = Kd[e], K2d = Kd[N + y], K3d = Kd[2 * N + z];
+      skew_fix<double>(sk, e, y, z, K1d, K2d, K3d);
+      kx64[(size_t)vec * N3 + off] = K1d * xv[off] + K2d * xv[N3 + off] + K3d * xv[2 * N3 + off];
     }
     if (PRE) {  // K_A^{+} = K_A^H / s (s floored at sfl near k = 0)
       const T sq = abs2(v1) + abs2(v2) + abs2(v3);
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
                                                         const double* __restrict__ gamma,
                                                         VecMap vm, VecMap vmy, const cpx<T>* __restrict__ gtw,
                                                         const cpx<T>* __restrict__ kxin, const c64* __restrict__ kx64,
-                                                        const double* __restrict__ sfl) {
+                                                        const double* __restrict__ sfl, Skew sk) {
   using G = TileGeom<N, P, 3>;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
@@ -168,17 +171,17 @@ __global__ __launch_bounds__(NT) void k_x2_fwd_curl_pen(const cpx<T>* __restrict
   fft_tile<N, P, 3, NT, -1, T>(lds, tw);
   const c64* xv = x + vm.off(vec) * 3 * N3;
   c64* yv = y + vmy.off(vec) * 3 * N3;
-  const cpx<T> K3 = K[2 * N + z];
-  const c64 K3d = Kd[2 * N + z];
   for (int w = threadIdx.x; w < N * P; w += NT) {
     const int e = w % N, p = w / N, yy = yt * P + p;
     const size_t off = (size_t)z * N * N + (size_t)yy * N + e;
     const cpx<T> e1 = lds[G::addr3(0, e, p)], e2 = lds[G::addr3(1, e, p)], e3 = lds[G::addr3(2, e, p)];
-    const cpx<T> K1 = K[e], K2 = K[N + yy];
+    cpx<T> K1 = K[e], K2 = K[N + yy], K3 = K[2 * N + z];
+    skew_fix<T>(sk, e, yy, z, K1, K2, K3);
     const c64 c1 = cvt<double>(K2 * e3 - K3 * e2);
     const c64 c2 = cvt<double>(K3 * e1 - K1 * e3);
     const c64 c3 = cvt<double>(K1 * e2 - K2 * e1);
-    const c64 K1d = Kd[e], K2d = Kd[N + yy];
+    c64 K1d = Kd[e], K2d = Kd[N + yy], K3d = Kd[2 * N + z];
+    skew_fix<double>(sk, e, yy, z, K1d, K2d, K3d);
     c64 kx;  // K . x
     if constexpr (PRE && XT) {
       kx = cvt<double>(kxin[(size_t)vec * N3 + off]);
@@ -587,7 +590,7 @@ __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E
 // K_P = s I + (gamma - 1) v v^H (eq (2.31) with K_A K_A^H + K_B = s I, Lemma 2.4 (1)),
 // Sherman-Morrison gives K_P^{-1} r = (r - v (v^H r)/s)/s + v (v^H r)/(gamma s^2).
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_precond(const c64* r, c64* z, const c64* __restrict__ ktab64,
+__global__ __launch_bounds__(NT) void k_precond(const c64* r, c64* z, const c64* __restrict__ ktab64, Skew sk,
                                                 const double* __restrict__ gamma, int N, int nvec,
                                                 int vecs_per_k) {
   const size_t N3 = (size_t)N * N * N;
@@ -597,7 +600,8 @@ __global__ __launch_bounds__(NT) void k_precond(const c64* r, c64* z, const c64*
     const int ik = (int)(vec / vecs_per_k);
     const c64* K = ktab64 + (size_t)ik * 3 * N;
     const int qx = (int)(p % N), qy = (int)((p / N) % N), qz = (int)(p / ((size_t)N * N));
-    const c64 K1 = K[qx], K2 = K[N + qy], K3 = K[2 * N + qz];
+    c64 K1 = K[qx], K2 = K[N + qy], K3 = K[2 * N + qz];
+    skew_fix<double>(sk, qx, qy, qz, K1, K2, K3);
     const c64* rv = r + vec * 3 * N3;
     c64* zv = z + vec * 3 * N3;
     const c64 r1 = rv[p], r2 = rv[N3 + p], r3 = rv[2 * N3 + p];
@@ -682,7 +686,7 @@ static void launch_x1(kc_op* op, int pass, int nvec, const c64* x, cpx<T>* A, co
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
     k_x1_curl_inv<N, T, PRE, P, XT>
-        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw, kx, ktab64, kx64, sfl);
+        <<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(x, A, ktab, vm, tw, kx, ktab64, kx64, sfl, op->skew);
   });
 }
 
@@ -694,7 +698,7 @@ static void launch_x2(kc_op* op, int pass, int nvec, const cpx<T>* A, const c64*
   with_tile<N, 3, T>(tile_of<T>(op, pass), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
     k_x2_fwd_curl_pen<N, T, PRE, P, XT><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(
-        A, x, y, ktab, ktab64, gam, vm, vmy, tw, kx, kx64, sfl);
+        A, x, y, ktab, ktab64, gam, vm, vmy, tw, kx, kx64, sfl, op->skew);
   });
 }
 
@@ -1077,7 +1081,7 @@ int apply_precond(kc_op* op, int ik0, int nvec, int vecs_per_k, const c64* r, c6
   if (nvec == 0) return KC_OK;
   const size_t tot = (size_t)op->N * op->N * op->N * nvec;
   const unsigned grid = (unsigned)std::min<size_t>((tot + NT - 1) / NT, 65536);
-  k_precond<<<grid, NT, 0, s>>>(r, z, op->ktab64.as<c64>() + (size_t)ik0 * 3 * op->N,
+  k_precond<<<grid, NT, 0, s>>>(r, z, op->ktab64.as<c64>() + (size_t)ik0 * 3 * op->N, op->skew,
                                 op->gamma_d.as<double>() + ik0, op->N, nvec, vecs_per_k);
   KC_LAUNCHED();
   return KC_OK;

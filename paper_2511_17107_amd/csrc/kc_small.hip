@@ -223,7 +223,8 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
                                                   const int* __restrict__ pmask, double* __restrict__ theta,
                                                   c64* __restrict__ Cu, int* __restrict__ pvalid,
                                                   c64* __restrict__ Lsave, int* __restrict__ flags,
-                                                  const int* __restrict__ kskip, c64* __restrict__ gapp_out) {
+                                                  const int* __restrict__ kskip, c64* __restrict__ gapp_out,
+                                                  const double* __restrict__ res) {
   const int b = blockIdx.x;
   if (kskip && kskip[b]) return;
   extern __shared__ c64 sm[];
@@ -339,6 +340,52 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
     ord[r] = i;
   }
   __syncthreads();
+  // Plausibility of the new Ritz values.  The search space contains the current X (orthonormal,
+  // Ritz values theta_old, residuals R = AX - X Theta), so in exact arithmetic the j-th new Ritz
+  // value lies in [lambda_j, theta_old_j] and lambda_j >= theta_old_j - |R|_2 (the eigenvalues
+  // of A are within |R|_2 of those of Theta), |R|_2 <= (sum_j |r_j|^2)^(1/2), when X holds the
+  // lowest eigenvectors' neighbourhood; the operator is
+  // positive semi-definite as well.  A value below both bounds can only come from a pencil that
+  // lost its rank in rounding (seen when the residuals sit at the rounding floor of the FP64
+  // application): with a complete X block the step is then rejected -- X and its image stay, P
+  // is dropped, and the host restarts the iteration from X (flag 2).
+  __shared__ int reject;
+  if (threadIdx.x == 0) {
+    bool xfull = true;
+    for (int i = 0; i < mb; ++i) xfull = xfull && act[i];
+    reject = 0;
+    if (xfull) {
+      double r2 = 0.0;
+      for (int j = 0; j < mb; ++j) r2 += res ? res[b * mb + j] * res[b * mb + j] : 0.0;
+      const double rn = sqrt(r2);
+      double tmax = 0.0;
+      for (int j = 0; j < mb; ++j) tmax = fmax(tmax, fabs(theta[b * mb + j]));
+      // the residual bound is applied only once the block is nearly converged (|R| below 1e-4 of
+      // the Ritz values): earlier, a lower eigenvalue that X has not met yet may still enter
+      const bool late = res && std::isfinite(rn) && rn < 1e-4 * tmax;
+      for (int j = 0; j < mb; ++j) {
+        const double t_old = theta[b * mb + j], t_new = ev[ord[j]];
+        if (t_new < -1e-8 * fro || (late && t_new < t_old - 2.0 * rn - 1e-10 * fabs(t_old))) reject = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (reject) {
+    for (int j = threadIdx.x; j < mb; j += blockDim.x) {
+      const double gbj = gb[(size_t)j * n + j].re;
+      theta[b * mb + j] = gbj > 0.0 ? ga[(size_t)j * n + j].re / gbj : 0.0;
+      pvalid[b * mb + j] = 0;
+    }
+    c64* out = Cu + (size_t)b * n * 2 * mb;
+    for (int e = threadIdx.x; e < n * 2 * mb; e += blockDim.x) {
+      const int i = e / (2 * mb), j = e % (2 * mb);
+      out[e] = (j < mb && i == j) ? mk(1.0, 0.0) : mk(0.0, 0.0);
+    }
+    if (gapp_out)
+      for (int e = threadIdx.x; e < mb * mb; e += blockDim.x) gapp_out[(size_t)b * mb * mb + e] = mk(0.0, 0.0);
+    if (threadIdx.x == 0) atomicOr(&flags[b], 2);
+    return;
+  }
   for (int j = threadIdx.x; j < mb; j += blockDim.x) theta[b * mb + j] = ev[ord[j]];
   // C1 = L^{-H} V[:, ord[0..mb)]
   for (int e = threadIdx.x; e < n * mb; e += blockDim.x) {
@@ -480,7 +527,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
 
 int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,
              double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, c64* gapp_out,
-             hipStream_t s) {
+             hipStream_t s, const double* res) {
   if (3 * mb > RR_NMAX || mb > 21) {
     set_error("block size too large");
     return KC_ERR_INVALID_ARG;
@@ -492,7 +539,7 @@ int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, con
     attr = true;
   }
   k_small_rr<<<nb, RR_THREADS, shm, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave, flags, kskip,
-                                  gapp_out);
+                                  gapp_out, res);
   KC_LAUNCHED();
   return KC_OK;
 }

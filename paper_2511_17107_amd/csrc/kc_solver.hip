@@ -92,7 +92,7 @@ int rayleigh_ritz(Batch& B, bool implicit = false, bool fused = false) {
   }
   KC_TRY(small_rr(B.w->GA.as<c64>(), B.w->GB.as<c64>(), B.mb, B.nb, B.xmask, B.wmask, B.pmask,
                   B.w->theta.as<double>(), B.w->Cu.as<c64>(), B.pvalid, B.w->Lsave.as<c64>(), B.flags, B.kskip,
-                  B.w->GApp.as<c64>(), B.s));
+                  B.w->GApp.as<c64>(), B.s, B.w->res.as<double>()));
   // [X | P] <- S Cu, [AX | AP] <- AS Cu
   if (fused)
     return update_res(B.S, B.AS, B.nc, B.mb, B.w->Cu.as<c64>(), B.n, B.nb, B.w->theta.as<double>(),
@@ -119,7 +119,7 @@ int residuals(Batch& B, bool copy_r) {
   KC_TRY(resid_precond(B.S, B.AS, B.S, B.w->theta.as<double>(), B.op->ktab64.as<c64>() + (size_t)B.ik0 * 3 * B.N,
                        B.op->gamma_d.as<double>() + B.ik0, B.N, B.nc, 0, B.mb, B.mb, B.nb, B.w->part_res,
                        B.w->res.as<double>(), B.w->xn2.as<double>(), B.kskip, B.s, R, nullptr,
-                       copy_r ? B.wskip : nullptr, B.op->sfloor_d.as<double>() + B.ik0));
+                       copy_r ? B.wskip : nullptr, B.op->sfloor_d.as<double>() + B.ik0, &B.op->skew));
   return deflate_w(B);
 }
 
@@ -217,6 +217,9 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   std::vector<char> done(nb, 0);
   std::vector<int> its(nb, 0), brk_count(nb, 0);
   std::vector<char> drop_p(nb, 0);
+  std::vector<double> sbest(nb, 1e300);
+  std::vector<int> sstall(nb, 0);
+  std::vector<char> stalled(nb, 0);
 
   KC_HIP(hipMemsetAsync(B.S, 0, (size_t)nb * nc * colbytes, s));
   KC_HIP(hipMemsetAsync(B.AS, 0, (size_t)nb * nc * colbytes, s));
@@ -325,6 +328,11 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       if (done[b]) continue;
       for (int j = 0; j < mb; ++j)
         if (!std::isfinite(hres[b * mb + j])) hflags[b] |= 1;
+      if (hflags[b] & 2) {  // a rejected Rayleigh-Ritz step (negative Ritz value): restart from X
+        reset_flags = true;
+        drop_p[b] = 1;
+        full_gram = true;
+      }
       if (hflags[b] & 1) {
         reset_flags = true;
         drop_p[b] = 1;
@@ -452,6 +460,28 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
         continue;
       }
     }
+    // stagnation (FP64 phase): a k-point whose largest band residual has not halved in 200
+    // iterations (e.g. a tolerance below the rounding floor of the operator's FP64 application)
+    // stops there and is reported as not converged
+    if (prec == KC_PREC_FP64) {
+      bool any_live = false;
+      for (int b = 0; b < nb; ++b) {
+        if (done[b]) continue;
+        double mx = 0.0;
+        for (int j = 0; j < m; ++j) mx = std::max(mx, hres[b * mb + j]);
+        if (mx < 0.5 * sbest[b]) {
+          sbest[b] = mx;
+          sstall[b] = 0;
+        } else if (++sstall[b] >= 200) {
+          done[b] = 1;
+          stalled[b] = 1;
+          its[b] = it;
+          if (o.verbose) fprintf(stderr, "[kc_solve] k %d: stagnated at %.3e\n", ik0 + b, sbest[b]);
+        }
+        any_live = any_live || !done[b];
+      }
+      if (!any_live) break;
+    }
     // masks for this iteration; after a breakdown the k-point restarts without P
     int nact = 0;
     for (int b = 0; b < nb; ++b)
@@ -511,7 +541,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       res_out[(size_t)b * m + j] = hres[b * mb + j];
     }
     if (iters) iters[b] = done[b] ? its[b] : it;
-    allc = allc && done[b];
+    allc = allc && done[b] && !stalled[b];
     if (Xout) {
       for (int j = 0; j < m; ++j)
         KC_HIP(hipMemcpyAsync(Xout + ((size_t)b * m + j) * n, B.S + ((size_t)b * nc + j) * n, colbytes,

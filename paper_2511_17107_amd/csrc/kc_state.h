@@ -66,9 +66,12 @@ struct kc_op {
   int scheme = 0;
   int n_mat = 0;
   int stencil_m = 1;             // order 2m of the curl/divergence stencils (eq (2.34))
+  kc::Skew skew;                 // lattice transform of the symbols (eq (2.12)); cubic: l1d == nullptr
+  kc::DevBuf lam1;               // Lambda_1(q): c64 [N] then c32 [N] (non-cubic lattices)
   kc::Allocator alloc;           // source of every device buffer of the handle
   int flags = 0;                 // KC_FLAG_* found by kc_create
   std::vector<double> smin;      // [nk] smallest positive s(p) = |K(p)|^2 (spurious-mode bound)
+  std::vector<double> smax;      // [nk] largest s(p) (scale of the operator's rounding)
   std::vector<int> kflags;       // [nk] KC_KFLAG_* of each k-point
   std::vector<double> eps_host;  // [n_mat][3][3][2]
   kc::DevBuf ids;                // uint32 [N^3]: x-edge | y-edge << 8 | z-edge << 16 | vol << 24
@@ -98,7 +101,7 @@ struct kc_op {
   bool tuned[2] = {false, false};
   // every device buffer of the handle takes its memory from `alloc`
   void bind_allocator() {
-    kc::DevBuf* bufs[] = {&ids, &eps64, &eps32, &tw64, &tw32, &ktab64, &ktab32, &gamma_d, &sfloor_d, &dcl_d, &work_a, &work_b,
+    kc::DevBuf* bufs[] = {&ids, &eps64, &eps32, &tw64, &tw32, &ktab64, &ktab32, &gamma_d, &sfloor_d, &dcl_d, &lam1, &work_a, &work_b,
                           &work_c, &work_k, &epsfeat, &efield, &efield_t, &efield_k, &kdev};
     for (kc::DevBuf* b : bufs) b->al = &alloc;
   }

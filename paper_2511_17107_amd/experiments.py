@@ -39,7 +39,7 @@ def _solve(op, m, **kw):
     return eig, res, its, st, time.perf_counter() - t
 
 
-def highorder(sizes, orders, bands=8, tol=1e-9):
+def highorder(sizes, orders, bands=8, tol=1e-8):
     import workloads as W
 
     out = {"experiment": "highorder", "k": "(pi, pi, pi)", "permittivity": "8.9 sin(2 pi (x+y+z)) + 13",
@@ -66,11 +66,12 @@ def highorder(sizes, orders, bands=8, tol=1e-9):
     return out
 
 
-def robust(N, bands=10, seed=0, maxit=600):
+def robust(N, bands=10, seed=0, maxit=600, tol=1e-8):
     import workloads as W
 
     wl = W.sphere_illconditioned(N, seed=seed, m=bands)
-    out = {"experiment": "robust", "N": N, "bands": bands, "k": [float(v) for v in wl.kpoints[0]],
+    out = {"experiment": "robust", "N": N, "bands": bands, "tol": tol, "maxit": maxit,
+           "k": [float(v) for v in wl.kpoints[0]],
            "inverse_permittivity_eigenvalues": [1e-1, 1e-3, 1e-5], "inclusion": "sphere r=0.25 at the cell centre",
            "runs": []}
     eigs = {}
@@ -79,7 +80,7 @@ def robust(N, bands=10, seed=0, maxit=600):
         op.set_kpoints(wl.kpoints)
         for prec, pc in ((kc.KC_PREC_FP64, kc.KC_PRECOND_TRANSVERSE), (kc.KC_PREC_FP32, kc.KC_PRECOND_TRANSVERSE),
                          (kc.KC_PREC_FP64, kc.KC_PRECOND_DIAG)):
-            eig, res, its, st, dt = _solve(op, bands, tol=1e-8, guard=4, prec=prec, switch_tol=3e-4, precond=pc,
+            eig, res, its, st, dt = _solve(op, bands, tol=tol, guard=4, prec=prec, switch_tol=3e-4, precond=pc,
                                            maxit=maxit)
             h, hp = op.residual_history(0)
             step = max(1, len(h) // 40)
@@ -139,6 +140,8 @@ def main(argv=None):
     b = sub.add_parser("robust")
     b.add_argument("--N", type=int, default=128)
     b.add_argument("--bands", type=int, default=10)
+    b.add_argument("--tol", type=float, default=1e-8)
+    b.add_argument("--maxit", type=int, default=600)
     c = sub.add_parser("schemes")
     c.add_argument("--geometry", choices=["sphere64", "woodpile128"], default="sphere64")
     c.add_argument("--nk", type=int, default=40)
@@ -150,7 +153,7 @@ def main(argv=None):
     if args.cmd == "highorder":
         out = highorder(args.sizes, args.orders)
     elif args.cmd == "robust":
-        out = robust(args.N, args.bands)
+        out = robust(args.N, args.bands, maxit=args.maxit, tol=args.tol)
     else:
         out = schemes(args.geometry, args.nk, args.batch)
     print(json.dumps(out), flush=True)

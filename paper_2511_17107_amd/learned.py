@@ -98,6 +98,7 @@ def make_samples(N, seeds, m=8, nk_path=40, amp=(0.02, 0.3), rng_seed=0, log=pri
         op.set_kpoints(wl.kpoints[kidx:kidx + 1])
         X = torch.zeros((m, 3, n3), dtype=torch.complex128, device=dev)
         eig, res, its, st = op.solve(m, tol=1e-7, guard=2, X_out=X, seed=int(s), precond=kc.KC_PRECOND_TRANSVERSE)
+        op.release_workspaces()  # the training passes need only the operator's own buffers
         # perturbation: smoothed noise orthogonal to the converged block
         noise = torch.from_numpy(W.random_block(10_000 + int(s), m, N)).to(dev)
         e = op.precond(noise, vecs_per_k=m)
@@ -112,6 +113,7 @@ def make_samples(N, seeds, m=8, nk_path=40, amp=(0.02, 0.3), rng_seed=0, log=pri
         r = (Ax - theta[:, None, None] * x).contiguous()
         c = pcg(op, 0, r)
         feat = op.net_features(0, 1)
+        op.release_workspaces()
         out.append(Sample(op, feat, r, c, {"seed": int(s), "k": kidx, "eig0": float(eig[0][0]), "iters": int(its[0])}))
         log("samples: geometry %d k=%d eig[0]=%.4f iters=%d" % (s, kidx, eig[0][0], its[0]))
     return out
@@ -158,13 +160,19 @@ def sample_loss(net, smp, grad=False, loss_kind="energy"):
 
 
 def train(net, samples, steps=400, batch=4, lr=1e-3, log=print, seed=0, loss_kind="energy"):
+    """Adam on the mean sample loss; each step draws its batch from one grid size (the samples'
+    network inputs are concatenated), cycling through the sizes present."""
     torch = _torch()
-    S = len(samples)
-    N = samples[0].op.N
+    groups = {}
+    for i, smp in enumerate(samples):
+        groups.setdefault(smp.op.N, []).append(i)
+    sizes = sorted(groups)
     g = np.random.default_rng(seed)
     hist = []
     for it in range(steps):
-        idx = g.choice(S, size=min(batch, S), replace=False)
+        N = sizes[it % len(sizes)]
+        pool = groups[N]
+        idx = [pool[i] for i in g.choice(len(pool), size=min(batch, len(pool)), replace=False)]
         feats, gys, ls = [], [], []
         for i in idx:
             smp = samples[i]
@@ -226,6 +234,82 @@ def evaluate(weights, N=96, nk=8, m=16, guard=4, seed=1000, log=print, batch_k=N
         out[name]["max_rel_eig_diff"] = float(np.max(np.abs(e1 - e0) / e0))
         out[name]["iteration_ratio"] = float(np.sum(out[name]["iterations"]) / np.sum(out["diagonal"]["iterations"]))
         out[name]["time_ratio"] = out[name]["seconds"] / out["diagonal"]["seconds"]
+    return out
+
+
+def c5(geoms32=400, geoms64=100, steps=600, nk=40, N=96, m=16, guard=4, batch_k=10, log=print):
+    """The learned-preconditioner workload: train on solver-generated pairs of geoms32 random
+    geometries at 32^3 and geoms64 at 64^3 (seeds 0.. of workloads.random_inclusions), then solve a
+    held-out geometry (seed 1000) at N^3 over nk k-points of its path to Res <= 1e-8 with
+      fp64_diagonal : FP64 operator, the diagonal-block preconditioner of eqs (2.31)-(2.32)
+      fp32_diagonal : FP32 operator phase + FP64 finish, the same preconditioner
+      fp32_transverse: FP32 phase, T_E with the classical field
+      fp32_learned  : FP32 phase, T_E with the trained network's field
+    all batched batch_k k-points per launch set; returns timings, iterations and eigenvalue
+    differences against the FP64 run."""
+    torch = _torch()
+    import paper_2511_17107_amd as kc
+    import workloads as W
+
+    t0 = time.time()
+    net = kc.Net(seed=0)
+    cnt = [0]
+
+    def every(msg):  # progress every 25 geometries
+        cnt[0] += 1
+        if cnt[0] % 25 == 0:
+            log("c5 samples %d (%.0f s): %s" % (cnt[0], time.time() - t0, msg))
+
+    samples = make_samples(32, range(geoms32), log=every)
+    if geoms64:
+        samples += make_samples(64, range(geoms64), rng_seed=7, log=every)
+    held = make_samples(32, range(5000, 5008), rng_seed=1, log=every)
+    t_samples = time.time() - t0
+    l0 = mean_loss(net, held)
+    hist = train(net, samples, steps=steps, log=log)
+    l1 = mean_loss(net, held)
+    t_train = time.time() - t0 - t_samples
+    log("c5: %d samples in %.0f s, training %.0f s, held-out loss %.4f -> %.4f" % (len(samples), t_samples, t_train, l0, l1))
+    for smp in samples + held:  # release the training handles before the large solves
+        smp.op.close()
+    del samples, held
+    torch.cuda.empty_cache()
+    wl = W.random_inclusions(N, 1000, nk=nk, m=m)
+    op = kc.Op(N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(wl.kpoints)
+    op.attach_net(net)
+    out = {"workload": "random inclusions (held-out seed 1000) at %d^3, %d bands (+%d guard), %d k-points of the "
+                       "G-X-M-G-R path, %d per launch set" % (N, m, guard, nk, batch_k),
+           "training": {"geometries_32": geoms32, "geometries_64": geoms64, "steps": steps,
+                        "seconds_samples": t_samples, "seconds_training": t_train,
+                        "heldout_loss_E0": l0, "heldout_loss_trained": l1}, "runs": {}}
+    cfgs = [("fp64_diagonal", kc.KC_PREC_FP64, kc.KC_PRECOND_DIAG), ("fp32_diagonal", kc.KC_PREC_FP32, kc.KC_PRECOND_DIAG),
+            ("fp32_transverse", kc.KC_PREC_FP32, kc.KC_PRECOND_TRANSVERSE),
+            ("fp32_learned", kc.KC_PREC_FP32, kc.KC_PRECOND_LEARNED)]
+    eig = {}
+    for name, prec, pc in cfgs:
+        op.solve(m, nk=2, batch_k=2, tol=1e-8, guard=guard, precond=pc, prec=prec, switch_tol=3e-4)  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        E, I, S = [], [], []
+        kept = 0.0
+        for ik0 in range(0, nk, batch_k):
+            nb = min(batch_k, nk - ik0)
+            e, r, its, st = op.solve(m, ik0=ik0, nk=nb, batch_k=nb, tol=1e-8, guard=guard, precond=pc, prec=prec,
+                                     switch_tol=3e-4, check=False)
+            E.append(e), I.append(its), S.append(st)
+            kept += op.last_solve_stats()[4]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        its = np.concatenate(I)
+        eig[name] = np.concatenate(E)
+        out["runs"][name] = {"seconds": dt, "kpoints_per_s": nk / dt, "iterations_mean": float(its.mean()),
+                             "status": [int(v) for v in S], "learned_kept": kept if pc == kc.KC_PRECOND_LEARNED else None}
+        log("c5 %s: %.2f s, %.1f iterations per k-point" % (name, dt, its.mean()))
+    for name in out["runs"]:
+        out["runs"][name]["max_rel_eig_diff_vs_fp64"] = float(np.max(np.abs(eig[name] - eig["fp64_diagonal"]) /
+                                                                    eig["fp64_diagonal"]))
+        out["runs"][name]["speedup_vs_fp64_diagonal"] = out["runs"]["fp64_diagonal"]["seconds"] / out["runs"][name]["seconds"]
     return out
 
 

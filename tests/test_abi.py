@@ -138,15 +138,16 @@ def test_header_declares_boundary_extensions():
 
 
 def test_create_checks_lattice_stencil_and_allocator_before_device_work():
-    """Non-cubic lattices are KC_ERR_UNSUPPORTED; stencil orders outside 2..10 and a lone
-    allocator callback are KC_ERR_INVALID_ARG; all found before any device call."""
+    """Dependent or non-finite lattice vectors, stencil orders outside 2..10 and a lone allocator
+    callback are KC_ERR_INVALID_ARG, all found before any device call."""
     N = 4
     ids = np.zeros((4, N ** 3), dtype=np.uint8)
     tab = W.eps_table([])
-    fcc = 0.5 * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
-    with pytest.raises(kc.KcError) as e:
-        kc.Op(N, kc.KC_EPS_CROSSDOF, ids, tab, lattice=fcc)
-    assert e.value.status == 2
+    flat = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [1.0, 1.0, 0.0]])
+    for lat in (flat, np.full((3, 3), np.nan)):
+        with pytest.raises(kc.KcError) as e:
+            kc.Op(N, kc.KC_EPS_CROSSDOF, ids, tab, lattice=lat)
+        assert e.value.status == 1
     for m in (0, 6):
         with pytest.raises(kc.KcError) as e:
             kc.Op(N, kc.KC_EPS_CROSSDOF, ids, tab, stencil_m=m)

@@ -116,6 +116,54 @@ class Slab:
         return (c >= self.lo) & (c < self.hi)
 
 
+# Primitive lattice vectors as ROWS (lattice constant 1), Section 4, eq (4.1); a cell point with
+# fractional coordinates xi (the unit-cube grid) sits at x = xi_1 a_1 + xi_2 a_2 + xi_3 a_3.
+LATTICES = {
+    "sc": np.eye(3),
+    "fcc": np.array([[0.0, 0.5, 0.5], [0.5, 0.0, 0.5], [0.5, 0.5, 0.0]]),
+    "bcc": np.array([[-0.5, 0.5, 0.5], [0.5, -0.5, 0.5], [0.5, 0.5, -0.5]]),
+    # a triclinic cell whose lattice matrix is not symmetric (catches transposed conventions)
+    "tric": np.array([[1.0, 0.0, 0.0], [0.3, 0.9, 0.0], [0.2, 0.25, 0.8]]),
+}
+
+# Symmetry points of the Brillouin zones, Section 4, eq (4.2) (Cartesian, lattice constant 1)
+BZ_POINTS = {
+    "fcc": {"X": (0.0, 2 * math.pi, 0.0), "U": (math.pi / 2, 2 * math.pi, math.pi), "L": (math.pi,) * 3,
+            "G": (0.0, 0.0, 0.0), "W": (math.pi, 2 * math.pi, 0.0), "K": (1.5 * math.pi, 1.5 * math.pi, 0.0)},
+    "bcc": {"H'": (2 * math.pi, 0.0, 0.0), "G": (0.0, 0.0, 0.0), "P": (math.pi,) * 3, "N": (math.pi, 0.0, math.pi),
+            "H": (0.0, 2 * math.pi, 0.0)},
+}
+
+
+@dataclasses.dataclass
+class LatticeSphere:
+    """Sphere of physical radius `radius` around the point with fractional coordinates `center`
+    of a lattice (vectors as rows); periodic images through the 27 nearest lattice vectors."""
+    lattice: np.ndarray
+    center: Sequence[float]
+    radius: float
+    mat: int
+
+    def contains(self, pts: np.ndarray) -> np.ndarray:
+        L = np.asarray(self.lattice, dtype=np.float64)
+        d = _min_image(pts - np.asarray(self.center, dtype=np.float64))
+        best = np.full(pts.shape[0], np.inf)
+        for n in np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1], indexing="ij")).reshape(3, -1).T:
+            x = (d + n[None, :]) @ L
+            best = np.minimum(best, np.einsum("ij,ij->i", x, x))
+        return best < self.radius ** 2
+
+
+def lattice_sphere(lattice: str, N: int, radius: float = 0.25, eps=13.0, k=(0.3, 0.5, 0.7), m: int = 8,
+                   scheme: str = "crossdof") -> Workload:
+    """A dielectric sphere at the lattice origin in air for the lattice `lattice` (LATTICES);
+    eps a scalar or a 3x3 permittivity tensor."""
+    L = LATTICES[lattice]
+    ids = sample_ids(N, [LatticeSphere(L, (0.0, 0.0, 0.0), radius, 1)])
+    e = eps * np.eye(3) if np.ndim(eps) == 0 else np.asarray(eps)
+    return Workload("%s%d-sphere" % (lattice, N), N, ids, eps_table([e]), np.array([k], dtype=np.float64), m, scheme)
+
+
 def sample_ids(N: int, shapes: Sequence) -> np.ndarray:
     """uint8 material ids, shape (4, N^3), rows in POINT_SETS order."""
     ids = np.zeros((4, N ** 3), dtype=np.uint8)
