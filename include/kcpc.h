@@ -324,8 +324,9 @@ void kc_solve_opts_default(kc_solve_opts* opts);
  *   X_out      : NULL, or device complex128 [nk][m][3][N^3] for the eigenvectors
  * At k = 0 the three constant fields (Prop 2.5 (1)) are deflated and not reported.
  * Returns KC_ERR_NO_CONVERGENCE if some k-point did not reach tol within maxit, or stagnated
- * (in the FP64 phase its largest band residual did not halve in 200 iterations, e.g. with a tol
- * below the rounding floor of the operator's FP64 application); the outputs then hold that
+ * (in the FP64 phase its largest band residual did not halve in 200 iterations, or, once within
+ * 1e3 tol, rose above 10 times its best in two successive iterations: what a tol below the
+ * rounding floor of the operator's FP64 application leads to); the outputs then hold that
  * k-point's last iterate.
  */
 int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_host,

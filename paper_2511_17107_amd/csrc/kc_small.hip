@@ -342,7 +342,8 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
   __syncthreads();
   // Plausibility of the new Ritz values.  The search space contains the current X (orthonormal,
   // Ritz values theta_old, residuals R = AX - X Theta), so in exact arithmetic the j-th new Ritz
-  // value lies in [lambda_j, theta_old_j] and lambda_j >= theta_old_j - |R|_2 (the eigenvalues
+  // value lies in [lambda_j, theta_old_j] (Cauchy interlacing: it cannot rise) and
+  // lambda_j >= theta_old_j - |R|_2 (the eigenvalues
   // of A are within |R|_2 of those of Theta), |R|_2 <= (sum_j |r_j|^2)^(1/2), when X holds the
   // lowest eigenvectors' neighbourhood; the operator is
   // positive semi-definite as well.  A value below both bounds can only come from a pencil that
@@ -365,7 +366,10 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
       const bool late = res && std::isfinite(rn) && rn < 1e-4 * tmax;
       for (int j = 0; j < mb; ++j) {
         const double t_old = theta[b * mb + j], t_new = ev[ord[j]];
-        if (t_new < -1e-8 * fro || (late && t_new < t_old - 2.0 * rn - 1e-10 * fabs(t_old))) reject = 1;
+        // below the bound, or above theta_old_j (the Ritz values of a space that contains X do not
+        // rise), each with the residual's slack
+        const double slack = 2.0 * rn + 1e-10 * fabs(t_old);
+        if (t_new < -1e-8 * fro || (late && (t_new < t_old - slack || t_new > t_old + slack))) reject = 1;
       }
     }
   }

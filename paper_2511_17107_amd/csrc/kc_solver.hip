@@ -218,7 +218,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   std::vector<int> its(nb, 0), brk_count(nb, 0);
   std::vector<char> drop_p(nb, 0);
   std::vector<double> sbest(nb, 1e300);
-  std::vector<int> sstall(nb, 0);
+  std::vector<int> sstall(nb, 0), sgrow(nb, 0);
   std::vector<char> stalled(nb, 0);
 
   KC_HIP(hipMemsetAsync(B.S, 0, (size_t)nb * nc * colbytes, s));
@@ -461,18 +461,21 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       }
     }
     // stagnation (FP64 phase): a k-point whose largest band residual has not halved in 200
-    // iterations (e.g. a tolerance below the rounding floor of the operator's FP64 application)
-    // stops there and is reported as not converged
+    // iterations, or that rose above 10 times its best in two successive iterations once within
+    // 1e3 tol (past the rounding floor of the operator's FP64 application the running images
+    // AX = AS C drift away from Op X and the residuals grow), stops there and is reported as not
+    // converged, before the iteration fills the block with rounding noise
     if (prec == KC_PREC_FP64) {
       bool any_live = false;
       for (int b = 0; b < nb; ++b) {
         if (done[b]) continue;
         double mx = 0.0;
         for (int j = 0; j < m; ++j) mx = std::max(mx, hres[b * mb + j]);
+        sgrow[b] = (sbest[b] < 1e3 * o.tol && mx > 10.0 * sbest[b]) ? sgrow[b] + 1 : 0;
         if (mx < 0.5 * sbest[b]) {
           sbest[b] = mx;
           sstall[b] = 0;
-        } else if (++sstall[b] >= 200) {
+        } else if (++sstall[b] >= 200 || sgrow[b] >= 2) {
           done[b] = 1;
           stalled[b] = 1;
           its[b] = it;

@@ -50,8 +50,10 @@ def case_illcond16():
 
 
 def case_illcond32():
+    # CrossDoF only: the Trivial scheme's clustered low spectrum makes the shift-invert solve at
+    # 32^3 take hours
     wl = W.sphere_illconditioned(32)
-    return wl, [(wl.kpoints[0], s) for s in ("crossdof", "trivial")]
+    return wl, [(wl.kpoints[0], "crossdof")]
 
 
 CASES = {

@@ -109,8 +109,9 @@ def test_trivial_and_crossdof_frequencies_close():
 
 def test_unreachable_tolerance_stops_cleanly():
     """Order-10 stencils at 64^3 put the rounding floor of an FP64 application near 1e-9: asking
-    for 1e-10 ends as KC_ERR_NO_CONVERGENCE after the stagnation window, with the eigenvalues of
-    the converged solve (no Ritz values made of rounding noise)."""
+    for 1e-10 ends as KC_ERR_NO_CONVERGENCE after the stagnation window (200 iterations without
+    progress), with the eigenvalues of the converged solve: the Rayleigh-Ritz steps whose Ritz
+    values fall below the residual bound are rejected, so none is made of rounding noise."""
     N = 64
     wl = W.smooth_isotropic(N)
     op = kc.Op(N, kc.KC_EPS_DIAGONAL, wl.ids, wl.table, stencil_m=5)
@@ -119,5 +120,5 @@ def test_unreachable_tolerance_stops_cleanly():
     e1, r1, i1, s1 = op.solve(8, tol=1e-8, guard=4, precond=kc.KC_PRECOND_TRANSVERSE)
     e2, r2, i2, s2 = op.solve(8, tol=1e-10, guard=4, precond=kc.KC_PRECOND_TRANSVERSE, maxit=500, check=False)
     assert s1 == 0 and s2 == kc.KC_ERR_NO_CONVERGENCE
-    assert i2[0] < 200
-    assert np.max(np.abs(e2 - e1) / e1) < 1e-9
+    assert np.max(np.abs(e2 - e1) / e1) < 1e-9, (e1, e2)
+    assert i2[0] < 100  # stopped by the stagnation rule, not by maxit
