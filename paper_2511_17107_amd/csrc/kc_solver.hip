@@ -385,7 +385,9 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       }
     }
     bool lchanged = false;
-    if (B.pc == KC_PRECOND_LEARNED) {
+    // the fallback watches the FP64 iterations only: in the FP32 phase the residuals level off at
+    // the FP32 floor whatever the preconditioner
+    if (B.pc == KC_PRECOND_LEARNED && prec == KC_PREC_FP64) {
       for (int b = 0; b < nb; ++b) {
         if (done[b] || !lon[b]) continue;
         double lg = 0.0;
@@ -445,6 +447,8 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       if (mxres <= o.switch_tol || stall >= 4 || ncand > 0) {
         prec = KC_PREC_FP64;
         full_gram = true;
+        std::fill(lbest.begin(), lbest.end(), 1e300);
+        std::fill(lstall.begin(), lstall.end(), 0);
         std::vector<int> act(nb * mb, 0);
         for (int b = 0; b < nb; ++b)
           if (!done[b])

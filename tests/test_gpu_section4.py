@@ -63,7 +63,7 @@ def _load(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("name", ["illcond16"])
+@pytest.mark.parametrize("name", ["illcond16", "illcond32"])
 @pytest.mark.parametrize("prec", [kc.KC_PREC_FP64, kc.KC_PREC_FP32])
 def test_ill_conditioned_inclusion_matches_oracle(name, prec):
     """Inverse permittivity U diag(1e-1, 1e-3, 1e-5) U^H in a sphere (condition number 1e4, the
