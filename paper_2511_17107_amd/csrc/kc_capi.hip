@@ -683,6 +683,7 @@ int kc_release_workspaces(kc_op* op) {
   op->work_c.release();
   op->work_k.release();
   op->efield_k.release();
+  op->efield_kt.release();
   return KC_OK;
 }
 
@@ -837,8 +838,7 @@ int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void*
          "r and z must not overlap");
   hipStream_t s = (hipStream_t)stream;
   const int nk = (nvec - 1) / vecs_per_k + 1;
-  KC_TRY(op->efield_k.ensure((size_t)nk * n * sizeof(float)));
-  KC_TRY(nn_efield(op, ik0, nk, op->efield_k.as<float>(), s));
+  KC_TRY(learned_fields(op, ik0, nk, s));
   VecMap vm;
   vm.vpk = vecs_per_k;
   vm.kstride = vecs_per_k;

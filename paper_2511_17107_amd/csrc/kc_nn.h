@@ -28,7 +28,10 @@ int nn_gradients(Net* net, int N, int batch, const uint16_t* in, const float* ta
 int nn_backward(Net* net, int N, int batch, const uint16_t* in, const float* gout, hipStream_t s);
 int nn_adam(Net* net, float lr, float b1, float b2, float eps, hipStream_t s);
 int nn_features(kc_op* op, int ik0, int nk, uint16_t* F, hipStream_t s);
-int nn_efield(kc_op* op, int ik0, int nk, float* E, hipStream_t s);
+// learned fields E (f32 [nk][3][N^3]) and, with Et != nullptr, their x-major copy ([nk][3][x][z][y])
+int nn_efield(kc_op* op, int ik0, int nk, float* E, hipStream_t s, float* Et = nullptr);
+// the learned fields of k-points ik0 .. ik0+nk-1 into op->efield_k and op->efield_kt
+int learned_fields(kc_op* op, int ik0, int nk, hipStream_t s);
 int nn_build_eps_features(kc_op* op);
 
 }  // namespace kc

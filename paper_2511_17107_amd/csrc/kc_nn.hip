@@ -319,14 +319,17 @@ __global__ void k_features(const float* __restrict__ epsf, const float* __restri
 
 // E[b][c][p] = E0[c][p] exp(clamp(y[b][p][c], -3, 3)) from the network output y (f32 [nk][N3][16])
 __global__ void k_efield(const float* __restrict__ y, const float* __restrict__ e0, int N, int nk,
-                         float* __restrict__ E) {
+                         float* __restrict__ E, float* __restrict__ Et) {
   const size_t N3 = (size_t)N * N * N;
   for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < N3 * nk; t += (size_t)gridDim.x * 256) {
     const size_t b = t / N3, p = t - b * N3;
+    const size_t xm = Et ? ((p % N) * N + p / ((size_t)N * N)) * N + (p / N) % N : 0;  // [x][z][y]
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float o = fminf(fmaxf(y[t * 16 + c], -3.f), 3.f);
-      E[(b * 3 + c) * N3 + p] = e0[c * N3 + p] * expf(o);
+      const float e = e0[c * N3 + p] * expf(o);
+      E[(b * 3 + c) * N3 + p] = e;
+      if (Et) Et[(b * 3 + c) * N3 + xm] = e;
     }
   }
 }
@@ -525,7 +528,7 @@ int nn_features(kc_op* op, int ik0, int nk, uint16_t* F, hipStream_t s) {
 }
 
 // learned fields E of k-points ik0..ik0+nk-1 (f32 [nk][3][N3]) with the attached network
-int nn_efield(kc_op* op, int ik0, int nk, float* E, hipStream_t s) {
+int nn_efield(kc_op* op, int ik0, int nk, float* E, hipStream_t s, float* Et) {
   Net* net = op->net;
   const int N = op->N;
   const size_t N3 = (size_t)N * N * N;
@@ -534,9 +537,16 @@ int nn_efield(kc_op* op, int ik0, int nk, float* E, hipStream_t s) {
   KC_TRY(nn_features(op, ik0, nk, net->feat.as<uint16_t>(), s));
   KC_TRY(nn_forward(net, N, nk, net->feat.as<uint16_t>(), net->out.as<float>(), s));
   const unsigned g = (unsigned)std::min<size_t>((N3 * nk + 255) / 256, 65535);
-  k_efield<<<g, 256, 0, s>>>(net->out.as<float>(), op->efield.as<float>(), N, nk, E);
+  k_efield<<<g, 256, 0, s>>>(net->out.as<float>(), op->efield.as<float>(), N, nk, E, Et);
   KC_LAUNCHED();
   return KC_OK;
+}
+
+int learned_fields(kc_op* op, int ik0, int nk, hipStream_t s) {
+  const size_t bytes = (size_t)nk * 3 * op->N * op->N * op->N * sizeof(float);
+  KC_TRY(op->efield_k.ensure(bytes));
+  KC_TRY(op->efield_kt.ensure(bytes));
+  return nn_efield(op, ik0, nk, op->efield_k.as<float>(), s, op->efield_kt.as<float>());
 }
 
 // E0_c = 1/(eps^-1)_cc of the material at the c-edge points (f32 [3][N3])

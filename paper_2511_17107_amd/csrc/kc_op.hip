@@ -411,7 +411,7 @@ constexpr bool plane_ok() {
 template <int N, typename T>
 __global__ __launch_bounds__(NT_PLANE) void k_yz_field(cpx<T>* __restrict__ buf, const float* __restrict__ fieldt,
                                                        const cpx<T>* __restrict__ gtw,
-                                                       const int* __restrict__ active) {
+                                                       const int* __restrict__ active, int vpk, int fks) {
   constexpr int PL = N + 1;
   constexpr size_t N3 = (size_t)N * N * N;
   constexpr T inv = T(1) / T(N3);
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(NT_PLANE) void k_yz_field(cpx<T>* __restrict__ buf,
   if (active && !active[vec]) return;
   load_twiddles<N>(tw, gtw);
   cpx<T>* pl = buf + vec * 3 * N3 + (size_t)c * N3 + (size_t)x * N * N;  // [z][y]
-  const float* f = fieldt + (size_t)c * N3 + (size_t)x * N * N;
+  const float* f = fieldt + ((vec / vpk) * fks * 3 + c) * N3 + (size_t)x * N * N;
   for (int t = threadIdx.x; t < N * N; t += NT_PLANE) lds[(t / N) * PL + t % N] = pl[t];
   __syncthreads();
   fft_2d<N, N, 1, PL, NT_PLANE, +1, T>(lds, tw);  // along y: pencils = rows z
@@ -703,9 +703,11 @@ static void launch_x2(kc_op* op, int pass, int nvec, const cpx<T>* A, const c64*
 }
 
 template <int N, typename T>
-static void launch_yz(int nvec, cpx<T>* A, const float* fieldt, const cpx<T>* tw, const int* act, hipStream_t s) {
+static void launch_yz(int nvec, cpx<T>* A, const float* fieldt, int vpk, int fks, const cpx<T>* tw, const int* act,
+                      hipStream_t s) {
   if constexpr (plane_ok<N, T>())
-    k_yz_field<N, T><<<nblk((size_t)nvec * 3 * N), NT_PLANE, plane_lds_bytes<N, T>(), s>>>(A, fieldt, tw, act);
+    k_yz_field<N, T><<<nblk((size_t)nvec * 3 * N), NT_PLANE, plane_lds_bytes<N, T>(), s>>>(A, fieldt, tw, act, vpk,
+                                                                                            fks);
 }
 
 template <int N, int DIR, typename T>
@@ -838,14 +840,17 @@ static int apply_tp_n(kc_op* op, int ik0, int nvec, const VecMap& vm, const VecM
   const PassArgs<T> pa = pass_args<N, T>(op, ik0);
   const int* act = vm.active;
   if constexpr (plane_ok<N, T>()) {
-    // the classical field shared by all k-points: x-passes in the x-major layout around one
-    // yz-plane pass
-    if (fkstride == 0 && field == op->efield.as<float>() && op->efield_t.p != nullptr) {
+    // fields with an x-major copy (the classical field shared by all k-points, the learned
+    // fields one per k-point): x-passes in the x-major layout around one yz-plane pass
+    const float* fieldt = nullptr;
+    if (fkstride == 0 && field == op->efield.as<float>()) fieldt = op->efield_t.as<float>();
+    if (fkstride == 1 && field == op->efield_k.as<float>()) fieldt = op->efield_kt.as<float>();
+    if (fieldt != nullptr) {
       KC_TRY(op->work_k.ensure((size_t)nvec * N3 * sizeof(cpx<T>)));
       cpx<T>* kx = op->work_k.as<cpx<T>>();
       launch_x1<N, T, true, true>(op, TP_X1P, nvec, x, A, pa.ktab, vm, pa.tw, s, kx, nullptr, nullptr, sfl);
       KC_LAUNCHED();
-      launch_yz<N, T>(nvec, A, op->efield_t.as<float>(), pa.tw, act, s);
+      launch_yz<N, T>(nvec, A, fieldt, vm.vpk, fkstride, pa.tw, act, s);
       KC_LAUNCHED();
       launch_x2<N, T, true, true>(op, TP_X2P, nvec, A, x, y, pa.ktab, pa.ktab64, pa.gam, vm, vmy, pa.tw, s, kx,
                                   nullptr, sfl);

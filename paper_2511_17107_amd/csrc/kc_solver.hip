@@ -172,8 +172,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       return KC_ERR_INVALID_ARG;
     }
     // one network pass per k-point of the batch gives its field
-    KC_TRY(op->efield_k.ensure((size_t)nb * n * sizeof(float)));
-    KC_TRY(nn_efield(op, ik0, nb, op->efield_k.as<float>(), s));
+    KC_TRY(learned_fields(op, ik0, nb, s));
     B.field = op->efield_k.as<float>();
     B.fks = 1;
   } else if (B.pc == KC_PRECOND_TRANSVERSE) {

@@ -218,6 +218,29 @@ def test_learned_field_and_precond_match_definition():
     assert rel_err(z, ref) < 1e-10
 
 
+@pytest.mark.parametrize("N", [16, 32])
+@pytest.mark.parametrize("prec,tol", [(kc.KC_PREC_FP64, 1e-10), (kc.KC_PREC_FP32, 2e-6)])
+def test_learned_precond_per_kpoint_fields(N, prec, tol):
+    """kc_precond_learned over three k-points, two vectors each: every k-point's T_E takes its own
+    learned field (FP32: through the yz-plane pass, which reads the x-major copy written beside
+    the fields), against the oracle's pseudo-inverse definition of T_E with the field that
+    kc_net_efield returns for that k-point."""
+    wl = W.sphere_anisotropic(N=N, nk=9, m=6)
+    op = kc.Op(N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(wl.kpoints)
+    net, _ = rand_net(37, scale=0.05)
+    op.attach_net(net)
+    note("nn precond per k N=%d prec=%d" % (N, prec))
+    E = to_host(op.net_efield(ik0=1, nk=3)).astype(np.float64)
+    assert np.abs(E[0] - E[2]).max() > 1e-3 * E.max()  # the fields differ between k-points
+    r = W.random_block(90 + N, 6, N)
+    z = to_host(op.precond_learned(to_dev(r), ik0=1, vecs_per_k=2, prec=prec))
+    g = op.gamma()
+    for b in range(3):
+        ref = kspace.transverse_precond_apply(N, wl.kpoints[1 + b], g[1 + b], E[b], r[2 * b:2 * b + 2])
+        assert rel_err(z[2 * b:2 * b + 2], ref) < tol, (N, b)
+
+
 def test_solve_with_learned_preconditioner_matches_oracle():
     """Eigenvalues do not depend on the preconditioner: with a (random) network attached the
     solve still matches the oracle (and falls back to the diagonal one if it stalls)."""
