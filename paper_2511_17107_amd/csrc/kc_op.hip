@@ -462,23 +462,33 @@ struct ZPlane {
   uint32_t id[7];  // ids at (i,j), (i+1,j), (i,j-1), (i+1,j-1), (i-1,j), (i,j+1), (i-1,j+1)
 };
 
+// 32-bit byte offsets from a uniform base: the loads take the scalar-base + vector-offset form
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 template <typename T>
 __device__ __forceinline__ void load_plane(ZPlane<T>& z, const cpx<T>* E1, const cpx<T>* E2, const cpx<T>* E3,
-                                           const uint32_t* ids, const size_t (&col)[7], size_t plane) {
+                                           const uint32_t* ids, const uint32_t (&col)[7], uint32_t plane) {
   // col: (i,j), (i+1,j), (i,j-1), (i+1,j-1), (i-1,j), (i,j+1), (i-1,j+1)
-  z.e1[0] = E1[plane + col[0]];
-  z.e1[1] = E1[plane + col[1]];
-  z.e1[2] = E1[plane + col[2]];
-  z.e1[3] = E1[plane + col[3]];
-  z.e2[0] = E2[plane + col[0]];
-  z.e2[1] = E2[plane + col[4]];
-  z.e2[2] = E2[plane + col[5]];
-  z.e2[3] = E2[plane + col[6]];
-  z.e3[0] = E3[plane + col[0]];
-  z.e3[1] = E3[plane + col[4]];
-  z.e3[2] = E3[plane + col[2]];
+  uint32_t o[7];
 #pragma unroll
-  for (int c = 0; c < 7; ++c) z.id[c] = ids[plane + col[c]];
+  for (int c = 0; c < 7; ++c) o[c] = plane + col[c];
+  constexpr uint32_t B = sizeof(cpx<T>);
+  z.e1[0] = ld_off(E1, o[0] * B);
+  z.e1[1] = ld_off(E1, o[1] * B);
+  z.e1[2] = ld_off(E1, o[2] * B);
+  z.e1[3] = ld_off(E1, o[3] * B);
+  z.e2[0] = ld_off(E2, o[0] * B);
+  z.e2[1] = ld_off(E2, o[4] * B);
+  z.e2[2] = ld_off(E2, o[5] * B);
+  z.e2[3] = ld_off(E2, o[6] * B);
+  z.e3[0] = ld_off(E3, o[0] * B);
+  z.e3[1] = ld_off(E3, o[4] * B);
+  z.e3[2] = ld_off(E3, o[2] * B);
+#pragma unroll
+  for (int c = 0; c < 7; ++c) z.id[c] = ld_off(ids, o[c] * 4u);
 }
 
 template <int N, int P>
@@ -502,9 +512,12 @@ __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E
   constexpr int NSEG = ZbSeg<N, P>::NSEG, ZL = ZbSeg<N, P>::ZL;
   __shared__ cpx<T> lds[G::ELEMS];
   __shared__ cpx<T> tw[N];
-  __shared__ EpsEntry<T> eps[KC_MAX_MAT];
+  // the permittivity table, n_mat entries (dynamic LDS: the tile and this table fit three
+  // workgroups per CU at N = 128, P = 16 in FP32)
+  extern __shared__ __align__(16) unsigned char zb_eps_smem[];
+  EpsEntry<T>* eps = reinterpret_cast<EpsEntry<T>*>(zb_eps_smem);
   constexpr size_t N3 = (size_t)N * N * N;
-  constexpr size_t NN = (size_t)N * N;
+  constexpr uint32_t NN = (uint32_t)N * N;
   const unsigned nb = gridDim.x;
   unsigned b = xcd_swizzle(blockIdx.x, nb);
   const int xt = b % (N / P);
@@ -524,14 +537,19 @@ __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E
     const int i = xt * P + p, j = yy;
     const int ip = (i + 1 == N) ? 0 : i + 1, im = (i == 0) ? N - 1 : i - 1;
     const int jp = (j + 1 == N) ? 0 : j + 1, jm = (j == 0) ? N - 1 : j - 1;
-    const size_t col[7] = {(size_t)j * N + i,   (size_t)j * N + ip, (size_t)jm * N + i, (size_t)jm * N + ip,
-                           (size_t)j * N + im, (size_t)jp * N + i, (size_t)jp * N + im};
+    const uint32_t col[7] = {(uint32_t)(j * N + i),  (uint32_t)(j * N + ip), (uint32_t)(jm * N + i),
+                             (uint32_t)(jm * N + ip), (uint32_t)(j * N + im), (uint32_t)(jp * N + i),
+                             (uint32_t)(jp * N + im)};
     const int kb = seg * ZL;
     ZPlane<T> prev, cur, next;
-    load_plane(prev, E1, E2, E3, ids, col, (size_t)(kb == 0 ? N - 1 : kb - 1) * NN);
-    load_plane(cur, E1, E2, E3, ids, col, (size_t)kb * NN);
-    for (int k = kb; k < kb + ZL; ++k) {
-      load_plane(next, E1, E2, E3, ids, col, (size_t)(k + 1 == N ? 0 : k + 1) * NN);
+    load_plane(prev, E1, E2, E3, ids, col, (uint32_t)(kb == 0 ? N - 1 : kb - 1) * NN);
+    load_plane(cur, E1, E2, E3, ids, col, (uint32_t)kb * NN);
+    // fully unrolled (ZL is a compile-time constant): the three planes rotate by renaming, not
+    // by register moves
+#pragma unroll
+    for (int t = 0; t < ZL; ++t) {
+      const int k = kb + t;
+      load_plane(next, E1, E2, E3, ids, col, (uint32_t)(k + 1 == N ? 0 : k + 1) * NN);
       const uint32_t idc = cur.id[0];
       const EpsEntry<T>& ex = eps[idc & 255u];
       const EpsEntry<T>& ey = eps[(idc >> 8) & 255u];
@@ -732,8 +750,8 @@ static void launch_zb(kc_op* op, int nvec, const cpx<T>* B, cpx<T>* A, const Eps
                       const int* act, hipStream_t s) {
   with_tile<N, 3, T>(tile_of<T>(op, TP_ZB), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    k_zb_crossdof<N, T, P><<<nblk((size_t)nvec * N * (N / P)), NT, 0, s>>>(B, A, op->ids.as<uint32_t>(), eps,
-                                                                           op->n_mat, tw, act);
+    k_zb_crossdof<N, T, P><<<nblk((size_t)nvec * N * (N / P)), NT, op->n_mat * sizeof(EpsEntry<T>), s>>>(
+        B, A, op->ids.as<uint32_t>(), eps, op->n_mat, tw, act);
   });
 }
 
