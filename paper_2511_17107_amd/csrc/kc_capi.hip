@@ -328,6 +328,9 @@ int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, 
       e32[m].o[q] = mk((float)re, (float)im);
     }
   }
+  op->zoff = false;
+  for (int m = 0; m < n_mat; ++m)
+    for (int q = 1; q < 3; ++q) op->zoff = op->zoff || e64[m].o[q].re != 0.0 || e64[m].o[q].im != 0.0;
   int st = upload(op->ids, packed, hs);
   if (st == KC_OK) st = upload(op->eps64, e64, hs);
   if (st == KC_OK) st = upload(op->eps32, e32, hs);

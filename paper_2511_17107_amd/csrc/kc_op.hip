@@ -453,6 +453,9 @@ __global__ __launch_bounds__(NT_PLANE) void k_yz_field(cpx<T>* __restrict__ buf,
 // (i,j+1), (i-1,j+1), E3 at (i,j), (i-1,j), (i,j-1), and the ids at those seven columns, on the
 // planes k-1, k, k+1; the three planes live in registers and slide along z, so each plane is
 // read once per thread.  E and ids are read through the cache (neighbouring tiles share them).
+// Where no material couples z to x or y ((eps^-1)_13 = (eps^-1)_23 = 0, e.g. gyrotropic media
+// magnetised along z) the blocks (1,3), (2,3) and their transposes are zero and the kernel
+// (ZOFF = false) reads and multiplies only the in-plane stencils of plane k.
 // ------------------------------------------------------------------------------------
 template <typename T>
 struct ZPlane {
@@ -468,7 +471,8 @@ __device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
-template <typename T>
+// ZOFF == false: only the values of the in-plane blocks (1,2), (2,1) and the diagonal
+template <bool ZOFF = true, typename T>
 __device__ __forceinline__ void load_plane(ZPlane<T>& z, const cpx<T>* E1, const cpx<T>* E2, const cpx<T>* E3,
                                            const uint32_t* ids, const uint32_t (&col)[7], uint32_t plane) {
   // col: (i,j), (i+1,j), (i,j-1), (i+1,j-1), (i-1,j), (i,j+1), (i-1,j+1)
@@ -485,8 +489,10 @@ __device__ __forceinline__ void load_plane(ZPlane<T>& z, const cpx<T>* E1, const
   z.e2[2] = ld_off(E2, o[5] * B);
   z.e2[3] = ld_off(E2, o[6] * B);
   z.e3[0] = ld_off(E3, o[0] * B);
-  z.e3[1] = ld_off(E3, o[4] * B);
-  z.e3[2] = ld_off(E3, o[2] * B);
+  if constexpr (ZOFF) {
+    z.e3[1] = ld_off(E3, o[4] * B);
+    z.e3[2] = ld_off(E3, o[2] * B);
+  }
 #pragma unroll
   for (int c = 0; c < 7; ++c) z.id[c] = ld_off(ids, o[c] * 4u);
 }
@@ -503,7 +509,7 @@ struct ZbSeg {  // z-segments per x: the largest divisor of N with P * NSEG <= 2
   static constexpr int ZL = N / NSEG;
 };
 
-template <int N, typename T, int P>
+template <int N, typename T, int P, bool ZOFF>
 __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E, cpx<T>* __restrict__ out,
                                                     const uint32_t* __restrict__ ids,
                                                     const EpsEntry<T>* __restrict__ geps, int n_mat,
@@ -541,6 +547,36 @@ __global__ __launch_bounds__(NT) void k_zb_crossdof(const cpx<T>* __restrict__ E
                              (uint32_t)(jm * N + ip), (uint32_t)(j * N + im), (uint32_t)(jp * N + i),
                              (uint32_t)(jp * N + im)};
     const int kb = seg * ZL;
+    if constexpr (!ZOFF) {
+      // (eps^-1)_13 = (eps^-1)_23 = 0 in every material: the blocks (1,3), (2,3) and their
+      // transposes vanish, and each plane needs only its own values
+#pragma unroll
+      for (int t = 0; t < ZL; ++t) {
+        const int k = kb + t;
+        ZPlane<T> cur;
+        load_plane<false>(cur, E1, E2, E3, ids, col, (uint32_t)k * NN);
+        const uint32_t idc = cur.id[0];
+        const EpsEntry<T>& ex = eps[idc & 255u];
+        const EpsEntry<T>& ey = eps[(idc >> 8) & 255u];
+        const EpsEntry<T>& ez = eps[(idc >> 16) & 255u];
+        auto mx = [&](uint32_t id) -> const EpsEntry<T>& { return eps[id & 255u]; };
+        auto my = [&](uint32_t id) -> const EpsEntry<T>& { return eps[(id >> 8) & 255u]; };
+        cpx<T> a1 = mk(T(0), T(0));
+        cfma(a1, ex.o[0] + my(cur.id[0]).o[0], cur.e2[0]);
+        cfma(a1, ex.o[0] + my(cur.id[4]).o[0], cur.e2[1]);
+        cfma(a1, ex.o[0] + my(cur.id[5]).o[0], cur.e2[2]);
+        cfma(a1, ex.o[0] + my(cur.id[6]).o[0], cur.e2[3]);
+        cpx<T> a2 = mk(T(0), T(0));
+        cfmac(a2, mx(cur.id[0]).o[0] + ey.o[0], cur.e1[0]);
+        cfmac(a2, mx(cur.id[1]).o[0] + ey.o[0], cur.e1[1]);
+        cfmac(a2, mx(cur.id[2]).o[0] + ey.o[0], cur.e1[2]);
+        cfmac(a2, mx(cur.id[3]).o[0] + ey.o[0], cur.e1[3]);
+        lds[G::addr3(0, k, p)] = ex.d[0] * cur.e1[0] + e8 * a1;
+        lds[G::addr3(1, k, p)] = ey.d[1] * cur.e2[0] + e8 * a2;
+        lds[G::addr3(2, k, p)] = ez.d[2] * cur.e3[0];
+      }
+      continue;
+    }
     ZPlane<T> prev, cur, next;
     load_plane(prev, E1, E2, E3, ids, col, (uint32_t)(kb == 0 ? N - 1 : kb - 1) * NN);
     load_plane(cur, E1, E2, E3, ids, col, (uint32_t)kb * NN);
@@ -750,8 +786,12 @@ static void launch_zb(kc_op* op, int nvec, const cpx<T>* B, cpx<T>* A, const Eps
                       const int* act, hipStream_t s) {
   with_tile<N, 3, T>(tile_of<T>(op, TP_ZB), [&](auto pc) {
     constexpr int P = decltype(pc)::value;
-    k_zb_crossdof<N, T, P><<<nblk((size_t)nvec * N * (N / P)), NT, op->n_mat * sizeof(EpsEntry<T>), s>>>(
-        B, A, op->ids.as<uint32_t>(), eps, op->n_mat, tw, act);
+    const size_t lds = op->n_mat * sizeof(EpsEntry<T>);
+    const unsigned g = nblk((size_t)nvec * N * (N / P));
+    if (op->zoff)
+      k_zb_crossdof<N, T, P, true><<<g, NT, lds, s>>>(B, A, op->ids.as<uint32_t>(), eps, op->n_mat, tw, act);
+    else
+      k_zb_crossdof<N, T, P, false><<<g, NT, lds, s>>>(B, A, op->ids.as<uint32_t>(), eps, op->n_mat, tw, act);
   });
 }
 

@@ -65,6 +65,7 @@ struct kc_op {
   int N = 0;
   int scheme = 0;
   int n_mat = 0;
+  bool zoff = true;              // some material has (eps^-1)_13 or (eps^-1)_23 != 0
   int stencil_m = 1;             // order 2m of the curl/divergence stencils (eq (2.34))
   kc::Skew skew;                 // lattice transform of the symbols (eq (2.12)); cubic: l1d == nullptr
   kc::DevBuf lam1;               // Lambda_1(q): c64 [N] then c32 [N] (non-cubic lattices)

@@ -64,6 +64,12 @@ def _case(N, scheme_name, seed=0):
     if scheme_name == "iso":
         wl = W.sphere_isotropic(N=N)
         return wl.ids, wl.table, "crossdof"
+    if scheme_name == "gyro":
+        # gyrotropic materials only ((eps^-1)_13 = (eps^-1)_23 = 0 everywhere: the stencil pass
+        # drops the blocks (1,3) and (2,3)), two of them so that ids differ between point sets
+        ids = W.sample_ids(N, [W.Sphere((0.5, 0.5, 0.5), 0.3, 1), W.Rod(2, (0.1, 0.2, 0.0), 0.17, 2)])
+        tab = W.eps_table([W.gyrotropic_eps(12.0, 0.5, 10.0), W.gyrotropic_eps(7.0, -0.8, 4.0)])
+        return ids, tab, "crossdof"
     wl = W.sphere_anisotropic(N=N, nk=2, m=4, seed=seed)
     # add a second inclusion with a gyrotropic tensor so all off-diagonals and complex
     # entries are exercised, and material ids differ between the point sets
@@ -73,7 +79,7 @@ def _case(N, scheme_name, seed=0):
 
 
 @pytest.mark.parametrize("N", SMALL_N)
-@pytest.mark.parametrize("scheme", ["diagonal", "trivial", "crossdof", "iso"])
+@pytest.mark.parametrize("scheme", ["diagonal", "trivial", "crossdof", "iso", "gyro"])
 def test_apply_fp64_matches_oracle(N, scheme):
     ids, tab, sch = _case(N, scheme)
     op = kc.Op(N, kc.SCHEMES[sch], ids, tab)
@@ -90,7 +96,7 @@ def test_apply_fp64_matches_oracle(N, scheme):
 
 
 @pytest.mark.parametrize("N", [8, 16])
-@pytest.mark.parametrize("scheme", ["trivial", "crossdof"])
+@pytest.mark.parametrize("scheme", ["trivial", "crossdof", "gyro"])
 def test_apply_fp32_close_to_oracle(N, scheme):
     ids, tab, sch = _case(N, scheme)
     op = kc.Op(N, kc.SCHEMES[sch], ids, tab)
@@ -161,7 +167,8 @@ def test_apply_hermitian_positive(N):
 
 
 @pytest.mark.parametrize("scheme,prec,tol", [("crossdof", kc.KC_PREC_FP64, 1e-11), ("trivial", kc.KC_PREC_FP64, 1e-11),
-                                             ("crossdof", kc.KC_PREC_FP32, 3e-6)])
+                                             ("crossdof", kc.KC_PREC_FP32, 3e-6), ("gyro", kc.KC_PREC_FP64, 1e-11),
+                                             ("gyro", kc.KC_PREC_FP32, 3e-6)])
 def test_apply_n128_tiled_geometry_matches_scaled_oracle(scheme, prec, tol):
     """Full-size parity at N = 128, the benchmark's grid: with a geometry that repeats every 16
     cells and a field of the same period, the 128^3 operator at wave vector k equals 64 times the
