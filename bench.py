@@ -12,7 +12,7 @@ reuses it.  Prints one JSON line (see the keys below).
 
     python bench.py [--steps K] [--warmup W] [--kpb 10] [--guard 4] [--prec fp32|fp64]
                     [--precond transverse|diag] [--no-cpu-baseline]
-    python bench.py --matvec-only | --update-only     (single kernels, for rocprofv3)
+    python bench.py --matvec-only | --update-only | --gram-only   (single kernels, for rocprofv3)
 
 `roofline` is the fused block update + residual pass (the largest kernel of a step), timed live
 at the solve's batch shape after the solve; `matvec` lists the operator passes, the roofline of
@@ -34,7 +34,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch, from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE (x 1.0), the factors
 # read off a plain 1 GiB device copy in the same run: operator passes on 16 vectors at 128^3,
-# FP32, keyed by pass and tile width (profiles/matvec_woodpile128_fp32_16vec.md); the fused
+# FP32, keyed by pass and tile width (profiles/matvec_woodpile128_fp32_16vec.md; the stencil pass Zb
+# as it runs on the woodpile, whose materials couple no z); the fused
 # update keyed by N, k-points and block width (profiles/update_woodpile128_10k_20col.md).
 MEASURED_TRAFFIC = {
     ("X1", 128, 16, "fp32", 4): 2.953e9, ("X1", 128, 16, "fp32", 8): 2.953e9, ("X1", 128, 16, "fp32", 16): 2.953e9,
@@ -42,7 +43,7 @@ MEASURED_TRAFFIC = {
     ("Y1", 128, 16, "fp32", 32): 1.611e9,
     ("Za", 128, 16, "fp32", 4): 4.027e9, ("Za", 128, 16, "fp32", 8): 2.416e9, ("Za", 128, 16, "fp32", 16): 1.611e9,
     ("Za", 128, 16, "fp32", 32): 1.611e9,
-    ("Zb", 128, 16, "fp32", 4): 1.794e9, ("Zb", 128, 16, "fp32", 8): 1.776e9, ("Zb", 128, 16, "fp32", 16): 1.959e9,
+    ("Zb", 128, 16, "fp32", 4): 1.777e9, ("Zb", 128, 16, "fp32", 8): 1.757e9, ("Zb", 128, 16, "fp32", 16): 1.755e9,
     ("Y2", 128, 16, "fp32", 4): 4.027e9, ("Y2", 128, 16, "fp32", 8): 2.416e9, ("Y2", 128, 16, "fp32", 16): 1.611e9,
     ("Y2", 128, 16, "fp32", 32): 1.611e9,
     ("X2", 128, 16, "fp32", 4): 2.953e9, ("X2", 128, 16, "fp32", 8): 2.953e9, ("X2", 128, 16, "fp32", 16): 2.954e9,
@@ -79,6 +80,9 @@ def parse():
     ap.add_argument("--update-only", action="store_true",
                     help="only the fused block update (kc_block_update) at the solve's batch shape, three "
                          "launches, and the 1 GiB device copy; for profiling")
+    ap.add_argument("--gram-only", action="store_true",
+                    help="only the Gram products S^H AS, S^H S (kc_block_gram) at the solve's batch shape, "
+                         "three launches; for profiling the MFMA counters")
     ap.add_argument("--workload", choices=["c4", "c2", "c3", "c5"], default="c4",
                     help="c4: the headline (128^3 woodpile); c2: 64^3 anisotropic sphere, 20 bands, 40 "
                          "k-points, FP64; c3: the same sphere, 16 bands, 120 k-points in two launch sets, "
@@ -170,6 +174,31 @@ def update_block(a, dev):
     C = torch.from_numpy(W.random_complex(8, (nb, 3 * mb, 2 * mb)) / np.sqrt(6 * mb)).to(dev)
     theta = torch.from_numpy(np.random.default_rng(9).uniform(0.05, 0.5, (nb, mb))).to(dev)
     return S, AS, C, theta
+
+
+def gram_only(a, dev):
+    """Three Gram launches (GA = S^H AS, GB = S^H S over 3mb columns per k-point) at the solve's
+    batch shape, with their HIP-event durations and the FP64 MFMA rate they imply."""
+    import torch
+
+    import paper_2511_17107_amd as kc
+
+    mb, nb, n = a.m + a.guard, a.kpb, 3 * a.N ** 3
+    S, AS, _, _ = update_block(a, dev)
+    nc = 3 * mb
+    GA = torch.empty((nb, nc, nc), dtype=torch.complex128, device=dev)
+    GB = torch.empty_like(GA)
+    work = torch.empty(kc.block_work_bytes(nb, n, nc), dtype=torch.uint8, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    for r in range(3):
+        ev[2 * r].record()
+        kc.block_gram(S, AS, GA, GB, work)
+        ev[2 * r + 1].record()
+    torch.cuda.synchronize()
+    ms = [ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(3)]
+    flops = 2 * nb * n * nc * nc * 8  # two nc x nc complex products over n rows (8 real flops per complex MAC)
+    print(json.dumps({"gram_kpoints": nb, "columns": nc, "N": a.N, "ms": ms,
+                      "tflops": flops / (min(ms) * 1e-3) / 1e12, "checksum": float(GB.abs().sum())}), flush=True)
 
 
 def update_roofline(a, dev, reps=5):
@@ -324,6 +353,9 @@ def main():
         return
     if a.update_only:
         update_only(a, dev)
+        return
+    if a.gram_only:
+        gram_only(a, dev)
         return
 
     xbuf = None
