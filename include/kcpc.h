@@ -409,6 +409,47 @@ int kc_net_efield(kc_op* op, int ik0, int nk, float* efield, void* stream);
 int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void* r, void* z, int prec,
                        void* stream);
 
+/*
+ * Training support of the learned preconditioner (not part of the paper, whose solver uses the
+ * diagonal-block K_P^{-1} of eqs (2.31)-(2.32); the network predicts the field E of T_E).  All
+ * vectors are device complex128 k-space vectors [nvec][3][N^3] of one k-point ik; the calls run
+ * on `stream`, synchronise it before returning, and take their work vectors from the handle's
+ * allocator (released by kc_release_workspaces).
+ *
+ * kc_pcg: c_j = Op^{-1} r_j by conjugate gradients preconditioned with T_E of the classical field
+ *   E_c = 1/(eps^-1)_cc, FP64 operator applications, until every recurrence residual satisfies
+ *   |r_j - Op c_j| <= tol |r_j|.  r and c must not overlap; c is overwritten.  *iters (host, may
+ *   be NULL) receives the iterations done.  1 <= nvec <= 256, tol > 0, maxit >= 1.  Returns
+ *   KC_ERR_NO_CONVERGENCE after maxit iterations (c then holds the last iterate).  Op must be
+ *   nonsingular: k = 0 is rejected only by the iteration failing to converge.
+ */
+int kc_pcg(kc_op* op, int ik, int nvec, const void* r, void* c, double tol, int maxit, int* iters, void* stream);
+
+/*
+ * kc_perturbed_residuals: training inputs from orthonormal vectors X [m][3][N^3] (converged
+ *   eigenvectors of k-point ik): e = K_P^{-1} noise (eqs (2.31)-(2.32)), minus its orthogonal
+ *   projection onto span(X), scaled to unit length; x_j = X_j + amp_j e_j; theta_j =
+ *   <x_j, Op x_j> / <x_j, x_j> (Rayleigh quotient); r_j = Op x_j - theta_j x_j (FP64).
+ *   noise: device [m][3][N^3]; amp: host double [m]; x (may be NULL) and r: device outputs
+ *   [m][3][N^3], not overlapping X or noise.  1 <= m <= 32.
+ */
+int kc_perturbed_residuals(kc_op* op, int ik, int m, const void* X, const void* noise, const double* amp, void* x,
+                           void* r, void* stream);
+
+/*
+ * kc_net_loss_grad: mean over j < nvec of the scale-free misfit of z_j = T_E r_j (E: the attached
+ *   network's field for k-point ik, as kc_net_efield) against the targets c_j = Op^{-1} r_j:
+ *   kind 0 (Op-norm, the norm of the eigensolver's convergence):
+ *     min_alpha |alpha z - c|_Op^2 / |c|_Op^2 = 1 - (z^H r)^2 / ((z^H Op z)(c^H r));
+ *   kind 1 (Euclidean): min_alpha |alpha z - c|^2 / |c|^2.
+ *   *loss (host) receives the mean.  With gout != NULL (device float32 [N^3][16], the layout of
+ *   the network's output y), also writes scale * d(mean)/dy: channels 0-2 through
+ *   E = E0 exp(clamp(y, -3, 3)) (zero where the clamp is active), the other channels zero; the
+ *   optimal alpha is held fixed (it is stationary).  1 <= nvec <= 256.
+ */
+int kc_net_loss_grad(kc_op* op, int ik, int nvec, const void* r, const void* c, int kind, double scale, double* loss,
+                     float* gout, void* stream);
+
 /* Human-readable name of a status code. */
 const char* kc_status_string(int status);
 

@@ -25,6 +25,9 @@ eigs      smallest strictly positive eigenvalues of the compensated operator
           k = 0 constant-field null space removed (Prop 2.5).
 nn        direct-summation 3D convolution with circular padding and its
           gradients (learned preconditioner), in FP64.
+train     the training quantities of the learned preconditioner (not part of the
+          paper): perturbed iterates and their residuals, exact corrections by a
+          sparse direct solve, the scale-free misfit from its definition.
 block     the dense block steps of the LOBPCG iteration (Section 4): Gram matrices of
           the search space and the Rayleigh-Ritz update with the residuals of
           eq (4.3), from their definitions.

@@ -125,6 +125,9 @@ def lib():
         L.kc_net_features.argtypes = [vp, i32, i32, vp, vp]
         L.kc_net_efield.argtypes = [vp, i32, i32, vp, vp]
         L.kc_precond_learned.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp]
+        L.kc_pcg.argtypes = [vp, i32, i32, vp, vp, ctypes.c_double, i32, ctypes.POINTER(i32), vp]
+        L.kc_perturbed_residuals.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.kc_net_loss_grad.argtypes = [vp, i32, i32, vp, vp, i32, ctypes.c_double, dp, vp, vp]
         L.kc_block_work_bytes.argtypes = [i32, ctypes.c_size_t, i32]
         L.kc_block_work_bytes.restype = ctypes.c_size_t
         L.kc_block_gram.argtypes = [i32, ctypes.c_size_t, i32, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
@@ -564,6 +567,69 @@ class Op:
         _check(lib().kc_net_efield(self._h, int(ik0), int(nk), _dev_ptr(out, "torch.float32", "efield"),
                                    _stream(stream)), "kc_net_efield")
         return out
+
+    def pcg(self, r, ik: int = 0, tol: float = 1e-7, maxit: int = 400, out=None, stream=None):
+        """kc_pcg: c = Op^{-1} r (block r complex128 [nvec][3][N^3] of k-point ik).  Returns
+        (c, iterations, converged)."""
+        import torch
+
+        nvec = int(r.shape[0])
+        _numel(r, nvec * 3 * self.n3, "r")
+        if out is None:
+            out = torch.empty_like(r)
+        _numel(out, nvec * 3 * self.n3, "c")
+        its = ctypes.c_int(0)
+        st = lib().kc_pcg(self._h, int(ik), nvec, _dev_ptr(r, "torch.complex128", "r"),
+                          _dev_ptr(out, "torch.complex128", "c"), float(tol), int(maxit), ctypes.byref(its),
+                          _stream(stream))
+        if st not in (KC_OK, KC_ERR_NO_CONVERGENCE):
+            _check(st, "kc_pcg")
+        return out, its.value, st == KC_OK
+
+    def perturbed_residuals(self, X, noise, amp, ik: int = 0, x_out=None, r_out=None, stream=None):
+        """kc_perturbed_residuals: (x, r) for orthonormal X and noise (complex128 [m][3][N^3])
+        and amplitudes amp (m host values)."""
+        import torch
+
+        m = int(X.shape[0])
+        _numel(X, m * 3 * self.n3, "X")
+        _numel(noise, m * 3 * self.n3, "noise")
+        a = np.ascontiguousarray(np.asarray(amp, dtype=np.float64).reshape(-1))
+        if a.size != m:
+            raise ValueError("amp needs one value per vector")
+        x = torch.empty_like(X) if x_out is None else x_out
+        r = torch.empty_like(X) if r_out is None else r_out
+        _numel(x, m * 3 * self.n3, "x")
+        _numel(r, m * 3 * self.n3, "r")
+        _check(lib().kc_perturbed_residuals(self._h, int(ik), m, _dev_ptr(X, "torch.complex128", "X"),
+                                            _dev_ptr(noise, "torch.complex128", "noise"),
+                                            a.ctypes.data_as(ctypes.c_void_p), _dev_ptr(x, "torch.complex128", "x"),
+                                            _dev_ptr(r, "torch.complex128", "r"), _stream(stream)),
+               "kc_perturbed_residuals")
+        return x, r
+
+    def net_loss_grad(self, r, c, ik: int = 0, kind: str = "energy", grad: bool = False, scale: float = 1.0,
+                      out=None, stream=None):
+        """kc_net_loss_grad: mean misfit of T_E r (the attached network's field) against c; with
+        grad, also scale * d(mean)/d(network output) (float32 [N^3][16]).  Returns (loss, gout)."""
+        import torch
+
+        nvec = int(r.shape[0])
+        _numel(r, nvec * 3 * self.n3, "r")
+        _numel(c, nvec * 3 * self.n3, "c")
+        if kind not in ("energy", "euclidean"):
+            raise ValueError("kind: 'energy' or 'euclidean'")
+        gptr = None
+        if grad:
+            if out is None:
+                out = torch.empty((self.n3, 16), dtype=torch.float32, device=r.device)
+            _numel(out, self.n3 * 16, "gout")
+            gptr = _dev_ptr(out, "torch.float32", "gout")
+        loss = ctypes.c_double(0.0)
+        _check(lib().kc_net_loss_grad(self._h, int(ik), nvec, _dev_ptr(r, "torch.complex128", "r"),
+                                      _dev_ptr(c, "torch.complex128", "c"), 0 if kind == "energy" else 1,
+                                      float(scale), ctypes.byref(loss), gptr, _stream(stream)), "kc_net_loss_grad")
+        return loss.value, (out if grad else None)
 
     def precond_learned(self, r, ik0: int = 0, vecs_per_k: Optional[int] = None, prec: int = KC_PREC_FP64,
                         out=None, stream=None):

@@ -687,6 +687,7 @@ int kc_release_workspaces(kc_op* op) {
   op->work_k.release();
   op->efield_k.release();
   op->efield_kt.release();
+  op->train_buf.release();
   return KC_OK;
 }
 

@@ -95,6 +95,7 @@ struct kc_op {
   kc::DevBuf efield_k;        // f32 [nb][3][N^3] learned fields of the k-points being solved
   kc::DevBuf efield_kt;       // the same, x-major ([nb][3][x][z][y]), written with efield_k
   kc::DevBuf kdev;            // double [nk][3] wave vectors
+  kc::DevBuf train_buf;       // work vectors of kc_pcg, kc_perturbed_residuals, kc_net_loss_grad
   double stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   std::vector<std::vector<double>> hist;  // per k-point of the last kc_solve: max Res_j per iteration
   std::vector<std::vector<int8_t>> histp; // ... and the precision of that iteration's AW
@@ -104,7 +105,7 @@ struct kc_op {
   // every device buffer of the handle takes its memory from `alloc`
   void bind_allocator() {
     kc::DevBuf* bufs[] = {&ids, &eps64, &eps32, &tw64, &tw32, &ktab64, &ktab32, &gamma_d, &sfloor_d, &dcl_d, &lam1, &work_a, &work_b,
-                          &work_c, &work_k, &epsfeat, &efield, &efield_t, &efield_k, &efield_kt, &kdev};
+                          &work_c, &work_k, &epsfeat, &efield, &efield_t, &efield_k, &efield_kt, &kdev, &train_buf};
     for (kc::DevBuf* b : bufs) b->al = &alloc;
   }
 };

@@ -19,9 +19,10 @@ network output, and the library's backward and Adam kernels update the weights.
     python -m paper_2511_17107_amd.learned train --out weights.npy [--geoms 32 --N 32]
     python -m paper_2511_17107_amd.learned eval --weights weights.npy [--N 96 --nk 8]
 
-PyTorch here holds device buffers and does the inner products, norms and elementwise products
-of the loss; every operator application, preconditioner, FFT and network pass runs in the
-library's kernels.
+PyTorch here only holds device buffers (allocation, host-device copies, concatenation of the
+network inputs and output gradients of a batch); the iterates, residuals, corrections (kc_pcg),
+the loss and its gradient (kc_net_loss_grad), and every operator application, preconditioner,
+FFT and network pass run in the library's kernels.
 """
 from __future__ import annotations
 
@@ -44,35 +45,11 @@ def _torch():
     return torch
 
 
-def _dot(a, b):
-    """Re<a_j, b_j> per vector of blocks [nv][3][N^3]."""
-    return (a.conj() * b).real.sum(dim=(1, 2))
-
-
 def pcg(op, ik, r, tol=1e-7, maxit=400):
-    """Solve Op c = r (one k-point, block of columns r [nv][3][N^3]) by preconditioned CG with
-    the library's operator and the classical transverse-projection preconditioner."""
-    torch = _torch()
-    nv = r.shape[0]
-    c = torch.zeros_like(r)
-    res = r.clone()
-    z = op.precond_transverse(res, ik0=ik, vecs_per_k=nv)
-    p = z.clone()
-    rz = _dot(res, z)
-    rn0 = torch.linalg.vector_norm(r.reshape(nv, -1), dim=1)
-    for it in range(maxit):
-        Ap = op.apply(p, ik0=ik, vecs_per_k=nv)
-        alpha = rz / _dot(p, Ap)
-        c += alpha[:, None, None] * p
-        res -= alpha[:, None, None] * Ap
-        rn = torch.linalg.vector_norm(res.reshape(nv, -1), dim=1)
-        if bool((rn <= tol * rn0).all()):
-            break
-        z = op.precond_transverse(res, ik0=ik, vecs_per_k=nv)
-        rz_new = _dot(res, z)
-        p = z + (rz_new / rz)[:, None, None] * p
-        rz = rz_new
-    return c
+    """c = Op^{-1} r for a block r [nv][3][N^3] of k-point ik (kc_pcg: conjugate gradients with
+    the library's FP64 operator, preconditioned with T_E of the classical field)."""
+    c, its, ok = op.pcg(r, ik=ik, tol=tol, maxit=maxit)
+    return c, its, ok
 
 
 class Sample:
@@ -99,64 +76,30 @@ def make_samples(N, seeds, m=8, nk_path=40, amp=(0.02, 0.3), rng_seed=0, log=pri
         X = torch.zeros((m, 3, n3), dtype=torch.complex128, device=dev)
         eig, res, its, st = op.solve(m, tol=1e-7, guard=2, X_out=X, seed=int(s), precond=kc.KC_PRECOND_TRANSVERSE)
         op.release_workspaces()  # the training passes need only the operator's own buffers
-        # perturbation: smoothed noise orthogonal to the converged block
+        # iterates x = X + a e with smoothed noise e orthogonal to the converged block, and
+        # their residuals (kc_perturbed_residuals); targets c = Op^{-1} r (kc_pcg)
         noise = torch.from_numpy(W.random_block(10_000 + int(s), m, N)).to(dev)
-        e = op.precond(noise, vecs_per_k=m)
-        Q = X.reshape(m, -1)
-        E = e.reshape(m, -1)
-        E = E - (E @ Q.conj().T) @ Q
-        E = E / torch.linalg.vector_norm(E, dim=1, keepdim=True)
-        a = torch.from_numpy(rng.uniform(amp[0], amp[1], size=m)).to(dev)
-        x = (Q + a[:, None] * E).reshape(m, 3, n3).contiguous()
-        Ax = op.apply(x, vecs_per_k=m)
-        theta = _dot(x, Ax) / _dot(x, x)
-        r = (Ax - theta[:, None, None] * x).contiguous()
-        c = pcg(op, 0, r)
+        a = rng.uniform(amp[0], amp[1], size=m)
+        _, r = op.perturbed_residuals(X, noise, a)
+        c, pits, ok = pcg(op, 0, r)
         feat = op.net_features(0, 1)
         op.release_workspaces()
-        out.append(Sample(op, feat, r, c, {"seed": int(s), "k": kidx, "eig0": float(eig[0][0]), "iters": int(its[0])}))
-        log("samples: geometry %d k=%d eig[0]=%.4f iters=%d" % (s, kidx, eig[0][0], its[0]))
+        out.append(Sample(op, feat, r, c, {"seed": int(s), "k": kidx, "eig0": float(eig[0][0]), "iters": int(its[0]),
+                                           "pcg_iters": pits, "pcg_converged": ok}))
+        log("samples: geometry %d k=%d eig[0]=%.4f iters=%d pcg %d%s" % (s, kidx, eig[0][0], its[0], pits,
+                                                                         "" if ok else " (not converged)"))
     return out
 
 
-def sample_loss(net, smp, grad=False, loss_kind="energy"):
-    """Mean scale-free misfit over the sample's residuals; with grad, also the gradient of that
-    mean with respect to the network output (float32 [N^3][16]).
+def sample_loss(net, smp, grad=False, loss_kind="energy", scale=1.0):
+    """Mean scale-free misfit over the sample's residuals (kc_net_loss_grad); with grad, also
+    scale times its gradient with respect to the network output (float32 [N^3][16]).
 
     energy:    min_alpha |alpha T_E r - c|_Op^2 / |c|_Op^2 = 1 - (z^H r)^2 / ((z^H Op z)(c^H r)),
                z = T_E r (the Op-norm, in which LOBPCG's convergence is measured)
     euclidean: min_alpha |alpha T_E r - c|^2 / |c|^2"""
-    torch = _torch()
-    op = smp.op
-    m = smp.r.shape[0]
-    E = op.net_efield(0, 1)
-    z = op.precond_transverse(smp.r, vecs_per_k=m, efield=E)
-    if loss_kind == "energy":
-        Oz = op.apply(z, vecs_per_k=m)
-        cr = _dot(smp.c, smp.r)
-        zr = _dot(z, smp.r)
-        zOz = _dot(z, Oz)
-        alpha = zr / zOz
-        loss = float((1.0 - zr * zr / (zOz * cr)).mean())
-        if not grad:
-            return loss, None
-        ge = (alpha[:, None, None] * Oz - smp.r).contiguous()  # Op e with e = alpha z - c
-        w = (2.0 * alpha / (cr * m)).contiguous()
-    else:
-        cn2 = _dot(smp.c, smp.c)
-        alpha = _dot(z, smp.c) / _dot(z, z)
-        ge = (alpha[:, None, None] * z - smp.c).contiguous()
-        loss = float((_dot(ge, ge) / cn2).mean())
-        if not grad:
-            return loss, None
-        w = (2.0 * alpha / (cn2 * m)).contiguous()
-    gE = torch.zeros_like(E)
-    op.tp_grad(smp.r, ge, w, gE, vecs_per_k=m)
-    y = net.forward(smp.feat, op.N)[0]  # [N^3][16]
-    gy = torch.zeros_like(y)
-    inside = (y[:, :3].abs() < 3.0).float()
-    gy[:, :3] = (gE[0] * E[0]).T * inside  # dE/dy = E inside the clamp range
-    return loss, gy
+    smp.op.attach_net(net)
+    return smp.op.net_loss_grad(smp.r, smp.c, kind=loss_kind, grad=grad, scale=scale)
 
 
 def train(net, samples, steps=400, batch=4, lr=1e-3, log=print, seed=0, loss_kind="energy"):
@@ -176,11 +119,10 @@ def train(net, samples, steps=400, batch=4, lr=1e-3, log=print, seed=0, loss_kin
         feats, gys, ls = [], [], []
         for i in idx:
             smp = samples[i]
-            smp.op.attach_net(net)
-            loss, gy = sample_loss(net, smp, grad=True, loss_kind=loss_kind)
+            loss, gy = sample_loss(net, smp, grad=True, loss_kind=loss_kind, scale=1.0 / len(idx))
             ls.append(loss)
             feats.append(smp.feat)
-            gys.append(gy / len(idx))
+            gys.append(gy)
         net.backward(torch.cat(feats).contiguous(), torch.stack(gys).contiguous(), N, host_grads=False)
         net.adam_step(lr * (0.5 ** (it / max(steps // 3, 1))))
         hist.append(float(np.mean(ls)))

@@ -89,6 +89,19 @@ def test_null_handle_arguments():
     L.kc_destroy(None)
 
 
+def test_training_calls_check_arguments():
+    """The learned preconditioner's training calls reject a NULL handle before any device work."""
+    L = kc.lib()
+    vp = ctypes.c_void_p
+    its = ctypes.c_int(-1)
+    assert L.kc_pcg(None, 0, 1, vp(1), vp(2), 1e-7, 10, ctypes.byref(its), None) == 1
+    amp = np.ones(2)
+    assert L.kc_perturbed_residuals(None, 0, 2, vp(1), vp(2), amp.ctypes.data_as(vp), None, vp(3), None) == 1
+    loss = ctypes.c_double(0.0)
+    assert L.kc_net_loss_grad(None, 0, 1, vp(1), vp(2), 0, 1.0, ctypes.byref(loss), None, None) == 1
+    assert its.value == -1
+
+
 def test_solve_opts_defaults():
     """kc_solve_opts_default is host-only: the struct layout of the binding matches the header."""
     import ctypes
@@ -190,6 +203,11 @@ def test_binding_checks_sizes_before_the_library():
                  lambda: op.solve(2, nk=2, X_out=torch.zeros((2, 2, n - 1), dtype=torch.complex128)),
                  lambda: op.solve(2, nk=2, x_init=torch.zeros((2, 2, n + 1), dtype=torch.complex128)),
                  lambda: op.net_efield(nk=2, out=torch.zeros((2, 3, N ** 3 - 1), dtype=torch.float32)),
+                 lambda: op.pcg(short), lambda: op.pcg(good, out=short),
+                 lambda: op.perturbed_residuals(good, short, [0.1, 0.2]),
+                 lambda: op.perturbed_residuals(good, good, [0.1]),
+                 lambda: op.perturbed_residuals(good, good, [0.1, 0.2], r_out=short),
+                 lambda: op.net_loss_grad(good, short), lambda: op.net_loss_grad(good, good, kind="l1"),
                  lambda: kc.kc_fft3d(torch.zeros((2, N ** 3), dtype=torch.complex128), 1,
                                      out=torch.zeros((2, N ** 3 - 2), dtype=torch.complex128))]:
         with pytest.raises(ValueError):
