@@ -92,6 +92,7 @@ def parse():
     ap.add_argument("--c5-geoms", type=int, nargs=2, default=[400, 100],
                     help="training geometries at 32^3 and at 64^3 (c5)")
     ap.add_argument("--c5-steps", type=int, default=600)
+    ap.add_argument("--c2-guard", type=int, default=4, help="guard columns of the c2 workload (20 bands)")
     ap.add_argument("--verbose", type=int, default=0)
     return ap.parse_args()
 
@@ -254,8 +255,8 @@ def update_only(a, dev):
 def sphere64_run(a, dev):
     """The 64^3 anisotropic-sphere configurations (sphere r = 0.3a, eps = R diag(e) R^T with
     e_i ~ U[4,14], seed 0, CrossDoF, k-points uniform on Gamma-X-M-Gamma-R):
-      c2: 20 bands (+1 guard column, the largest block the one-workgroup Rayleigh-Ritz takes), 40
-          k-points in one launch set, FP64 operator;
+      c2: 20 bands (+ --c2-guard guard columns, default 4: a 24-column block, on the wide path of
+          the block kernels), 40 k-points in one launch set, FP64 operator;
       c3: 16 bands (+4 guard), 120 k-points in two launch sets of 60, FP32 operator phase with FP64
           block algebra and finish, against the FP64 path on the same k-points (per-band relative
           eigenvalue differences) and the FP64 path one k-point at a time.
@@ -266,7 +267,7 @@ def sphere64_run(a, dev):
     import workloads as W
 
     c2 = a.workload == "c2"
-    m, guard, nk, kpb = (20, 1, 40, 40) if c2 else (16, 4, 120, 60)
+    m, guard, nk, kpb = (20, a.c2_guard, 40, 40) if c2 else (16, 4, 120, 60)
     wl = W.sphere_anisotropic(N=64, nk=nk, m=m)
     op = kc.Op(64, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
     op.set_kpoints(wl.kpoints)

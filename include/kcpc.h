@@ -291,7 +291,9 @@ enum { KC_PRECOND_DIAG = 0, KC_PRECOND_LEARNED = 1, KC_PRECOND_TRANSVERSE = 2 };
 /* Solver options for kc_solve (LOBPCG with soft locking, Section 4). */
 typedef struct kc_solve_opts {
   int m;              /* bands wanted (smallest positive eigenvalues)                      */
-  int guard;          /* extra block columns carried but not required to converge (>= 0) */
+  int guard;          /* extra block columns carried but not required to converge (>= 0); */
+                      /* m + guard <= 32 (blocks of more than 21 columns take the wide    */
+                      /* kernels: Rayleigh-Ritz matrices in global memory)                 */
   double tol;         /* convergence: Res_j = ||Op x_j - lambda_j x_j|| / ||x_j|| <= tol  */
                       /* (eq (4.3)), checked with an FP64 operator application             */
   int maxit;          /* iteration limit                                                   */

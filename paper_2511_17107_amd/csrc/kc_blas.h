@@ -63,7 +63,8 @@ int random_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, uint
                  hipStream_t s);
 
 // Small dense steps (one workgroup per k-point), see kc_small.hip.
-constexpr int RR_NMAX = 64;      // 3 * block size
+constexpr int RR_NMAX = 64;       // 3 * block size of the LDS-resident kernels (block size <= 21)
+constexpr int RR_NMAX_WIDE = 96;  // 3 * block size of the wide path (block size <= 32)
 constexpr int RR_THREADS = 1024;  // one workgroup per k-point: 16 waves hide the LDS latency
 
 // Rayleigh-Ritz on S = [X W P]: from GA = S^H AS, GB = S^H S (3mb x 3mb) compute the mb
@@ -74,8 +75,11 @@ constexpr int RR_THREADS = 1024;  // one workgroup per k-point: 16 waves hide th
 // res (device [nb * mb], or nullptr): the current residual norms |r_j| of the (orthonormal) X
 // block, theta its current Ritz values: a step whose Ritz values fall below what they allow is
 // rejected (X kept, P dropped, flags[b] |= 2).
+// Blocks of up to 21 columns (3mb <= RR_NMAX) keep the matrices in LDS; wider ones (mb <= 32) in
+// Lsave, which holds small_rr_ws_bytes(mb) bytes per k-point.
 int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,
              double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, c64* gapp_out,
              hipStream_t s, const double* res = nullptr);
+size_t small_rr_ws_bytes(int mb);
 
 }  // namespace kc

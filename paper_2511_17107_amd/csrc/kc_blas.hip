@@ -43,12 +43,15 @@ constexpr int GW_THREADS = 64 * GW_WAVES;
 
 // MAXT tiles per wave: ceil(ntile / G2_WAVES).  (At nc = 60, 20 tiles over 8 waves leave four
 // slots that multiply zeros; 4 waves x 5 tiles would waste none, but at one wave per SIMD it
-// measured 45.7 instead of 33 ms per launch.)
-template <int MAXT>
+// measured 45.7 instead of 33 ms per launch.)  COLS: columns a stage row holds per block (64,
+// or 96 for the wide blocks of more than 21 columns per k-point).
+template <int MAXT, int COLS = G2_COLS>
 __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
                                                int nc, int kstride, int rows_per_chunk, int ntile,
                                                c64* __restrict__ part, const int* __restrict__ kskip) {
-  __shared__ c64 st[G2_ROWS * G2_PITCH];
+  constexpr int ZERO = 2 * COLS;            // 16 zero entries (tiles a wave does not own)
+  constexpr int PITCH = 2 * COLS + 16 + 1;  // LDS row pitch (complex), odd to spread banks
+  __shared__ c64 st[G2_ROWS * PITCH];
   const int b = blockIdx.y;
   if (kskip && kskip[b]) return;
   const int chunk = blockIdx.x;
@@ -60,7 +63,7 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
   int tmat[MAXT], tti[MAXT], ttj[MAXT];
   for (int t = 0; t < MAXT; ++t) {
     tmat[t] = 1;
-    tti[t] = ttj[t] = G2_ZERO / 16;
+    tti[t] = ttj[t] = ZERO / 16;
   }
   int nt = 0;
   {
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
   const size_t r_begin = (size_t)chunk * rows_per_chunk;
   const size_t r_end = std::min(n, r_begin + rows_per_chunk);
   const int ncol2 = 2 * nc;
-  constexpr int PER = (G2_ROWS * 2 * 64 + G2_THREADS - 1) / G2_THREADS;  // staged entries per thread
+  constexpr int PER = (G2_ROWS * 2 * COLS + G2_THREADS - 1) / G2_THREADS;  // staged entries per thread
   c64 nxt[PER];
   auto fetch = [&](size_t r0) {
 #pragma unroll
@@ -110,12 +113,12 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
       const int e = threadIdx.x + q * G2_THREADS;
       if (e < G2_ROWS * ncol2) {
         const int c = e / G2_ROWS;
-        st[(e % G2_ROWS) * G2_PITCH + (c < nc ? c : G2_COLS + c - nc)] = nxt[q];
+        st[(e % G2_ROWS) * PITCH + (c < nc ? c : COLS + c - nc)] = nxt[q];
       }
     }
   };
   // padding columns (nc..63 of S and of AS) and the zero block stay zero for the whole chunk
-  for (int e = threadIdx.x; e < G2_ROWS * G2_PITCH; e += blockDim.x) st[e] = mk(0.0, 0.0);
+  for (int e = threadIdx.x; e < G2_ROWS * PITCH; e += blockDim.x) st[e] = mk(0.0, 0.0);
   __syncthreads();
   if (r_begin < r_end) {
     fetch(r_begin);
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
     constexpr int K = decltype(kc_)::value;
 #pragma unroll
     for (int kb = 0; kb < G2_ROWS; kb += 4) {
-      const c64* srow = st + (kb + lk) * G2_PITCH;
+      const c64* srow = st + (kb + lk) * PITCH;
       asm volatile("" ::: "memory");  // one 4-row step's operands live at a time (occupancy)
       c64 av[K], bv[K];
 #pragma unroll
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(G2_THREADS) void k_gram2(const c64* __restrict__ S,
         const int ca = tti[t] * 16 + li;
         const int cb = ttj[t] * 16 + li;
         av[t] = srow[ca];
-        bv[t] = srow[(tmat[t] == 0 ? G2_COLS : 0) + cb];
+        bv[t] = srow[(tmat[t] == 0 ? COLS : 0) + cb];
       }
       // consecutive MFMAs go to different accumulators
 #pragma unroll
@@ -222,14 +225,15 @@ __global__ void k_gram2_reduce(const c64* __restrict__ part, int nchunk, int nti
 // zeros after; the 16x16 tiles (ti < ceil(nc/16), tj < ceil(2mb/16)) are dealt to the waves,
 // MAXT = ceil(ntile / GW_WAVES) each (12 tiles at mb = 20: three per wave, none idle).
 // ------------------------------------------------------------------------------------
-constexpr int GW_R = G2_COLS;                      // start of [W | AW] in a stage row
-constexpr int GW_ZERO = G2_COLS + 48;              // 16 zero entries
-constexpr int GW_PITCH = G2_COLS + 48 + 16 + 1;
-
-template <int MAXT>
+// COLS: columns of S a stage row holds (64, or 96 for blocks of more than 21 columns); WW: room
+// for [W | AW] (2mb <= 48, or 64)
+template <int MAXT, int COLS = G2_COLS, int WW = 48>
 __global__ __launch_bounds__(GW_THREADS) void k_gramw(const c64* __restrict__ S, const c64* __restrict__ AS, size_t n,
                                                       int mb, int kstride, int rows_per_chunk, int ntile,
                                                       c64* __restrict__ part, const int* __restrict__ kskip) {
+  constexpr int GW_R = COLS;                 // start of [W | AW] in a stage row
+  constexpr int GW_ZERO = COLS + WW;         // 16 zero entries
+  constexpr int GW_PITCH = COLS + WW + 16 + 1;
   __shared__ c64 st[G2_ROWS * GW_PITCH];
   const int b = blockIdx.y;
   if (kskip && kskip[b]) return;
@@ -262,8 +266,8 @@ __global__ __launch_bounds__(GW_THREADS) void k_gramw(const c64* __restrict__ S,
   const c64* AWb = AS + ((size_t)b * kstride + mb) * n;
   const size_t r_begin = (size_t)chunk * rows_per_chunk;
   const size_t r_end = std::min(n, r_begin + rows_per_chunk);
-  const int ncl = nc + mb;  // loaded columns: S, then AW (at most 4 * RR_NMAX / 3)
-  constexpr int PER = (G2_ROWS * (4 * (RR_NMAX / 3)) + GW_THREADS - 1) / GW_THREADS;
+  const int ncl = nc + mb;  // loaded columns: S, then AW (at most 4 COLS / 3)
+  constexpr int PER = (G2_ROWS * (4 * (COLS / 3)) + GW_THREADS - 1) / GW_THREADS;
   c64 nxt[PER];
   auto fetch = [&](size_t r0) {
 #pragma unroll
@@ -401,11 +405,11 @@ __global__ void k_gramw_reduce(const c64* __restrict__ part, int nchunk, int nti
 // With U (p a multiple of 4) the clamp moves whole groups of 4 columns, so every column offset
 // is uniform (scalar registers) and a lane adds only its 32-bit byte offset `boff` (lk*n + row);
 // otherwise each lane clamps its own column.
-template <int TQ, bool U>
+template <int TQ, bool U, int NMAX>
 __device__ __forceinline__ void rows_times_c(const c64* Sb, const c64* csh, int p, size_t n, size_t rowc,
                                              uint32_t boff, int lk, int li, d4 (&p1)[TQ], d4 (&p2)[TQ],
                                              d4 (&p3)[TQ]) {
-  constexpr int PK = RR_NMAX / 4;
+  constexpr int PK = NMAX / 4;
   constexpr int QP = TQ * 16;
   asm volatile("" ::: "memory");
   c64 sv[PK];
@@ -459,24 +463,24 @@ __device__ __forceinline__ c64& elem(c64* base, int col, size_t n, uint32_t boff
     return base[(size_t)col * n + row];
 }
 
-// C_b (p x q) into LDS, zero-padded to RR_NMAX x TQ*16
-template <int TQ>
+// C_b (p x q) into LDS, zero-padded to NMAX x TQ*16
+template <int TQ, int NMAX>
 __device__ __forceinline__ void stage_c(const c64* Cb, c64* csh, int p, int q) {
   constexpr int QP = TQ * 16;
-  for (int t = threadIdx.x; t < RR_NMAX * QP; t += blockDim.x) {
+  for (int t = threadIdx.x; t < NMAX * QP; t += blockDim.x) {
     const int r = t / QP, c = t % QP;
     csh[t] = (r < p && c < q) ? Cb[r * q + c] : mk(0.0, 0.0);
   }
 }
 
-template <int TQ, bool U>
+template <int TQ, bool U, int NMAX = RR_NMAX>
 __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64* __restrict__ C, size_t n,
                                                 int p, int q, int skstride, int scol0, int ykstride, int q1,
                                                 int ycol0, int ycol1, const int* __restrict__ kskip) {
-  extern __shared__ c64 csh[];  // C_b zero-padded to RR_NMAX x TQ*16
+  extern __shared__ c64 csh[];  // C_b zero-padded to NMAX x TQ*16
   const int b = blockIdx.y;
   if (kskip && kskip[b]) return;
-  stage_c<TQ>(C + (size_t)b * p * q, csh, p, q);
+  stage_c<TQ, NMAX>(C + (size_t)b * p * q, csh, p, q);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -490,7 +494,7 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
     const size_t rowc = rok ? row : n - 1;
     const uint32_t boff = (uint32_t)(((size_t)lk * n + rowc) * sizeof(c64));
     d4 p1[TQ], p2[TQ], p3[TQ];
-    rows_times_c<TQ, U>(Sb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
+    rows_times_c<TQ, U, NMAX>(Sb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
 #pragma unroll
     for (int t = 0; t < TQ; ++t)
 #pragma unroll
@@ -511,20 +515,20 @@ __global__ __launch_bounds__(256) void k_update(const c64* S, c64* Y, const c64*
 // k_resid_reduce).  X column j = 4s + lk is slot s < XS of lane (lk, li): tile s/4, entry s%4;
 // between the two products each lane parks its new X values in a private LDS slot (in registers
 // they would push the kernel to one wave per SIMD).
-template <int XS, bool U>
+template <int XS, bool U, int NMAX = RR_NMAX>
 __global__ __launch_bounds__(256) void k_update_res(c64* S, c64* AS, const c64* __restrict__ C, size_t n, int mb,
                                                     int kstride, const double* __restrict__ theta,
                                                     c64* __restrict__ R, double* __restrict__ part,
                                                     const int* __restrict__ kskip) {
   constexpr int TQ = (XS + 1) / 2;  // 2mb output columns in tiles of 16
-  extern __shared__ c64 csh[];  // C_b (RR_NMAX x TQ*16), then the parked X values [4][XS][64]
-  __shared__ double th[RR_NMAX];
+  extern __shared__ c64 csh[];  // C_b (NMAX x TQ*16), then the parked X values [4][XS][64]
+  __shared__ double th[NMAX / 3];
   __shared__ double red[4][XS][4][2];
-  c64* xpark = csh + RR_NMAX * TQ * 16;
+  c64* xpark = csh + NMAX * TQ * 16;
   const int b = blockIdx.y;
   if (kskip && kskip[b]) return;
   const int p = 3 * mb, q = 2 * mb;
-  stage_c<TQ>(C + (size_t)b * p * q, csh, p, q);
+  stage_c<TQ, NMAX>(C + (size_t)b * p * q, csh, p, q);
   for (int j = threadIdx.x; j < mb; j += blockDim.x) th[j] = theta[b * mb + j];
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(256) void k_update_res(c64* S, c64* AS, const c64* 
     c64* xk = xpark + (size_t)wave * XS * 64 + lane;  // slot s at xk[s * 64]
     {
       d4 p1[TQ], p2[TQ], p3[TQ];
-      rows_times_c<TQ, U>(Sb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
+      rows_times_c<TQ, U, NMAX>(Sb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
 #pragma unroll
       for (int t = 0; t < TQ; ++t)
 #pragma unroll
@@ -560,7 +564,7 @@ __global__ __launch_bounds__(256) void k_update_res(c64* S, c64* AS, const c64* 
     }
     {
       d4 p1[TQ], p2[TQ], p3[TQ];
-      rows_times_c<TQ, U>(ASb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
+      rows_times_c<TQ, U, NMAX>(ASb, csh, p, n, rowc, boff, lk, li, p1, p2, p3);
 #pragma unroll
       for (int t = 0; t < TQ; ++t)
 #pragma unroll
@@ -806,16 +810,22 @@ static int gram2_rows(const c64* S, const c64* AS, int kstride, int nc, size_t n
                       c64* GB, const int* kskip, size_t rows, hipStream_t s) {
   const int T = (nc + 15) / 16;
   const int ntile = T * (T + 1);
-  if (nc > 64 || ntile > 20) {
+  if (nc > RR_NMAX_WIDE) {
     set_error("gram2: too many columns");
     return KC_ERR_INVALID_ARG;
   }
   const int nchunk = (int)((n + rows - 1) / rows);
   dim3 grid(nchunk, nb);
-  switch ((ntile + G2_WAVES - 1) / G2_WAVES) {
-    case 1: k_gram2<1><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
-    case 2: k_gram2<2><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
-    default: k_gram2<3><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
+  if (nc <= G2_COLS) {
+    switch ((ntile + G2_WAVES - 1) / G2_WAVES) {
+      case 1: k_gram2<1><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
+      case 2: k_gram2<2><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
+      default: k_gram2<3><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip); break;
+    }
+  } else if (nc <= 80) {  // 65..80 columns: 30 tiles on an 80-column stage
+    k_gram2<4, 80><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip);
+  } else {  // 81..96 columns: 42 tiles
+    k_gram2<6, RR_NMAX_WIDE><<<grid, G2_THREADS, 0, s>>>(S, AS, n, nc, kstride, (int)rows, ntile, part, kskip);
   }
   KC_LAUNCHED();
   dim3 g2(1, ntile, nb);
@@ -835,7 +845,7 @@ int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, De
   const int nc = 3 * mb;
   const int T = (nc + 15) / 16, TR = (2 * mb + 15) / 16;
   const int ntile = T * TR;
-  if (nc > 64 || 2 * mb > 48 || ntile > 16) {
+  if (nc > RR_NMAX_WIDE) {
     set_error("gramw: too many columns");
     return KC_ERR_INVALID_ARG;
   }
@@ -843,10 +853,20 @@ int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, De
   const int nchunk = (int)((n + rows - 1) / rows);
   KC_TRY(part.ensure((size_t)nb * nchunk * ntile * 256 * sizeof(c64)));
   dim3 grid(nchunk, nb);
-  switch ((ntile + GW_WAVES - 1) / GW_WAVES) {
-    case 1: k_gramw<1><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, part.as<c64>(), kskip); break;
-    case 2: k_gramw<2><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, part.as<c64>(), kskip); break;
-    default: k_gramw<3><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, part.as<c64>(), kskip); break;
+  c64* pp = part.as<c64>();
+  const int maxt = (ntile + GW_WAVES - 1) / GW_WAVES;
+  if (nc <= G2_COLS && 2 * mb <= 48) {  // at most 16 tiles
+    switch (maxt) {
+      case 1: k_gramw<1><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, pp, kskip); break;
+      case 2: k_gramw<2><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, pp, kskip); break;
+      default: k_gramw<3><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, pp, kskip); break;
+    }
+  } else {  // the wide blocks: up to 6 x 4 tiles
+    switch (maxt) {
+      case 4: k_gramw<4, 96, 64><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, pp, kskip); break;
+      case 5: k_gramw<5, 96, 64><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, pp, kskip); break;
+      default: k_gramw<6, 96, 64><<<grid, GW_THREADS, 0, s>>>(S, AS, n, mb, kstride, (int)rows, ntile, pp, kskip); break;
+    }
   }
   KC_LAUNCHED();
   dim3 g2(1, ntile + 1, nb);
@@ -855,28 +875,54 @@ int gramw(const c64* S, const c64* AS, int kstride, int mb, size_t n, int nb, De
   return KC_OK;
 }
 
+// rows of C staged by the update kernels of the wide path: 3mb rounded up to 72, 84 or 96, so
+// that no k-step multiplies only padding (and at mb <= 24 two workgroups fit a CU's LDS)
+static int wide_rows(int p) { return p <= 72 ? 72 : p <= 84 ? 84 : RR_NMAX_WIDE; }
+
 int update(const c64* S, int skstride, int scol0, int p, c64* Y, int ykstride, int q, int q1, int ycol0,
            int ycol1, const c64* C, size_t n, int nb, const int* kskip, hipStream_t s) {
   dim3 grid(update_grid_x(n, nb), nb);
-  const size_t shm = (size_t)RR_NMAX * ((q + 15) / 16 * 16) * sizeof(c64);
-  if (p > RR_NMAX) {
-    set_error("update: too many input columns");
+  if (p > RR_NMAX_WIDE || q > 64) {
+    set_error("update: too many input or output columns");
     return KC_ERR_INVALID_ARG;
   }
+  const bool wide = p > RR_NMAX;
+  const int rows = wide ? wide_rows(p) : RR_NMAX;
+  const size_t shm = (size_t)rows * ((q + 15) / 16 * 16) * sizeof(c64);
   const bool u = p % 4 == 0 && q % 4 == 0 && q1 % 4 == 0 && 4 * n * sizeof(c64) < (size_t(1) << 32);
-#define KC_UPD(T)                                                                                       \
-  if (u)                                                                                                \
-    k_update<T, true><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, \
-                                             kskip);                                                    \
-  else                                                                                                  \
-    k_update<T, false><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, \
-                                              kskip)
-  if (q <= 16) {
-    KC_UPD(1);
+#define KC_UPD(T, NM)                                                                                        \
+  if (u)                                                                                                     \
+    k_update<T, true, NM><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0, ycol1, \
+                                                 kskip);                                                     \
+  else                                                                                                       \
+    k_update<T, false, NM><<<grid, 256, shm, s>>>(S, Y, C, n, p, q, skstride, scol0, ykstride, q1, ycol0,    \
+                                                  ycol1, kskip)
+  if (wide) {
+    // the wide path (more than 21 columns per block): C needs more than 64 KiB of LDS
+    KC_TRY(update_res_prepare());
+    if (rows == 72) {
+      if (q <= 48) {
+        KC_UPD(3, 72);
+      } else {
+        KC_UPD(4, 72);
+      }
+    } else if (rows == 84) {
+      if (q <= 48) {
+        KC_UPD(3, 84);
+      } else {
+        KC_UPD(4, 84);
+      }
+    } else if (q <= 48) {
+      KC_UPD(3, 96);
+    } else {
+      KC_UPD(4, 96);
+    }
+  } else if (q <= 16) {
+    KC_UPD(1, RR_NMAX);
   } else if (q <= 32) {
-    KC_UPD(2);
+    KC_UPD(2, RR_NMAX);
   } else if (q <= 48) {
-    KC_UPD(3);
+    KC_UPD(3, RR_NMAX);
   } else {
     set_error("update: too many output columns");
     return KC_ERR_INVALID_ARG;
@@ -894,7 +940,8 @@ unsigned update_grid_x(size_t n, int nb) {
 // dynamic LDS of k_update_res: C_b and the parked X values
 static size_t update_res_lds(int mb) {
   const int xs = (mb + 3) / 4;
-  return ((size_t)RR_NMAX * (((xs + 1) / 2) * 16) + (size_t)4 * xs * 64) * sizeof(c64);
+  const size_t nmax = 3 * mb > RR_NMAX ? wide_rows(3 * mb) : RR_NMAX;
+  return (nmax * (((xs + 1) / 2) * 16) + (size_t)4 * xs * 64) * sizeof(c64);
 }
 
 int update_res_prepare() {
@@ -909,13 +956,31 @@ int update_res_prepare() {
   for (int i = 0; i < 12; ++i)
     KC_HIP(hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)update_res_lds(4 * (i % 6 + 1))));
+  // the wide path: 22 <= mb <= 32 (xs 6..8 with 72, 84, 96 staged rows of C), and the plain
+  // update with up to 96 input and 64 output columns
+  const void* kw[6] = {(const void*)k_update_res<6, false, 72>, (const void*)k_update_res<7, false, 84>,
+                       (const void*)k_update_res<8, false, 96>, (const void*)k_update_res<6, true, 72>,
+                       (const void*)k_update_res<7, true, 84>,  (const void*)k_update_res<8, true, 96>};
+  const int kwmb[6] = {24, 28, 32, 24, 28, 32};
+  for (int i = 0; i < 6; ++i)
+    KC_HIP(hipFuncSetAttribute(kw[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)update_res_lds(kwmb[i])));
+  const void* ku[12] = {(const void*)k_update<3, false, 72>, (const void*)k_update<4, false, 72>,
+                        (const void*)k_update<3, true, 72>,  (const void*)k_update<4, true, 72>,
+                        (const void*)k_update<3, false, 84>, (const void*)k_update<4, false, 84>,
+                        (const void*)k_update<3, true, 84>,  (const void*)k_update<4, true, 84>,
+                        (const void*)k_update<3, false, 96>, (const void*)k_update<4, false, 96>,
+                        (const void*)k_update<3, true, 96>,  (const void*)k_update<4, true, 96>};
+  const int kur[3] = {72, 84, 96};
+  for (int i = 0; i < 12; ++i)
+    KC_HIP(hipFuncSetAttribute(ku[i], hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kur[i / 4] * 64 * sizeof(c64))));
   done = true;
   return KC_OK;
 }
 
 int update_res(c64* S, c64* AS, int kstride, int mb, const c64* C, size_t n, int nb, const double* theta, c64* R,
                double* part, double* res, double* xnorm2, const int* kskip, hipStream_t s) {
-  if (mb < 1 || 3 * mb > RR_NMAX) {
+  if (mb < 1 || 3 * mb > RR_NMAX_WIDE) {
     set_error("update_res: block size out of range");
     return KC_ERR_INVALID_ARG;
   }
@@ -930,7 +995,20 @@ int update_res(c64* S, c64* AS, int kstride, int mb, const c64* C, size_t n, int
     k_update_res<X, true><<<grid, 256, shm, s>>>(S, AS, C, n, mb, kstride, theta, R, part, kskip); \
   else                                                                                        \
     k_update_res<X, false><<<grid, 256, shm, s>>>(S, AS, C, n, mb, kstride, theta, R, part, kskip)
-  switch (xs) {
+#define KC_UPDRES_W(X, NM)                                                                    \
+  if (u)                                                                                      \
+    k_update_res<X, true, NM><<<grid, 256, shm, s>>>(S, AS, C, n, mb, kstride, theta, R, part, kskip); \
+  else                                                                                        \
+    k_update_res<X, false, NM><<<grid, 256, shm, s>>>(S, AS, C, n, mb, kstride, theta, R, part, kskip)
+  if (3 * mb > RR_NMAX) {
+    // xs 6, 7, 8 <-> mb 22..24, 25..28, 29..32 <-> 72, 84, 96 staged rows
+    KC_TRY(update_res_prepare());
+    switch (xs) {
+      case 6: KC_UPDRES_W(6, 72); break;
+      case 7: KC_UPDRES_W(7, 84); break;
+      default: KC_UPDRES_W(8, 96); break;
+    }
+  } else switch (xs) {
     case 1: KC_UPDRES(1); break;
     case 2: KC_UPDRES(2); break;
     case 3: KC_UPDRES(3); break;
@@ -939,6 +1017,7 @@ int update_res(c64* S, c64* AS, int kstride, int mb, const c64* C, size_t n, int
     default: KC_UPDRES(6); break;
   }
 #undef KC_UPDRES
+#undef KC_UPDRES_W
   KC_LAUNCHED();
   const int nv = nb * mb;
   k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part, (int)gx, nv, res, xnorm2, nullptr);

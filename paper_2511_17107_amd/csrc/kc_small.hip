@@ -14,13 +14,23 @@
 
 namespace kc {
 
-constexpr int LD = RR_NMAX;  // leading dimension of LDS matrices
+// LD: leading dimension of the n x n matrices (RR_NMAX, matrices in LDS; RR_NMAX_WIDE, matrices in
+// global memory, for blocks of more than 21 columns per k-point)
+
+// elements per k-point of the Lsave workspace: the saved Cholesky factor, and in the wide form
+// (GLOBAL) the working matrices Am, Bm and C1 after it
+template <int LD, bool GLOBAL>
+constexpr size_t rr_ws_elems() {
+  constexpr int LDC = LD == RR_NMAX ? 24 : 32;
+  return (size_t)LD * LD + (GLOBAL ? (size_t)2 * LD * LD + (size_t)LD * LDC : 0);
+}
 
 // In-place right-looking Cholesky A = L L^H (lower triangle, leading dimension LD) of the
 // Hermitian n x n matrix.  A column whose pivot is not above tol * diag0[j] (or is not
 // finite) is dropped: its row and column of L become the identity, act[j] = 0, and if it is
 // `protect`ed the breakdown flag is raised.  The factor then belongs to the matrix with that
 // row and column replaced by the identity.
+template <int LD>
 __device__ void chol_masked(c64* A, int n, int* act, const double* diag0, double tol, const int* protect,
                             int* breakdown) {
   __shared__ double piv;
@@ -65,6 +75,7 @@ __device__ void chol_masked(c64* A, int n, int* act, const double* diag0, double
 }
 
 // B <- L^{-1} B for an n x ncol matrix B (leading dimension ldb), L lower (LD).
+template <int LD>
 __device__ void trsm_lower(const c64* L, int n, c64* B, int ldb, int ncol) {
   for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
     for (int i = 0; i < n; ++i) {
@@ -77,6 +88,7 @@ __device__ void trsm_lower(const c64* L, int n, c64* B, int ldb, int ncol) {
 }
 
 // B <- L^{-H} B (back substitution with L^H).
+template <int LD>
 __device__ void trsm_lower_h(const c64* L, int n, c64* B, int ldb, int ncol) {
   for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
     for (int i = n - 1; i >= 0; --i) {
@@ -89,6 +101,7 @@ __device__ void trsm_lower_h(const c64* L, int n, c64* B, int ldb, int ncol) {
 }
 
 // in-place conjugate transpose of an n x n LDS matrix (LD)
+template <int LD>
 __device__ void conj_transpose(c64* A, int n) {
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
@@ -114,6 +127,7 @@ __device__ void conj_transpose(c64* A, int n) {
 // A pair is rotated while |a_pq| > 1e-15 sqrt(|a_pp a_qq|) (relative accuracy) and |a_pq| is
 // above the rounding floor 4e-16 ||A||_F that the 2x2 updates themselves leave behind; without
 // the second test, pairs of a small and a large diagonal entry would keep rotating on noise.
+template <int LD>
 __device__ void jacobi(c64* A, c64* V, int n, const int* act, double fro) {
   __shared__ int idx[LD];
   __shared__ int na;
@@ -218,6 +232,7 @@ __device__ void jacobi(c64* A, c64* V, int n, const int* act, double fro) {
 // ------------------------------------------------------------------------------------
 // Rayleigh-Ritz.  Dynamic LDS: Am (LD x LD), Bm (LD x LD), C1 (LD x mb).
 // ------------------------------------------------------------------------------------
+template <int LD, bool GLOBAL>
 __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__ GA, const c64* __restrict__ GB, int mb,
                                                   const int* __restrict__ xmask, const int* __restrict__ wmask,
                                                   const int* __restrict__ pmask, double* __restrict__ theta,
@@ -227,11 +242,13 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
                                                   const double* __restrict__ res) {
   const int b = blockIdx.x;
   if (kskip && kskip[b]) return;
+  constexpr int LDC = LD == RR_NMAX ? 24 : 32;  // leading dim of n x mb blocks (mb <= 21, or 32)
+  // this k-point's saved Cholesky factor, then (wide form) its working matrices
+  c64* Ls = Lsave + (size_t)b * rr_ws_elems<LD, GLOBAL>();
   extern __shared__ c64 sm[];
-  c64* Am = sm;
-  c64* Bm = sm + LD * LD;
-  constexpr int LDC = 24;       // leading dim of n x mb blocks (mb <= 21)
-  c64* C1 = sm + 2 * LD * LD;  // n x mb
+  c64* Am = GLOBAL ? Ls + LD * LD : sm;
+  c64* Bm = Am + LD * LD;
+  c64* C1 = Am + 2 * LD * LD;  // n x mb
   __shared__ int act[LD], prot[LD], ord[LD], pact[LD];
   __shared__ double ev[LD], d0[LD], sc[LD];
   __shared__ int brk, nact;
@@ -275,7 +292,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
                                           : (sc[i] * sc[j]) * Bm[i * LD + j];
   }
   __syncthreads();
-  chol_masked(Bm, n, act, d0, 1e-8, prot, &brk);
+  chol_masked<LD>(Bm, n, act, d0, 1e-8, prot, &brk);
   // GA, masked and Hermitian (inactive: zero row/column, diagonal set after the transform)
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
@@ -287,9 +304,9 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
   }
   __syncthreads();
   // Am <- L^{-1} Am L^{-H}
-  trsm_lower(Bm, n, Am, LD, n);
-  conj_transpose(Am, n);
-  trsm_lower(Bm, n, Am, LD, n);
+  trsm_lower<LD>(Bm, n, Am, LD, n);
+  conj_transpose<LD>(Am, n);
+  trsm_lower<LD>(Bm, n, Am, LD, n);
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
     if (i < j) {
@@ -323,14 +340,13 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
   for (int i = threadIdx.x; i < n; i += blockDim.x)
     if (!act[i]) Am[i * LD + i] = mk(2.0 * fro + 1.0 + (double)i, 0.0);
   // save L, V = I
-  c64* Ls = Lsave + (size_t)b * LD * LD;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int i = e / n, j = e % n;
     Ls[i * LD + j] = Bm[i * LD + j];
     Bm[i * LD + j] = (i == j) ? mk(1.0, 0.0) : mk(0.0, 0.0);
   }
   __syncthreads();
-  jacobi(Am, Bm, n, act, fro);
+  jacobi<LD>(Am, Bm, n, act, fro);
   // ascending order by rank (ties by index)
   for (int i = threadIdx.x; i < n; i += blockDim.x) ev[i] = Am[i * LD + i].re;
   __syncthreads();
@@ -401,7 +417,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
     Am[i * LD + j] = Ls[i * LD + j];
   }
   __syncthreads();
-  trsm_lower_h(Am, n, C1, LDC, mb);
+  trsm_lower_h<LD>(Am, n, C1, LDC, mb);
   // P direction: Y = C1 with the X rows zeroed; Y' = Y - C1 (C1^H GB Y); Y'' = Y' M^{-1/2}
   // through the Cholesky factor of M = Y'^H GB Y'.  Bm <- GB (masked), Am regions:
   c64* GY = Am;                    // n x mb (LDC)
@@ -482,7 +498,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
     Yp[i * LDC + j] = ev[j] * Yp[i * LDC + j];
   }
   __syncthreads();
-  chol_masked(Bm, mb, pact, d0, 1e-10, nullptr, &brk);
+  chol_masked<LD>(Bm, mb, pact, d0, 1e-10, nullptr, &brk);
   // Y''^H = L_M^{-1} Y'^H (mb x n, leading dim LD) over the dead GY/T regions (below Yp)
   c64* YH = Am;
   __syncthreads();
@@ -491,7 +507,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
     YH[i * LD + c] = conj(Yp[c * LDC + i]);
   }
   __syncthreads();
-  trsm_lower(Bm, mb, YH, LD, n);
+  trsm_lower<LD>(Bm, mb, YH, LD, n);
   c64* out = Cu + (size_t)b * n * 2 * mb;
   for (int e = threadIdx.x; e < n * 2 * mb; e += blockDim.x) {
     const int i = e / (2 * mb), j = e % (2 * mb);
@@ -532,20 +548,34 @@ __global__ __launch_bounds__(RR_THREADS) void k_small_rr(const c64* __restrict__
 int small_rr(const c64* GA, const c64* GB, int mb, int nb, const int* xmask, const int* wmask, const int* pmask,
              double* theta, c64* Cu, int* pvalid, c64* Lsave, int* flags, const int* kskip, c64* gapp_out,
              hipStream_t s, const double* res) {
-  if (3 * mb > RR_NMAX || mb > 21) {
+  if (3 * mb > RR_NMAX_WIDE || mb > 32) {
     set_error("block size too large");
     return KC_ERR_INVALID_ARG;
   }
+  if (3 * mb > RR_NMAX || mb > 21) {
+    // wide blocks: the matrices do not fit in LDS and live in the Lsave workspace (L2-resident)
+    k_small_rr<RR_NMAX_WIDE, true><<<nb, RR_THREADS, 0, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave,
+                                                             flags, kskip, gapp_out, res);
+    KC_LAUNCHED();
+    return KC_OK;
+  }
+  constexpr int LD = RR_NMAX;
   const size_t shm = (size_t)(2 * LD * LD + LD * 24) * sizeof(c64);
   static bool attr = false;
   if (!attr) {
-    KC_HIP(hipFuncSetAttribute((const void*)k_small_rr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    KC_HIP(hipFuncSetAttribute((const void*)k_small_rr<RR_NMAX, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm));
     attr = true;
   }
-  k_small_rr<<<nb, RR_THREADS, shm, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave, flags, kskip,
-                                  gapp_out, res);
+  k_small_rr<RR_NMAX, false><<<nb, RR_THREADS, shm, s>>>(GA, GB, mb, xmask, wmask, pmask, theta, Cu, pvalid, Lsave,
+                                                         flags, kskip, gapp_out, res);
   KC_LAUNCHED();
   return KC_OK;
+}
+
+size_t small_rr_ws_bytes(int mb) {
+  const bool wide = 3 * mb > RR_NMAX || mb > 21;
+  return (wide ? rr_ws_elems<RR_NMAX_WIDE, true>() : rr_ws_elems<RR_NMAX, false>()) * sizeof(c64);
 }
 
 }  // namespace kc

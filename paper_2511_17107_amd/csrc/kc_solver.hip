@@ -159,7 +159,7 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(w->GA.ensure((size_t)nb * nc * nc * sizeof(c64)));
   KC_TRY(w->GB.ensure((size_t)nb * nc * nc * sizeof(c64)));
   KC_TRY(w->Cu.ensure((size_t)nb * nc * 2 * mb * sizeof(c64)));
-  KC_TRY(w->Lsave.ensure((size_t)nb * RR_NMAX * RR_NMAX * sizeof(c64)));
+  KC_TRY(w->Lsave.ensure((size_t)nb * small_rr_ws_bytes(mb)));
   KC_TRY(w->GApp.ensure((size_t)nb * mb * mb * sizeof(c64)));
   KC_TRY(w->theta.ensure((size_t)nb * mb * sizeof(double)));
   KC_TRY(w->res.ensure((size_t)nb * mb * sizeof(double)));
@@ -592,7 +592,7 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   KC_ARG(eig_host != nullptr && res_host != nullptr, "NULL eig or res output");
   KC_ARG(op->nk > 0 && nk >= 1 && ik0 >= 0 && ik0 + nk <= op->nk, "k-point range");
   const kc_solve_opts& o = *opts;
-  KC_ARG(o.m >= 1 && o.guard >= 0 && o.m + o.guard <= 21, "m + guard must be in [1, 21]");
+  KC_ARG(o.m >= 1 && o.guard >= 0 && o.m + o.guard <= 32, "m + guard must be in [1, 32]");
   KC_ARG((size_t)3 * (o.m + o.guard) <= 3 * (size_t)op->N * op->N * op->N, "block larger than the space");
   KC_ARG(o.tol > 0.0 && o.maxit >= 1 && o.batch_k >= 1, "tol > 0, maxit >= 1, batch_k >= 1");
   KC_ARG(o.prec == KC_PREC_FP64 || o.prec == KC_PREC_FP32, "prec");
