@@ -408,35 +408,85 @@ constexpr bool plane_ok() {
   return sizeof(T) == 4 && plane_lds_bytes<N, T>() <= 160 * 1024;
 }
 
+// Persistent: workgroup b takes the planes b, b + gridDim.x, ... (planes of inactive vectors
+// skipped) and loads the next plane into registers while it transforms the current one in LDS
+// (the loads stay in flight across the LDS barriers), since a 128 x 128 plane leaves room for
+// one workgroup per CU and nothing else would overlap its memory traffic.  The next plane's
+// field is loaded after the current one has been multiplied (one register set for it).
 template <int N, typename T>
 __global__ __launch_bounds__(NT_PLANE) void k_yz_field(cpx<T>* __restrict__ buf, const float* __restrict__ fieldt,
                                                        const cpx<T>* __restrict__ gtw,
-                                                       const int* __restrict__ active, int vpk, int fks) {
+                                                       const int* __restrict__ active, int vpk, int fks,
+                                                       unsigned nplanes) {
   constexpr int PL = N + 1;
   constexpr size_t N3 = (size_t)N * N * N;
   constexpr T inv = T(1) / T(N3);
+  constexpr int PER = (N * N + NT_PLANE - 1) / NT_PLANE;  // plane entries per thread
   extern __shared__ __align__(16) unsigned char plane_smem[];
   cpx<T>* lds = reinterpret_cast<cpx<T>*>(plane_smem);
   cpx<T>* tw = lds + N * PL;
-  const unsigned b = blockIdx.x;
-  const int x = b % N, c = (b / N) % 3;
-  const size_t vec = b / (3 * N);
-  if (active && !active[vec]) return;
-  load_twiddles<N>(tw, gtw);
-  cpx<T>* pl = buf + vec * 3 * N3 + (size_t)c * N3 + (size_t)x * N * N;  // [z][y]
-  const float* f = fieldt + ((vec / vpk) * fks * 3 + c) * N3 + (size_t)x * N * N;
-  for (int t = threadIdx.x; t < N * N; t += NT_PLANE) lds[(t / N) * PL + t % N] = pl[t];
-  __syncthreads();
-  fft_2d<N, N, 1, PL, NT_PLANE, +1, T>(lds, tw);  // along y: pencils = rows z
-  fft_2d<N, N, PL, 1, NT_PLANE, +1, T>(lds, tw);  // along z: pencils = columns y
-  for (int t = threadIdx.x; t < N * N; t += NT_PLANE) {
-    const int a = (t / N) * PL + t % N;
-    lds[a] = ((T)f[t] * inv) * lds[a];
+  load_twiddles<N>(tw, gtw);  // visible after the first barrier below
+  // plane p: x = p % N of component c = (p / N) % 3 of vector p / 3N, [z][y]
+  auto next_from = [&](unsigned p) {
+    while (p < nplanes && active && !active[p / (3 * N)]) p += gridDim.x;
+    return p;
+  };
+  auto plane = [&](unsigned p) { return buf + (size_t)p * N * N; };
+  auto field = [&](unsigned p) {
+    const size_t vec = p / (3 * N);
+    return fieldt + (size_t)(vec / vpk) * fks * 3 * N3 + (size_t)(p % (3 * N)) * N * N;
+  };
+  cpx<T> nv[PER];
+  float nf[PER];
+  auto load_plane_regs = [&](unsigned p) {
+    const cpx<T>* pl = plane(p);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = threadIdx.x + i * NT_PLANE;
+      if ((N * N) % NT_PLANE == 0 || t < N * N) nv[i] = pl[t];
+    }
+  };
+  auto load_field_regs = [&](unsigned p) {
+    const float* f = field(p);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = threadIdx.x + i * NT_PLANE;
+      if ((N * N) % NT_PLANE == 0 || t < N * N) nf[i] = f[t];
+    }
+  };
+  unsigned p = next_from(blockIdx.x);
+  if (p < nplanes) {
+    load_plane_regs(p);
+    load_field_regs(p);
   }
-  __syncthreads();
-  fft_2d<N, N, PL, 1, NT_PLANE, -1, T>(lds, tw);
-  fft_2d<N, N, 1, PL, NT_PLANE, -1, T>(lds, tw);
-  for (int t = threadIdx.x; t < N * N; t += NT_PLANE) pl[t] = lds[(t / N) * PL + t % N];
+  while (p < nplanes) {
+    const unsigned pn = next_from(p + gridDim.x);
+    __syncthreads();  // the previous plane's last LDS reads are done
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = threadIdx.x + i * NT_PLANE;
+      if ((N * N) % NT_PLANE == 0 || t < N * N) lds[(t / N) * PL + t % N] = nv[i];
+    }
+    if (pn < nplanes) load_plane_regs(pn);
+    __syncthreads();
+    fft_2d<N, N, 1, PL, NT_PLANE, +1, T>(lds, tw);  // along y: pencils = rows z
+    fft_2d<N, N, PL, 1, NT_PLANE, +1, T>(lds, tw);  // along z: pencils = columns y
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = threadIdx.x + i * NT_PLANE;
+      if ((N * N) % NT_PLANE == 0 || t < N * N) {
+        const int a = (t / N) * PL + t % N;
+        lds[a] = ((T)nf[i] * inv) * lds[a];
+      }
+    }
+    if (pn < nplanes) load_field_regs(pn);
+    __syncthreads();
+    fft_2d<N, N, PL, 1, NT_PLANE, -1, T>(lds, tw);
+    fft_2d<N, N, 1, PL, NT_PLANE, -1, T>(lds, tw);
+    cpx<T>* pl = plane(p);
+    for (int t = threadIdx.x; t < N * N; t += NT_PLANE) pl[t] = lds[(t / N) * PL + t % N];
+    p = pn;
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -759,9 +809,13 @@ static void launch_x2(kc_op* op, int pass, int nvec, const cpx<T>* A, const c64*
 template <int N, typename T>
 static void launch_yz(int nvec, cpx<T>* A, const float* fieldt, int vpk, int fks, const cpx<T>* tw, const int* act,
                       hipStream_t s) {
-  if constexpr (plane_ok<N, T>())
-    k_yz_field<N, T><<<nblk((size_t)nvec * 3 * N), NT_PLANE, plane_lds_bytes<N, T>(), s>>>(A, fieldt, tw, act, vpk,
-                                                                                            fks);
+  if constexpr (plane_ok<N, T>()) {
+    // one persistent workgroup per plane slot: CUs x the workgroups of 1024 threads that fit (LDS)
+    const unsigned np = (unsigned)nvec * 3 * N;
+    const unsigned per_cu = plane_lds_bytes<N, T>() > 80 * 1024 ? 1 : 2;
+    const unsigned g = std::min<unsigned>(np, 256 * per_cu);
+    k_yz_field<N, T><<<g, NT_PLANE, plane_lds_bytes<N, T>(), s>>>(A, fieldt, tw, act, vpk, fks, np);
+  }
 }
 
 template <int N, int DIR, typename T>
