@@ -421,7 +421,8 @@ int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void*
  * kc_pcg: c_j = Op^{-1} r_j by conjugate gradients preconditioned with T_E of the classical field
  *   E_c = 1/(eps^-1)_cc, FP64 operator applications, until every recurrence residual satisfies
  *   |r_j - Op c_j| <= tol |r_j|.  r and c must not overlap; c is overwritten.  *iters (host, may
- *   be NULL) receives the iterations done.  1 <= nvec <= 256, tol > 0, maxit >= 1.  Returns
+ *   be NULL) receives the iterations done; a zero r_j gives c_j = 0.  1 <= nvec <= 256, tol > 0,
+ *   maxit >= 1.  Returns
  *   KC_ERR_NO_CONVERGENCE after maxit iterations (c then holds the last iterate).  Op must be
  *   nonsingular: k = 0 is rejected only by the iteration failing to converge.
  */
@@ -447,7 +448,8 @@ int kc_perturbed_residuals(kc_op* op, int ik, int m, const void* X, const void* 
  *   *loss (host) receives the mean.  With gout != NULL (device float32 [N^3][16], the layout of
  *   the network's output y), also writes scale * d(mean)/dy: channels 0-2 through
  *   E = E0 exp(clamp(y, -3, 3)) (zero where the clamp is active), the other channels zero; the
- *   optimal alpha is held fixed (it is stationary).  1 <= nvec <= 256.
+ *   optimal alpha is held fixed (it is stationary).  1 <= nvec <= 256.  KC_ERR_INVALID_ARG when a
+ *   c_j or T_E r_j is zero (the misfit is undefined).
  */
 int kc_net_loss_grad(kc_op* op, int ik, int nvec, const void* r, const void* c, int kind, double scale, double* loss,
                      float* gout, void* stream);

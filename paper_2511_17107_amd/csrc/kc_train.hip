@@ -72,12 +72,13 @@ __global__ void k_sum_parts(const double* __restrict__ part, int nblk, int nv, d
   out[j] = s;
 }
 
-// c_j += (rz_j / pAp_j) p_j,  res_j -= (rz_j / pAp_j) Ap_j
+// c_j += (rz_j / pAp_j) p_j,  res_j -= (rz_j / pAp_j) Ap_j  (a vector whose direction vanished,
+// e.g. a zero right-hand side, stays where it is)
 __global__ __launch_bounds__(TT) void k_cg_step(c64* __restrict__ c, c64* __restrict__ res, const c64* __restrict__ p,
                                                 const c64* __restrict__ Ap, const double* __restrict__ rz,
                                                 const double* __restrict__ pAp, size_t n) {
   const size_t j = blockIdx.y;
-  const double al = rz[j] / pAp[j];
+  const double al = pAp[j] > 0.0 ? rz[j] / pAp[j] : 0.0;
   for (size_t t = (size_t)blockIdx.x * TT + threadIdx.x; t < n; t += (size_t)gridDim.x * TT) {
     const size_t q = j * n + t;
     c[q] = c[q] + al * p[q];
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(TT) void k_cg_dir(c64* __restrict__ p, const c64* _
                                                const double* __restrict__ rz_new, const double* __restrict__ rz,
                                                size_t n) {
   const size_t j = blockIdx.y;
-  const double be = rz_new[j] / rz[j];
+  const double be = rz[j] != 0.0 ? rz_new[j] / rz[j] : 0.0;
   for (size_t t = (size_t)blockIdx.x * TT + threadIdx.x; t < n; t += (size_t)gridDim.x * TT) {
     const size_t q = j * n + t;
     p[q] = z[q] + be * p[q];
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(TT) void k_perturb(c64* __restrict__ x, const c64* 
                                                 const c64* __restrict__ e, const double* __restrict__ amp,
                                                 const double* __restrict__ en2, size_t n) {
   const size_t j = blockIdx.y;
-  const double s = amp[j] / sqrt(en2[j]);
+  const double s = en2[j] > 0.0 ? amp[j] / sqrt(en2[j]) : 0.0;  // noise inside span(X): x = X
   for (size_t t = (size_t)blockIdx.x * TT + threadIdx.x; t < n; t += (size_t)gridDim.x * TT) {
     const size_t q = j * n + t;
     x[q] = X[q] + s * e[q];
@@ -241,7 +242,7 @@ int kc_pcg(kc_op* op, int ik, int nvec, const void* r_, void* c_, double tol, in
     KC_TRY(dots(res, res, nvec, n, part, rn, s));
     KC_TRY(to_host(rh, rn, nvec, s));
     conv = true;
-    for (int j = 0; j < nvec; ++j) conv = conv && std::sqrt(rh[j]) <= tol * std::sqrt(r0[j]);
+    for (int j = 0; j < nvec; ++j) conv = conv && (r0[j] == 0.0 || std::sqrt(rh[j]) <= tol * std::sqrt(r0[j]));
     if (conv) break;
     KC_TRY(apply_tp(op, ik, nvec, vm, vm, res, z, op->efield.as<float>(), 0, KC_PREC_FP64, s));
     KC_TRY(dots(res, z, nvec, n, part, rz2, s));
@@ -354,6 +355,10 @@ int kc_net_loss_grad(kc_op* op, int ik, int nvec, const void* r_, const void* c_
     KC_TRY(to_host(h1, d1, nvec, s));
     KC_TRY(to_host(h2, d2, nvec, s));
     for (int j = 0; j < nvec; ++j) {
+      if (!(h0[j] > 0.0 && h2[j] > 0.0)) {
+        set_error("kc_net_loss_grad: a residual or its preconditioned direction has no energy");
+        return KC_ERR_INVALID_ARG;
+      }
       sum += 1.0 - h1[j] * h1[j] / (h2[j] * h0[j]);
       ha[j] = h1[j] / h2[j];
       hw[j] = 2.0 * ha[j] / (h0[j] * nvec);
@@ -372,6 +377,10 @@ int kc_net_loss_grad(kc_op* op, int ik, int nvec, const void* r_, const void* c_
     KC_TRY(to_host(h1, d1, nvec, s));
     KC_TRY(to_host(h2, d2, nvec, s));
     for (int j = 0; j < nvec; ++j) {
+      if (!(h0[j] > 0.0 && h2[j] > 0.0)) {
+        set_error("kc_net_loss_grad: a target or a preconditioned residual is zero");
+        return KC_ERR_INVALID_ARG;
+      }
       ha[j] = h1[j] / h2[j];
       hw[j] = 2.0 * ha[j] / (h0[j] * nvec);
     }

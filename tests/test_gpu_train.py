@@ -43,6 +43,18 @@ def test_pcg_matches_direct_solve():
     assert rel_err(to_host(c), ref) < 1e-9
 
 
+def test_pcg_zero_right_hand_side():
+    """A zero r_j gives c_j = 0 and does not hold back the others."""
+    wl, op, g, Op = _setup()
+    r = W.random_block(16, 3, N)
+    r[1] = 0.0
+    c, its, ok = op.pcg(to_dev(r), ik=0, tol=1e-11, maxit=3000)
+    c = to_host(c)
+    assert ok and np.all(c[1] == 0.0)
+    ref = train.solve(Op[0], r, N)
+    assert rel_err(c, ref) < 1e-8
+
+
 def test_pcg_reports_no_convergence():
     wl, op, g, Op = _setup()
     r = W.random_block(12, 2, N)
