@@ -938,11 +938,15 @@ unsigned update_grid_x(size_t n, int nb) {
 }
 
 // dynamic LDS of k_update_res: C_b and the parked X values
-static size_t update_res_lds(int mb) {
-  const int xs = (mb + 3) / 4;
-  const size_t nmax = 3 * mb > RR_NMAX ? wide_rows(3 * mb) : RR_NMAX;
-  return (nmax * (((xs + 1) / 2) * 16) + (size_t)4 * xs * 64) * sizeof(c64);
+static size_t update_res_lds_n(int xs, int nmax) {
+  return ((size_t)nmax * (((xs + 1) / 2) * 16) + (size_t)4 * xs * 64) * sizeof(c64);
 }
+// rows of C staged for mb columns: 60 at 17..20 (the bench's 16 + 4), RR_NMAX up to 21, then
+// the wide rows
+static int update_res_rows(int mb) {
+  return 3 * mb > RR_NMAX ? wide_rows(3 * mb) : (mb >= 17 && mb <= 20) ? 60 : RR_NMAX;
+}
+static size_t update_res_lds(int mb) { return update_res_lds_n((mb + 3) / 4, update_res_rows(mb)); }
 
 int update_res_prepare() {
   static bool done = false;
@@ -955,7 +959,12 @@ int update_res_prepare() {
                        (const void*)k_update_res<5, true>,  (const void*)k_update_res<6, true>};
   for (int i = 0; i < 12; ++i)
     KC_HIP(hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)update_res_lds(4 * (i % 6 + 1))));
+                               (int)update_res_lds_n(i % 6 + 1, RR_NMAX)));
+  // 17..20 columns per block: C staged at 60 rows (no k-step of padding only)
+  KC_HIP(hipFuncSetAttribute((const void*)k_update_res<5, false, 60>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)update_res_lds(20)));
+  KC_HIP(hipFuncSetAttribute((const void*)k_update_res<5, true, 60>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)update_res_lds(20)));
   // the wide path: 22 <= mb <= 32 (xs 6..8 with 72, 84, 96 staged rows of C), and the plain
   // update with up to 96 input and 64 output columns
   const void* kw[6] = {(const void*)k_update_res<6, false, 72>, (const void*)k_update_res<7, false, 84>,
@@ -1013,7 +1022,7 @@ int update_res(c64* S, c64* AS, int kstride, int mb, const c64* C, size_t n, int
     case 2: KC_UPDRES(2); break;
     case 3: KC_UPDRES(3); break;
     case 4: KC_UPDRES(4); break;
-    case 5: KC_UPDRES(5); break;
+    case 5: KC_UPDRES_W(5, 60); break;  // mb 17..20
     default: KC_UPDRES(6); break;
   }
 #undef KC_UPDRES
