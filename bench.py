@@ -363,15 +363,20 @@ def main():
     if a.warm_start:  # converged fields of the previous step (position j of batch s-1 is point s-1+jP)
         xbuf = [torch.empty((a.kpb, a.m, 3, a.N ** 3), dtype=torch.complex128, device=dev) for _ in range(2)]
 
-    def run_step(step, x_init=None, x_out=None):
+    def run_step(step, x_init=None, x_out=None, tag="step"):
         ik0 = (step % nsteps_path) * a.kpb
         eig, res, its, st = op.solve(a.m, ik0=ik0, nk=a.kpb, tol=a.tol, maxit=a.maxit, prec=prec,
                                      switch_tol=a.switch_tol, batch_k=a.kpb, guard=a.guard,
                                      verbose=a.verbose, check=True, precond=pc, X_out=x_out, x_init=x_init)
+        # one progress line per solved batch (stderr; the result line is the only stdout line)
+        print("%s %d: k-points %d..%d, iterations %d..%d, max Res %.2e" % (tag, step, ik0, ik0 + a.kpb - 1,
+                                                                           int(its.min()), int(its.max()),
+                                                                           float(res.max())),
+              file=sys.stderr, flush=True)
         return ik0, eig, res, its, st, op.last_solve_stats()
 
     for w in range(a.warmup):
-        run_step(nsteps_path - 1 - w)
+        run_step(nsteps_path - 1 - w, tag="warm-up")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
