@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--precond", choices=["diag", "transverse"], default="transverse",
                     help="LOBPCG preconditioner: diagonal-block K_P^-1 or transverse-projection T_E")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--start", choices=["plane_waves", "random"], default="plane_waves",
+                    help="start block of every solve: seeded random (preconditioned), or the k-point's lowest "
+                         "transverse plane waves")
     ap.add_argument("--warm-start", action="store_true",
                     help="sweep the path: each timed step after the first starts its k-points from the "
                          "converged fields of the previous step's (their neighbours on the path)")
@@ -367,7 +370,8 @@ def main():
         ik0 = (step % nsteps_path) * a.kpb
         eig, res, its, st = op.solve(a.m, ik0=ik0, nk=a.kpb, tol=a.tol, maxit=a.maxit, prec=prec,
                                      switch_tol=a.switch_tol, batch_k=a.kpb, guard=a.guard,
-                                     verbose=a.verbose, check=True, precond=pc, X_out=x_out, x_init=x_init)
+                                     verbose=a.verbose, check=True, precond=pc, X_out=x_out, x_init=x_init,
+                                     start=a.start)
         # one progress line per solved batch (stderr; the result line is the only stdout line)
         print("%s %d: k-points %d..%d, iterations %d..%d, max Res %.2e" % (tag, step, ik0, ik0 + a.kpb - 1,
                                                                            int(its.min()), int(its.max()),
@@ -450,7 +454,8 @@ def main():
                                "%d k-points/step of the 60-point G-X-M-G-R path" % (a.guard, a.kpb),
                    "N": a.N, "bands": a.m, "kpoints_per_step": a.kpb, "tol": a.tol,
                    "precision": a.prec, "preconditioner": a.precond,
-                   "start": "previous step's fields" if a.warm_start else "seeded random"},
+                   "start": ("previous step's fields" if a.warm_start else
+                             "lowest transverse plane waves" if a.start == "plane_waves" else "seeded random")},
         "converged": converged,
         "max_residual": maxres,
         "iterations": iters,

@@ -312,10 +312,19 @@ typedef struct kc_solve_opts {
                       /* neighbouring k-points of a path, kc_solve's X_out); they enter the */
                       /* first search directions next to the random guard columns.  At k = 0 */
                       /* their constant (DC) part is removed (Prop 2.5 (1)).  Not modified. */
+  int start;          /* without x_init: KC_START_RANDOM (K_P^{-1} applied to a seeded random */
+                      /* block) or KC_START_PLANE_WAVES (up to m of the first directions are */
+                      /* the lowest transverse plane waves of the k-point: the frequencies q */
+                      /* with the smallest |K(q)|^2, s = 0 excluded, two polarizations      */
+                      /* orthogonal to conj(K(q)) each, whole groups of equal |K(q)|^2 only;  */
+                      /* the modes of a homogeneous medium, eq (2.30) with Lemma 2.4; the   */
+                      /* other columns as KC_START_RANDOM)                                   */
 } kc_solve_opts;
 
+enum { KC_START_RANDOM = 0, KC_START_PLANE_WAVES = 1 };
+
 /* Fill opts with defaults (m = 10, guard = 0, tol = 1e-8, maxit = 500, FP64, batch_k = 1,
- * diagonal-block preconditioner, graph = 1). */
+ * diagonal-block preconditioner, graph = 1, random start). */
 void kc_solve_opts_default(kc_solve_opts* opts);
 
 /*

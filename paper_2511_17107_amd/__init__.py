@@ -11,6 +11,8 @@ from ._binding import (  # noqa: F401
     KC_EPS_DIAGONAL,
     KC_EPS_TRIVIAL,
     KC_ERR_NO_CONVERGENCE,
+    KC_START_PLANE_WAVES,
+    KC_START_RANDOM,
     KC_FLAG_HPD_UNPROVEN,
     KC_KFLAG_K_OUTSIDE,
     KC_KFLAG_SPURIOUS_RISK,

@@ -13,6 +13,7 @@ lib_path = os.path.join(HERE, "libkcpc.so")
 KC_EPS_DIAGONAL, KC_EPS_TRIVIAL, KC_EPS_CROSSDOF = 0, 1, 2
 KC_PREC_FP64, KC_PREC_FP32 = 0, 1
 KC_OK, KC_ERR_NO_CONVERGENCE = 0, 6
+KC_START_RANDOM, KC_START_PLANE_WAVES = 0, 1
 KC_PRECOND_DIAG, KC_PRECOND_LEARNED, KC_PRECOND_TRANSVERSE = 0, 1, 2
 KC_FLAG_HPD_UNPROVEN = 1
 KC_KFLAG_K_OUTSIDE, KC_KFLAG_SPURIOUS_RISK = 1, 2
@@ -70,6 +71,7 @@ class KcSolveOpts(ctypes.Structure):
         ("precond", ctypes.c_int),
         ("graph", ctypes.c_int),
         ("x_init", ctypes.c_void_p),
+        ("start", ctypes.c_int),
     ]
 
 
@@ -490,10 +492,10 @@ class Op:
     def solve(self, m: int, ik0: int = 0, nk: Optional[int] = None, tol: float = 1e-8, maxit: int = 500,
               prec: int = KC_PREC_FP64, switch_tol: float = 1e-3, batch_k: int = 1, guard: int = 0,
               seed: int = 1234, X_out=None, verbose: int = 0, stream=None, check: bool = True,
-              precond: int = KC_PRECOND_DIAG, graph: bool = True, x_init=None):
+              precond: int = KC_PRECOND_DIAG, graph: bool = True, x_init=None, start: str = "random"):
         """Smallest positive eigenvalues for k-points ik0 .. ik0+nk-1 (x_init: optional start
-        vectors, complex128 (nk, m, 3, N^3) on the device).  Returns
-        (eig (nk, m), res (nk, m), iters (nk,), status)."""
+        vectors, complex128 (nk, m, 3, N^3) on the device; otherwise start = "random" or
+        "plane_waves").  Returns (eig (nk, m), res (nk, m), iters (nk,), status)."""
         nk = self.nk - ik0 if nk is None else int(nk)
         o = KcSolveOpts()
         lib().kc_solve_opts_default(ctypes.byref(o))
@@ -501,6 +503,9 @@ class Op:
         o.switch_tol, o.batch_k, o.seed, o.verbose = float(switch_tol), int(batch_k), int(seed), int(verbose)
         o.precond = int(precond)
         o.graph = 1 if graph else 0
+        if start not in ("random", "plane_waves"):
+            raise ValueError("start: 'random' or 'plane_waves'")
+        o.start = KC_START_PLANE_WAVES if start == "plane_waves" else KC_START_RANDOM
         if x_init is not None:
             if tuple(x_init.shape[:2]) != (nk, m):
                 raise ValueError("x_init must hold (nk, m) start vectors")

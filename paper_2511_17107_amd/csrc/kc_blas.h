@@ -61,6 +61,10 @@ int deflate_dc_long(c64* S, int kstride, int col0, int ncol, int nb, const c64* 
 
 int random_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, uint64_t seed, const int* kglobal,
                  hipStream_t s);
+// columns [col0, col0 + ncol) of each k-point's group: the plane waves q (device int [nb][ncol],
+// flattened frequency; q < 0 leaves the column) with polarizations pol (device c64 [nb][ncol][3])
+int plane_wave_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, const int* q, const c64* pol,
+                     hipStream_t s);
 
 // Small dense steps (one workgroup per k-point), see kc_small.hip.
 constexpr int RR_NMAX = 64;       // 3 * block size of the LDS-resident kernels (block size <= 21)

@@ -757,6 +757,21 @@ __global__ void k_random_block(c64* S, size_t n, int kstride, int col0, int ncol
   }
 }
 
+// column j of k-point b: the plane wave with frequency q[b][j] (flattened, x fastest) and
+// polarization pol[b][j][3], zero elsewhere; q < 0 leaves the column as it is
+__global__ void k_plane_waves(c64* S, size_t n, size_t N3, int kstride, int col0, int ncol, const int* __restrict__ q,
+                              const c64* __restrict__ pol) {
+  const int b = blockIdx.z, j = blockIdx.y;
+  c64* v = S + ((size_t)b * kstride + col0 + j) * n;
+  if (q[b * ncol + j] < 0) return;
+  const size_t qq = (size_t)q[b * ncol + j];
+  const c64* pp = pol + ((size_t)b * ncol + j) * 3;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t c = t / N3, p = t - c * N3;
+    v[t] = (p == qq) ? pp[c] : mk(0.0, 0.0);
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // host launchers
 // ------------------------------------------------------------------------------------
@@ -1047,6 +1062,14 @@ int resid_precond(const c64* S, const c64* AS, c64* W, const double* theta, cons
   KC_LAUNCHED();
   const int nv = nb * mb;
   k_resid_reduce<<<(nv + 255) / 256, 256, 0, s>>>(part.as<double>(), nblk, nv, res, xnorm2, rnorm2);
+  KC_LAUNCHED();
+  return KC_OK;
+}
+
+int plane_wave_block(c64* S, size_t n, int kstride, int col0, int ncol, int nb, const int* q, const c64* pol,
+                     hipStream_t s) {
+  const unsigned gx = (unsigned)std::min<size_t>((n + 255) / 256, 1024);
+  k_plane_waves<<<dim3(gx, ncol, nb), 256, 0, s>>>(S, n, n / 3, kstride, col0, ncol, q, pol);
   KC_LAUNCHED();
   return KC_OK;
 }

@@ -365,6 +365,7 @@ int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, 
         st = KC_ERR_HIP;
       }
     }
+    op->lam1_host = l64;
     op->skew.l1d = op->lam1.as<c64>();
     op->skew.l1f = (const c32*)((const char*)op->lam1.p + N * sizeof(c64));
     for (int i = 0; i < 9; ++i) op->skew.c[i] = cmat[i];
@@ -502,6 +503,7 @@ int kc_set_kpoints(kc_op* op, int nk, const double* k_host, const double* gamma_
   KC_TRY(upload(op->kdev, std::vector<double>(k_host, k_host + 3 * (size_t)nk)));
   KC_TRY(upload(op->ktab64, kt));
   KC_TRY(upload(op->ktab32, kf));
+  op->ktab_host = kt;
   KC_TRY(upload(op->gamma_d, gam));
   // The solver's preconditioners (K_P^{-1}, T_E) take s = |K(p)|^2 no smaller than this floor:
   // near k = 0 the DC frequency has s = |k|^2 and a gain 1/|k|^2 that makes every new search

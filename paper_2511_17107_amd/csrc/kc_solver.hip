@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <vector>
 
@@ -29,6 +30,7 @@ namespace kc {
 
 struct SolverWork {
   DevBuf S, AS;
+  DevBuf pw;  // plane-wave start: frequencies (int [nb][mb]) then polarizations (c64 [nb][mb][3])
   DevBuf part_gram, part_res, part_upd;
   DevBuf GA, GB, Cu, Lsave, GApp;
   DevBuf theta, res, xn2;
@@ -37,7 +39,7 @@ struct SolverWork {
   hipStream_t gstream = nullptr;  // private stream of graph-captured solves (default priority)
   void bind_allocator(const Allocator* al) {
     DevBuf* bufs[] = {&S, &AS, &part_gram, &part_res, &part_upd, &GA, &GB, &Cu, &Lsave, &GApp, &theta, &res, &xn2,
-                      &R, &tmask, &ints};
+                      &R, &tmask, &ints, &pw};
     for (DevBuf* b : bufs) b->al = al;
   }
   ~SolverWork() {
@@ -64,6 +66,96 @@ struct Batch {
   const float* field = nullptr;  // E of T_E: one per k-point (fks = 1) or shared (fks = 0)
   int fks = 0;
 };
+
+// The lowest transverse plane waves of k-point ik (the modes of a homogeneous medium): the
+// frequencies q with the smallest s(q) = |K(q)|^2 (s = 0, the constant fields at k = 0,
+// excluded), with K(q) from the symbol tables (and the lattice terms of eq (2.12)), and for each
+// two orthonormal polarizations orthogonal to v = conj(K(q)) (K_A K_A^H + K_B = s I with
+// K_B = v v^H, Lemma 2.4 (1)).  Only whole groups of equal s enter (a group cut in two would pick
+// an arbitrary part of a degenerate eigenspace), at most ncol columns; q_out [ncol] and
+// pol_out [ncol][3], q = -1 for the columns left to the random start.  The frequencies searched
+// are those within 4 of 0 on each axis (all of them below N = 10).
+void plane_wave_start(const kc_op* op, int ik, int ncol, int* q_out, c64* pol_out) {
+  const int N = op->N;
+  std::vector<int> ax;
+  if (N < 10) {
+    for (int q = 0; q < N; ++q) ax.push_back(q);
+  } else {
+    for (int q = 0; q <= 4; ++q) ax.push_back(q);
+    for (int q = N - 4; q < N; ++q) ax.push_back(q);
+  }
+  struct Cand {
+    double s;
+    int q;
+    std::complex<double> K[3];
+  };
+  std::vector<Cand> cand;
+  const c64* kt = op->ktab_host.data() + (size_t)ik * 3 * N;
+  const bool skew = op->skew.l1d != nullptr && !op->lam1_host.empty();
+  double smax = 0.0;
+  for (int qz : ax)
+    for (int qy : ax)
+      for (int qx : ax) {
+        const int qq[3] = {qx, qy, qz};
+        Cand c;
+        c.s = 0.0;
+        c.q = qx + N * (qy + N * qz);
+        for (int i = 0; i < 3; ++i) {
+          std::complex<double> Ki(kt[i * N + qq[i]].re, kt[i * N + qq[i]].im);
+          if (skew)
+            for (int j = 0; j < 3; ++j)
+              Ki += op->skew.c[i * 3 + j] * std::complex<double>(op->lam1_host[qq[j]].re, op->lam1_host[qq[j]].im);
+          c.K[i] = Ki;
+          c.s += std::norm(Ki);
+        }
+        smax = std::max(smax, c.s);
+        cand.push_back(c);
+      }
+  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.s < b.s; });
+  // drop s = 0, then keep whole groups of equal s (two columns per frequency) within ncol
+  cand.erase(std::remove_if(cand.begin(), cand.end(), [&](const Cand& c) { return c.s <= 1e-14 * smax; }),
+             cand.end());
+  size_t keep = 0;
+  for (size_t g = 0; g < cand.size();) {
+    size_t e = g + 1;
+    while (e < cand.size() && cand[e].s - cand[g].s <= 1e-9 * cand[g].s) ++e;
+    if (2 * e > (size_t)ncol) break;
+    keep = e;
+    g = e;
+  }
+  cand.resize(keep);
+  int col = 0;
+  for (const Cand& c : cand) {
+    const double kn = std::sqrt(c.s);
+    std::complex<double> v[3];
+    for (int i = 0; i < 3; ++i) v[i] = std::conj(c.K[i]) / kn;
+    // the two axes where v is smallest: e_a, e_b minus their projections give the basis
+    int o[3] = {0, 1, 2};
+    std::sort(o, o + 3, [&](int x, int y) { return std::abs(v[x]) < std::abs(v[y]); });
+    std::complex<double> u[2][3];
+    for (int t = 0; t < 2; ++t) {
+      const int a = o[t];
+      for (int i = 0; i < 3; ++i) u[t][i] = (i == a ? 1.0 : 0.0) - v[i] * std::conj(v[a]);
+      if (t == 1) {
+        std::complex<double> d(0.0, 0.0);
+        for (int i = 0; i < 3; ++i) d += std::conj(u[0][i]) * u[1][i];
+        for (int i = 0; i < 3; ++i) u[1][i] -= d * u[0][i];
+      }
+      double nn = 0.0;
+      for (int i = 0; i < 3; ++i) nn += std::norm(u[t][i]);
+      nn = std::sqrt(nn);
+      for (int i = 0; i < 3; ++i) u[t][i] /= nn;
+    }
+    for (int t = 0; t < 2 && col < ncol; ++t, ++col) {
+      q_out[col] = c.q;
+      for (int i = 0; i < 3; ++i) pol_out[(size_t)col * 3 + i] = mk(u[t][i].real(), u[t][i].imag());
+    }
+  }
+  for (; col < ncol; ++col) {
+    q_out[col] = -1;
+    for (int i = 0; i < 3; ++i) pol_out[(size_t)col * 3 + i] = mk(0.0, 0.0);
+  }
+}
 
 int upload_ints(int* dst, const std::vector<int>& v, hipStream_t s) {
   KC_HIP(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s));
@@ -230,6 +322,22 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
   KC_TRY(random_block(B.S, n, nc, 0, mb, nb, o.seed, B.kglobal, s));
   KC_HIP(hipMemcpyAsync(w->theta.p, htheta.data(), htheta.size() * sizeof(double), hipMemcpyHostToDevice, s));
   KC_TRY(residuals(B, false));
+  if (!xinit && o.start == KC_START_PLANE_WAVES) {
+    // the lowest transverse plane waves of each k-point (whole degenerate groups, up to mb
+    // columns) replace the first new directions of the first step; the others stay random
+    std::vector<int> hq((size_t)nb * mb);
+    std::vector<c64> hpol((size_t)nb * mb * 3);
+    for (int b = 0; b < nb; ++b)
+      plane_wave_start(op, ik0 + b, mb, hq.data() + (size_t)b * mb, hpol.data() + (size_t)b * mb * 3);
+    const size_t qbytes = (hq.size() * sizeof(int) + 15) / 16 * 16;  // the polarizations start aligned
+    KC_TRY(w->pw.ensure(qbytes + hpol.size() * sizeof(c64)));
+    c64* dpol = reinterpret_cast<c64*>(w->pw.as<char>() + qbytes);
+    KC_HIP(hipMemcpyAsync(w->pw.p, hq.data(), hq.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    KC_HIP(hipMemcpyAsync(dpol, hpol.data(), hpol.size() * sizeof(c64), hipMemcpyHostToDevice, s));
+    KC_HIP(hipStreamSynchronize(s));
+    KC_TRY(plane_wave_block(B.S, n, nc, mb, mb, nb, w->pw.as<int>(), dpol, s));
+    KC_TRY(deflate_w(B));
+  }
   if (xinit) {
     // given start vectors take the first m new directions (the guard columns keep the
     // preconditioned random ones); at k = 0 their DC entries go, as K_P^{-1} would remove them
@@ -584,6 +692,7 @@ void kc_solve_opts_default(kc_solve_opts* o) {
   o->precond = KC_PRECOND_DIAG;
   o->graph = 1;
   o->x_init = nullptr;
+  o->start = KC_START_RANDOM;
 }
 
 int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_host, double* res_host,
@@ -593,6 +702,7 @@ int kc_solve(kc_op* op, int ik0, int nk, const kc_solve_opts* opts, double* eig_
   KC_ARG(op->nk > 0 && nk >= 1 && ik0 >= 0 && ik0 + nk <= op->nk, "k-point range");
   const kc_solve_opts& o = *opts;
   KC_ARG(o.m >= 1 && o.guard >= 0 && o.m + o.guard <= 32, "m + guard must be in [1, 32]");
+  KC_ARG(o.start == KC_START_RANDOM || o.start == KC_START_PLANE_WAVES, "start: KC_START_RANDOM or _PLANE_WAVES");
   KC_ARG((size_t)3 * (o.m + o.guard) <= 3 * (size_t)op->N * op->N * op->N, "block larger than the space");
   KC_ARG(o.tol > 0.0 && o.maxit >= 1 && o.batch_k >= 1, "tol > 0, maxit >= 1, batch_k >= 1");
   KC_ARG(o.prec == KC_PREC_FP64 || o.prec == KC_PREC_FP32, "prec");

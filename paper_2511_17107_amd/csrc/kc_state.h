@@ -81,6 +81,8 @@ struct kc_op {
   int nk = 0;
   std::vector<double> kvec, gamma;  // [nk][3], [nk]
   kc::DevBuf ktab64, ktab32;        // 1D symbols [nk][3][N]
+  std::vector<kc::c64> ktab_host;   // the same (FP64) on the host
+  std::vector<kc::c64> lam1_host;   // Lambda_1(q) [N] on the host (non-cubic lattices)
   kc::DevBuf gamma_d;               // double [nk]
   kc::DevBuf sfloor_d;              // double [nk] floor of |K|^2 in the solver's preconditioners
   kc::DevBuf dcl_d;                 // int [nk] 1: the solver deflates the DC longitudinal direction

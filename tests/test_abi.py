@@ -113,9 +113,10 @@ def test_solve_opts_defaults():
     assert (o.m, o.guard, o.maxit, o.prec, o.batch_k, o.precond, o.graph) == (10, 0, 500, B.KC_PREC_FP64, 1,
                                                                               B.KC_PRECOND_DIAG, 1)
     assert o.tol == 1e-8 and o.seed == 1234
-    assert o.x_init is None  # seeded random start
-    o.x_init = 0x1234  # the last field: a layout mismatch would shift it
-    assert ctypes.sizeof(o) == B.KcSolveOpts.x_init.offset + ctypes.sizeof(ctypes.c_void_p)
+    assert o.x_init is None and o.start == B.KC_START_RANDOM  # seeded random start
+    # the last field: a layout mismatch would shift it (the struct ends padded to 8 bytes)
+    assert B.KcSolveOpts.start.offset == B.KcSolveOpts.x_init.offset + ctypes.sizeof(ctypes.c_void_p)
+    assert ctypes.sizeof(o) == (B.KcSolveOpts.start.offset + ctypes.sizeof(ctypes.c_int) + 7) // 8 * 8
 
 
 def test_block_calls_check_arguments():

@@ -333,3 +333,25 @@ def test_near_gamma_kpoints_match_oracle(prec, pc):
     for i, c in enumerate(g["cases"]):
         ref = np.array(c["eigenvalues"])
         assert np.max(np.abs(eig[i] - ref) / ref) <= REL, (c["k"], eig[i], ref)
+
+
+@pytest.mark.parametrize("scheme", ["crossdof", "trivial"])
+def test_plane_wave_start_matches_oracle(scheme):
+    """The plane-wave start (the k-points' lowest transverse plane waves as the first search
+    directions) reaches the same eigenvalues as the oracle on the anisotropic sphere, k = 0
+    included."""
+    g = load("sphere16_aniso")
+    wl = W.sphere_anisotropic(N=16, nk=9, m=10)
+    cases = [c for c in g["cases"] if c["scheme"] == scheme]
+    kpts = np.array([c["k"] for c in cases])
+    op = kc.Op(16, kc.SCHEMES[scheme], wl.ids, wl.table)
+    op.set_kpoints(kpts)
+    note("plane-wave start", scheme)
+    eig, res, its, st = op.solve(10, tol=1e-8, batch_k=len(kpts), guard=3, precond=kc.KC_PRECOND_TRANSVERSE,
+                                 start="plane_waves")
+    assert st == 0 and res.max() <= TOL
+    for i, c in enumerate(cases):
+        ref = np.array(c["eigenvalues"])
+        assert np.max(np.abs(eig[i] - ref) / ref) <= REL, (c["k"], eig[i], ref)
+    e2, r2, i2, s2 = op.solve(10, tol=1e-8, batch_k=len(kpts), guard=3, precond=kc.KC_PRECOND_TRANSVERSE)
+    note("iterations plane waves", its.tolist(), "random", i2.tolist())
