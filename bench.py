@@ -368,15 +368,15 @@ def main():
 
     def run_step(step, x_init=None, x_out=None, tag="step"):
         ik0 = (step % nsteps_path) * a.kpb
+        ts = time.perf_counter()
         eig, res, its, st = op.solve(a.m, ik0=ik0, nk=a.kpb, tol=a.tol, maxit=a.maxit, prec=prec,
                                      switch_tol=a.switch_tol, batch_k=a.kpb, guard=a.guard,
                                      verbose=a.verbose, check=True, precond=pc, X_out=x_out, x_init=x_init,
                                      start=a.start)
         # one progress line per solved batch (stderr; the result line is the only stdout line)
-        print("%s %d: k-points %d..%d, iterations %d..%d, max Res %.2e" % (tag, step, ik0, ik0 + a.kpb - 1,
-                                                                           int(its.min()), int(its.max()),
-                                                                           float(res.max())),
-              file=sys.stderr, flush=True)
+        print("%s %d: k-points %d..%d, iterations %d..%d (sum %d), max Res %.2e, %.3f s"
+              % (tag, step, ik0, ik0 + a.kpb - 1, int(its.min()), int(its.max()), int(its.sum()),
+                 float(res.max()), time.perf_counter() - ts), file=sys.stderr, flush=True)
         return ik0, eig, res, its, st, op.last_solve_stats()
 
     for w in range(a.warmup):
