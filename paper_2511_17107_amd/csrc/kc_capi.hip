@@ -286,6 +286,7 @@ int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, 
   hipStream_t hs = (hipStream_t)stream;
   const size_t N3 = (size_t)N * N * N;
   std::vector<uint32_t> packed(N3);
+  std::vector<char> present(n_mat, 0);
   for (size_t p = 0; p < N3; ++p) {
     uint32_t w = 0;
     for (int s = 0; s < 4; ++s) {
@@ -294,6 +295,7 @@ int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, 
         set_error("material id " + std::to_string(id) + " >= n_mat");
         return KC_ERR_INVALID_ARG;
       }
+      present[id] = 1;
       w |= (uint32_t)id << (8 * s);
     }
     packed[p] = w;
@@ -309,6 +311,14 @@ int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, 
   op->bind_allocator();
   if (!gershgorin_hpd(N, eps_scheme, mat_ids_host, eps_inv_host)) op->flags |= KC_FLAG_HPD_UNPROVEN;
   op->eps_host.assign(eps_inv_host, eps_inv_host + (size_t)n_mat * 18);
+  op->epsinv_norm = 0.0;  // bounds |eps^-1| where the grid uses it (the scale of FP32 rounding)
+  for (int m = 0; m < n_mat; ++m)
+    if (present[m])
+      for (int i = 0; i < 3; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < 3; ++j) r += std::hypot(eps_inv_host[m * 18 + (i * 3 + j) * 2], eps_inv_host[m * 18 + (i * 3 + j) * 2 + 1]);
+        op->epsinv_norm = std::max(op->epsinv_norm, r);
+      }
   // permittivity entries scaled by 1/N^3 (normalisation of the two unnormalised DFTs)
   const double sc = 1.0 / (double)N3;
   std::vector<EpsEntry<double>> e64(n_mat);

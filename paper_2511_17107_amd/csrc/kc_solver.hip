@@ -227,6 +227,17 @@ int precond_tp(Batch& B) {
   return deflate_w(B);
 }
 
+// Rounding floor of an FP32 operator application on the k-points ik0 .. ik0+nb-1, as an absolute
+// residual of a unit vector: the FP32 transforms round at 2^-24 of the largest values they carry,
+// and the curl-(eps^-1)-curl part of Op reaches s_max |eps^-1| (largest s(p) of the k-points
+// times the largest absolute row sum of eps^-1 over the materials the grid uses, which bounds
+// its norm); the penalty term is formed in FP64 and adds nothing.
+double fp32_floor(const kc_op* op, int ik0, int nb) {
+  double smx = 0.0;
+  for (int b = 0; b < nb; ++b) smx = std::max(smx, op->smax[ik0 + b]);
+  return std::ldexp(smx * op->epsinv_norm, -24);
+}
+
 int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig, double* res_out, int* iters,
                 c64* Xout, const c64* xinit, hipStream_t s, bool* all_conv) {
   if (!op->solver) op->solver = new SolverWork();
@@ -418,6 +429,9 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
 
   int it = 0;
   double best_max = 1e300;
+  // within ten times the FP32 rounding floor, a rise of the largest residual ends the FP32 phase
+  const double rise_level = 10.0 * fp32_floor(op, ik0, nb);
+  double min_max = 1e300;
   int stall = 0;
   bool verify_pending = false;
   bool need_resid = true;
@@ -543,15 +557,19 @@ int solve_batch(kc_op* op, int ik0, int nb, const kc_solve_opts& o, double* eig,
       continue;
     }
     if (it >= o.maxit) break;
-    // mixed precision: leave the FP32 phase once the residuals reach switch_tol or stall
+    // mixed precision: leave the FP32 phase once the residuals reach switch_tol or stall, or at
+    // their first rise near the FP32 rounding floor (there the rounding in AW has begun to steer
+    // the Rayleigh-Ritz steps, and waiting for the stall count lets the residuals grow tenfold)
     if (mixed && prec == KC_PREC_FP32) {
+      const bool rise = min_max <= rise_level && mxres > min_max;
+      min_max = std::min(min_max, mxres);
       if (mxres < best_max * 0.7) {
         best_max = mxres;
         stall = 0;
       } else {
         ++stall;
       }
-      if (mxres <= o.switch_tol || stall >= 4 || ncand > 0) {
+      if (mxres <= o.switch_tol || stall >= 4 || ncand > 0 || rise) {
         prec = KC_PREC_FP64;
         full_gram = true;
         std::fill(lbest.begin(), lbest.end(), 1e300);

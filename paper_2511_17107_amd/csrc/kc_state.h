@@ -75,6 +75,7 @@ struct kc_op {
   std::vector<double> smax;      // [nk] largest s(p) (scale of the operator's rounding)
   std::vector<int> kflags;       // [nk] KC_KFLAG_* of each k-point
   std::vector<double> eps_host;  // [n_mat][3][3][2]
+  double epsinv_norm = 1.0;      // largest absolute row sum of eps^-1 over the materials present
   kc::DevBuf ids;                // uint32 [N^3]: x-edge | y-edge << 8 | z-edge << 16 | vol << 24
   kc::DevBuf eps64, eps32;       // EpsEntry<double/float> [n_mat]
   kc::DevBuf tw64, tw32;         // twiddles exp(+2 pi i t/N), t < N

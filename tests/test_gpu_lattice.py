@@ -58,14 +58,16 @@ def test_preconditioners_match_oracle(lat):
         assert max_err(t[ik:ik + 1], kspace.transverse_precond_apply(N, k, g, E, r[ik:ik + 1], lattice=L)) < 1e-12
 
 
+@pytest.mark.parametrize("start", ["random", "plane_waves"])
 @pytest.mark.parametrize("lat,N", [("fcc", 8), ("bcc", 8), ("tric", 12)])
-def test_eigenvalues_match_oracle(lat, N):
+def test_eigenvalues_match_oracle(lat, N, start):
     ids, tab, L = _case(lat, N, "crossdof")
     kp = np.array([KPTS[0], KPTS[2]])
     op = kc.Op(N, kc.KC_EPS_CROSSDOF, ids, tab, lattice=L)
     op.set_kpoints(kp)
-    note("lattice solve", lat, N)
-    eig, res, its, st = op.solve(8, tol=1e-8, guard=3, batch_k=2, precond=kc.KC_PRECOND_TRANSVERSE)
+    note("lattice solve", lat, N, start)
+    eig, res, its, st = op.solve(8, tol=1e-8, guard=3, batch_k=2, precond=kc.KC_PRECOND_TRANSVERSE,
+                                 start=start)
     assert st == 0 and res.max() <= 1e-8
     for ik, k in enumerate(kp):
         Op = yee.compensated_operator(N, k, ids, tab, "crossdof", lattice=L)
@@ -106,3 +108,25 @@ def test_fcc_homogeneous_free_photon_spectrum_n64():
     g = yee.gamma_rule(k)
     ref = np.sort(np.concatenate([c * s, c * s, g * s]))[:12]
     assert np.max(np.abs(eig[0] - ref) / ref) <= 1e-6, (eig[0], ref)
+
+
+def test_fcc_homogeneous_plane_wave_start_is_exact():
+    """In a homogeneous isotropic medium the transverse plane waves are eigenvectors of the
+    k-space operator (eq (2.30) with Lemma 2.4 (1)), so the plane-wave start built from the FCC
+    lattice's symbols (eq (2.12)) must hold the 12 lowest eigenvectors already: the solve ends
+    within a few iterations, at the free-photon values."""
+    N, c = 32, 1.0 / 4.0
+    L = W.LATTICES["fcc"]
+    ids = np.ones((4, N ** 3), dtype=np.uint8)
+    tab = W.eps_table([4.0 * np.eye(3)])
+    k = np.array([0.4, 2.3, 0.9])
+    op = kc.Op(N, kc.KC_EPS_CROSSDOF, ids, tab, lattice=L)
+    op.set_kpoints(k[None])
+    note("fcc plane-wave start n32")
+    eig, res, its, st = op.solve(12, tol=1e-8, guard=4, precond=kc.KC_PRECOND_TRANSVERSE, start="plane_waves")
+    assert st == 0 and res.max() <= 1e-8
+    K = kspace.symbols_3d(N, k, 1, L)
+    s = np.sum(np.abs(K) ** 2, axis=0)
+    ref = np.sort(np.concatenate([c * s, c * s, yee.gamma_rule(k) * s]))[:12]
+    assert np.max(np.abs(eig[0] - ref) / ref) <= 1e-10, (eig[0], ref)
+    assert its[0] <= 3, its
