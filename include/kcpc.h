@@ -298,7 +298,9 @@ typedef struct kc_solve_opts {
                       /* (eq (4.3)), checked with an FP64 operator application             */
   int maxit;          /* iteration limit                                                   */
   int prec;           /* KC_PREC_FP64, or KC_PREC_FP32: FP32 operator applications until   */
-                      /* the residuals reach switch_tol, FP64 from there on                */
+                      /* the residuals reach switch_tol, stall (no 30 % progress in 4      */
+                      /* iterations) or first rise within 10x the FP32 rounding floor     */
+                      /* 2^-24 s_max |eps^-1|; FP64 from there on                          */
   double switch_tol;  /* residual level where FP32 applications stop (prec = FP32)         */
   int batch_k;        /* k-points solved together in one set of launches (>= 1)            */
   uint64_t seed;      /* seed of the random initial block                                  */

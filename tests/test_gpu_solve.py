@@ -355,3 +355,33 @@ def test_plane_wave_start_matches_oracle(scheme):
         assert np.max(np.abs(eig[i] - ref) / ref) <= REL, (c["k"], eig[i], ref)
     e2, r2, i2, s2 = op.solve(10, tol=1e-8, batch_k=len(kpts), guard=3, precond=kc.KC_PRECOND_TRANSVERSE)
     note("iterations plane waves", its.tolist(), "random", i2.tolist())
+
+
+def test_fp32_phase_ends_at_first_rise_near_its_floor():
+    """Mixed precision on the gyrotropic woodpile at 64^3 (one k-point, T_E): the FP32 phase ends
+    at the first rise of the largest residual once that residual is within ten times the FP32
+    rounding floor 2^-24 s_max |eps^-1| (s_max the largest |K(p)|^2 from the oracle's symbols of
+    Lemma 2.1, |eps^-1| the largest absolute row sum over the materials present).  So no
+    recorded FP32 iteration lies above the running minimum once that minimum is below the level,
+    the phase gets there, and the FP64 phase still converges."""
+    N = 64
+    wl = W.woodpile_gyrotropic(N=N, nk=60, m=8)
+    k = np.asarray(wl.kpoints[17])
+    op = kc.Op(N, kc.KC_EPS_CROSSDOF, wl.ids, wl.table)
+    op.set_kpoints(k[None])
+    note("fp32 phase exit", N)
+    eig, res, its, st = op.solve(8, tol=TOL, guard=4, prec=kc.KC_PREC_FP32, switch_tol=1e-12,
+                                 precond=kc.KC_PRECOND_TRANSVERSE)
+    assert st == 0 and res.max() <= TOL
+    h, p = op.residual_history(0)
+    smax = np.sum(np.abs(kspace.symbols_3d(N, k)) ** 2, axis=0).max()
+    en = max(np.abs(wl.table[mt]).sum(axis=1).max() for mt in np.unique(wl.ids))
+    level = 10.0 * 2.0 ** -24 * smax * en
+    i = int(np.argmax(p == kc.KC_PREC_FP64))
+    assert i > 0 and np.all(p[:i] == kc.KC_PREC_FP32) and np.all(p[i:] == kc.KC_PREC_FP64), p
+    run = np.minimum.accumulate(h[:i])
+    note("FP32 iterations", i, "lowest", run[-1], "level", level)
+    assert run[-1] <= level, (run[-1], level)
+    for j in range(1, i):
+        if run[j - 1] <= level:
+            assert h[j] <= run[j - 1], (j, h[:i].tolist(), level)
