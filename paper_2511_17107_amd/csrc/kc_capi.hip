@@ -316,7 +316,10 @@ int kc_create(int N, const double* lattice_host, int stencil_m, int eps_scheme, 
     if (present[m])
       for (int i = 0; i < 3; ++i) {
         double r = 0.0;
-        for (int j = 0; j < 3; ++j) r += std::hypot(eps_inv_host[m * 18 + (i * 3 + j) * 2], eps_inv_host[m * 18 + (i * 3 + j) * 2 + 1]);
+        for (int j = 0; j < 3; ++j) {
+          const double* e = eps_inv_host + m * 18 + (i * 3 + j) * 2;
+          r += std::hypot(e[0], e[1]);
+        }
         op->epsinv_norm = std::max(op->epsinv_norm, r);
       }
   // permittivity entries scaled by 1/N^3 (normalisation of the two unnormalised DFTs)
