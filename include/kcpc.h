@@ -203,7 +203,8 @@ size_t kc_block_work_bytes(int nb, size_t n, int nc);
  * row-major, G_b[i][j] = sum_r conj(S_b[r][i]) AS_b[r][j] (resp. S_b[r][j]).  Both are taken
  * to be Hermitian: AS_b must be the image A S_b of S_b under a Hermitian A (as in LOBPCG);
  * the 16 x 16 tiles on and above the diagonal are summed, the others are their conjugates.
- *   S, AS : device complex128, nb blocks of nc columns (1 <= nc <= 64)
+ *   S, AS : device complex128, nb blocks of nc columns (1 <= nc <= 96; above 64 the kernels
+ *           stage 80 or 96 columns, as for the solver's blocks of more than 21 columns)
  *   GA, GB: device complex128 [nb][nc][nc]
  *   work  : device scratch of at least kc_block_work_bytes(nb, n, nc) bytes
  * The partial sums over row chunks are added in a fixed order (results are reproducible).
@@ -229,7 +230,7 @@ int kc_block_gram_noalloc(int nb, size_t n, int nc, const void* S, const void* A
 
 /*
  * One Rayleigh-Ritz update with the next residuals (eq (4.3)), in place.  Per k-point b the
- * block holds 3mb columns S_b = [X W P] and AS_b = [AX AW AP] (1 <= mb <= 21), and
+ * block holds 3mb columns S_b = [X W P] and AS_b = [AX AW AP] (1 <= mb <= 32), and
  * C_b = [C1 | Cp] is 3mb x 2mb (row-major, complex128 [nb][3mb][2mb]):
  *   X <- S_b C1, P <- S_b Cp, AX <- AS_b C1, AP <- AS_b Cp   (W and AW are left as they are)
  *   R_j = AX_j - theta_j X_j          (new X, AX; R device complex128 [nb * mb][n])

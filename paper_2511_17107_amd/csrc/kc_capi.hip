@@ -865,8 +865,8 @@ int kc_precond_learned(kc_op* op, int ik0, int nvec, int vecs_per_k, const void*
 }
 
 size_t kc_block_work_bytes(int nb, size_t n, int nc) {
-  if (nb < 1 || n < 1 || nc < 1 || nc > RR_NMAX) return 0;
-  const size_t upd = (size_t)nb * (RR_NMAX / 3) * update_grid_x(n, nb) * 2 * sizeof(double);
+  if (nb < 1 || n < 1 || nc < 1 || nc > RR_NMAX_WIDE) return 0;
+  const size_t upd = (size_t)nb * (RR_NMAX_WIDE / 3) * update_grid_x(n, nb) * 2 * sizeof(double);
   return std::max(gram2_part_bytes(nc, n, nb), upd);
 }
 
@@ -901,7 +901,7 @@ static bool disjoint(const void* a, size_t na, const void* b, size_t nb) {
 
 int kc_block_gram(int nb, size_t n, int nc, const void* S, const void* AS, void* GA, void* GB, void* work,
                   size_t work_bytes, void* stream) {
-  KC_ARG(nb >= 0 && n >= 1 && nc >= 1 && nc <= RR_NMAX, "nb >= 0, n >= 1, 1 <= nc <= 64");
+  KC_ARG(nb >= 0 && n >= 1 && nc >= 1 && nc <= RR_NMAX_WIDE, "nb >= 0, n >= 1, 1 <= nc <= 96");
   if (nb == 0) return KC_OK;
   KC_ARG(S != nullptr && AS != nullptr && GA != nullptr && GB != nullptr && work != nullptr, "NULL buffer");
   KC_ARG(work_bytes >= gram2_part_bytes(nc, n, nb), "work_bytes below kc_block_work_bytes");
@@ -911,7 +911,7 @@ int kc_block_gram(int nb, size_t n, int nc, const void* S, const void* AS, void*
 
 int kc_block_gram_noalloc(int nb, size_t n, int nc, const void* S, const void* AS, void* GA, void* GB,
                           void* stream) {
-  KC_ARG(nb >= 0 && n >= 1 && nc >= 1 && nc <= RR_NMAX, "nb >= 0, n >= 1, 1 <= nc <= 64");
+  KC_ARG(nb >= 0 && n >= 1 && nc >= 1 && nc <= RR_NMAX_WIDE, "nb >= 0, n >= 1, 1 <= nc <= 96");
   if (nb == 0) return KC_OK;
   KC_ARG(S != nullptr && AS != nullptr && GA != nullptr && GB != nullptr, "NULL buffer");
   const size_t T = (size_t)(nc + 15) / 16;
@@ -927,7 +927,7 @@ int kc_block_gram_noalloc(int nb, size_t n, int nc, const void* S, const void* A
 
 int kc_block_update(int nb, size_t n, int mb, void* S, void* AS, const void* C, const double* theta, void* R,
                     double* res, double* xnorm2, void* work, size_t work_bytes, void* stream) {
-  KC_ARG(nb >= 0 && n >= 1 && mb >= 1 && 3 * mb <= RR_NMAX, "nb >= 0, n >= 1, 1 <= mb <= 21");
+  KC_ARG(nb >= 0 && n >= 1 && mb >= 1 && 3 * mb <= RR_NMAX_WIDE, "nb >= 0, n >= 1, 1 <= mb <= 32");
   if (nb == 0) return KC_OK;
   KC_ARG(S != nullptr && AS != nullptr && C != nullptr && theta != nullptr && R != nullptr && res != nullptr &&
              xnorm2 != nullptr && work != nullptr,

@@ -123,7 +123,8 @@ def test_block_calls_check_arguments():
     """kc_block_work_bytes is 0 out of range; kc_block_gram / kc_block_update reject bad sizes,
     NULL buffers, overlapping blocks and a short workspace before any device work."""
     L = kc.lib()
-    assert L.kc_block_work_bytes(0, 100, 60) == 0 and L.kc_block_work_bytes(2, 100, 65) == 0
+    assert L.kc_block_work_bytes(0, 100, 60) == 0 and L.kc_block_work_bytes(2, 100, 97) == 0
+    assert L.kc_block_work_bytes(2, 100, 96) > 0
     need = L.kc_block_work_bytes(2, 1000, 60)
     assert need > 0
     fake = ctypes.c_void_p(1 << 40)  # never dereferenced: every call below fails its checks first
@@ -131,10 +132,10 @@ def test_block_calls_check_arguments():
     # nb = 0 is a no-op
     assert L.kc_block_gram(0, 1000, 60, None, None, None, None, None, 0, None) == 0
     assert L.kc_block_update(0, 1000, 20, None, None, None, None, None, None, None, None, 0, None) == 0
-    bad = [L.kc_block_gram(2, 1000, 65, fake, other, fake, fake, fake, need, None),
+    bad = [L.kc_block_gram(2, 1000, 97, fake, other, fake, fake, fake, need, None),
            L.kc_block_gram(2, 1000, 60, None, other, fake, fake, fake, need, None),
            L.kc_block_gram(2, 1000, 60, fake, other, fake, fake, fake, need - 1, None),
-           L.kc_block_update(2, 1000, 22, fake, other, fake, fake, fake, fake, fake, fake, need, None),
+           L.kc_block_update(2, 1000, 33, fake, other, fake, fake, fake, fake, fake, fake, need, None),
            L.kc_block_update(2, 1000, 0, fake, other, fake, fake, fake, fake, fake, fake, need, None),
            L.kc_block_update(2, 1000, 20, fake, fake, fake, fake, other, fake, fake, fake, need, None),
            L.kc_block_update(2, 1000, 20, fake, other, fake, fake, None, fake, fake, fake, need, None),

@@ -1,6 +1,6 @@
 """The LOBPCG block kernels through the C ABI (kc_block_gram, kc_block_update) against the
 oracle's definitions (oracle/block.py), element by element: small blocks with ragged row
-counts and every block width class, and the full 128^3 shape of the benchmark (10 k-points,
+counts and every block width class (the wide blocks of 65-96 columns included), and the full 128^3 shape of the benchmark (10 k-points,
 16 bands + 4 guard) on sampled rows."""
 import numpy as np
 import pytest
@@ -18,7 +18,8 @@ def _colscale(S):
     return np.linalg.norm(S, axis=2)  # (nb, nc)
 
 
-@pytest.mark.parametrize("nb,nc,n", [(3, 60, 3 * 16 ** 3), (2, 13, 1007), (1, 64, 333), (4, 6, 16), (2, 63, 5)])
+@pytest.mark.parametrize("nb,nc,n", [(3, 60, 3 * 16 ** 3), (2, 13, 1007), (1, 64, 333), (4, 6, 16), (2, 63, 5),
+                                     (2, 72, 1007), (1, 80, 333), (2, 96, 3 * 8 ** 3 + 3)])
 def test_block_gram_matches_oracle(nb, nc, n):
     """AS = D S with a real diagonal D (a Hermitian operator, as the kernel requires)."""
     S = W.random_complex(11, (nb, nc, n))
@@ -35,7 +36,8 @@ def test_block_gram_matches_oracle(nb, nc, n):
 
 
 @pytest.mark.parametrize("nb,mb,n", [(3, 20, 3 * 16 ** 3), (2, 21, 1007), (2, 5, 1007), (1, 4, 48), (3, 1, 100),
-                                     (2, 8, 3 * 8 ** 3 + 3), (1, 13, 17)])
+                                     (2, 8, 3 * 8 ** 3 + 3), (1, 13, 17), (2, 22, 1007), (1, 24, 333),
+                                     (2, 27, 3 * 8 ** 3 + 3), (1, 32, 17)])
 def test_block_update_matches_oracle(nb, mb, n):
     """mb a multiple of 4 takes the uniform-offset path, the others the per-lane clamp; n not a
     multiple of 16 leaves a ragged last row block."""
