@@ -320,7 +320,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; --gpus %d is not "
-              "supported (k-points shard across GPUs with no communication; see DESIGN.md)" % a.gpus,
+              "supported (k-points would shard across GPUs with no communication)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
