@@ -319,7 +319,7 @@ def sphere64_run(a, dev):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X; --gpus %d is not "
+        print("bench.py measures one GPU, a single MI355X; --gpus %d is not "
               "supported (k-points would shard across GPUs with no communication)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
